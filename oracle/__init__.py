@@ -1,0 +1,133 @@
+"""FP64 CPU oracle for the intensity-driven gradient filter.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The GPU library
+never imports, links or calls it, and it shares no code with the GPU library:
+the only module both sides use is the seeded input generator ``igsynth``.
+
+Contents
+  * ``run`` / ``rms`` / ``round_bf16`` / ``round_f16``: ctypes front end to
+    ``oracle.c`` (plain C, FP64, OpenMP over z-planes), the definition of the
+    filter written out (Section 3.3, Eqs. 5-7).
+  * ``brute``: an independent NumPy pad-and-shift form of the same step, for
+    tiny cubes.
+  * ``surrogate``: FP64 NumPy forms of the learned surrogate's layers.
+
+Pins (tests/test_oracle_pins.py): constant cube is a fixed point, zero
+conductance is the identity, flux conservation of the per-edge forms under
+reflecting faces, a weighted conservation identity of the intensity form,
+closed-form impulse responses, the linear limit diagonalised by the
+orthonormal DCT-II, the maximum principle, symmetries, composition, the
+brute-force cross-check, and the storage rounding against IEEE casts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+COND = {"intensity": 0, "pm_exp": 1, "pm_rational": 2}
+ROUND = {None: 0, "f32": 0, "bf16": 1, "f16": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no fast-math, no FMA)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+                               "-shared", "-fPIC", src, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+        p = ctypes.c_void_p
+        lib.oracle_run.argtypes = [p, p, i64, i64, i64, i32, d, d, i32, d, d, d, d, i32,
+                                   ctypes.POINTER(d)]
+        lib.oracle_run.restype = i32
+        lib.oracle_rms.argtypes = [p, i64, ctypes.POINTER(d), ctypes.POINTER(i64)]
+        lib.oracle_rms.restype = d
+        lib.oracle_round_bf16.argtypes = [d]
+        lib.oracle_round_bf16.restype = d
+        lib.oracle_round_f16.argtypes = [d]
+        lib.oracle_round_f16.restype = d
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def run(cube, cond: str = "pm_exp", K: float = 2.0, tau: float = 1.0 / 16, n_iter: int = 1,
+        C=(1.0, 1.0, 1.0), rms: float | None = None, round_to: str | None = None):
+    """Filter `cube` (nz, ny, nx) in FP64.  Returns (result FP64 array, rho used)."""
+    lib = _load()
+    a = np.ascontiguousarray(cube, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("cube must be 3-D (nz, ny, nx)")
+    out = np.empty_like(a)
+    nz, ny, nx = a.shape
+    used = ctypes.c_double(0.0)
+    rc = lib.oracle_run(a.ctypes.data, out.ctypes.data, nx, ny, nz, COND[cond], float(K),
+                        float(tau), int(n_iter), float(C[0]), float(C[1]), float(C[2]),
+                        float(rms) if rms is not None else 0.0, ROUND[round_to], ctypes.byref(used))
+    if rc != 0:
+        raise OracleError({-1: "invalid argument", -2: "out of memory",
+                           -3: "non-finite input"}.get(rc, str(rc)))
+    return out, used.value
+
+
+def rms(cube):
+    """(rho, sum, nonfinite count) with rho = sqrt(sum I^2 / N) in FP64."""
+    lib = _load()
+    a = np.ascontiguousarray(cube, dtype=np.float64).ravel()
+    s = ctypes.c_double(0.0)
+    bad = ctypes.c_int64(0)
+    r = lib.oracle_rms(a.ctypes.data, a.size, ctypes.byref(s), ctypes.byref(bad))
+    return r, s.value, bad.value
+
+
+def round_bf16(x):
+    lib = _load()
+    return np.vectorize(lib.oracle_round_bf16, otypes=[np.float64])(np.asarray(x, np.float64))
+
+
+def round_f16(x):
+    lib = _load()
+    return np.vectorize(lib.oracle_round_f16, otypes=[np.float64])(np.asarray(x, np.float64))
+
+
+def run_points(cube, points, cond="pm_exp", K=2.0, tau=1.0 / 16, n_iter=1, C=(1.0, 1.0, 1.0),
+               rms: float = 1.0, round_to=None):
+    """Oracle values at selected voxels of a large cube, each from its own sub-box.
+
+    After n steps a voxel depends only on voxels within n steps along each
+    axis, so running the same oracle on the sub-box of half-width n around the
+    voxel (clipped to the cube, whose real faces keep their boundary) gives
+    that voxel's exact value.  `rms` must be given (the whole cube's value).
+    `points` is an iterable of (z, y, x).  Returns FP64 values.
+    """
+    a = np.asarray(cube)
+    nz, ny, nx = a.shape
+    vals = []
+    for (z, y, x) in points:
+        lo = [max(0, c - n_iter) for c in (z, y, x)]
+        hi = [min(e, c + n_iter + 1) for c, e in zip((z, y, x), (nz, ny, nx))]
+        sub = a[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        res, _ = run(sub, cond, K, tau, n_iter, C, rms=rms, round_to=round_to)
+        vals.append(res[z - lo[0], y - lo[1], x - lo[2]])
+    return np.array(vals)

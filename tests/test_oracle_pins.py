@@ -1,0 +1,309 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test states which part of the oracle a plausible mistake would break:
+a dropped or wrong-signed term, a transposed axis, a wrong boundary ghost, a
+wrong noise estimate, an in-place (Gauss-Seidel) update, or wrong rounding.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import igsynth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CONDS = ["intensity", "pm_exp", "pm_rational"]
+
+
+def _defaults():
+    vals = {}
+    with open(os.path.join(HERE, "golden", "paper_defaults.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, *v = line.split()
+                vals[k] = [float(x) for x in v]
+    return vals
+
+
+def test_paper_defaults_fixture():
+    d = _defaults()
+    assert d["K_default"] == [1.5] and d["tau_default"] == [0.0325]
+    assert d["n_default"] == [20] and d["C_default"] == [5, 5, 5]
+
+
+# --- I1: constant cube is a fixed point (all differences vanish) -------------
+@pytest.mark.parametrize("cond", CONDS)
+def test_constant_cube_fixed_point(oracle_lib, cond):
+    c = np.full((5, 6, 7), 3.25)
+    out, rho = oracle_lib.run(c, cond, K=1.7, tau=0.05, n_iter=7, C=(1, 2, 3))
+    assert rho == pytest.approx(3.25)
+    assert np.array_equal(out, c)
+
+
+def test_zero_cube_fixed_point(oracle_lib):
+    c = np.zeros((3, 4, 5))
+    for cond in CONDS:
+        out, rho = oracle_lib.run(c, cond, n_iter=3)
+        assert rho == 0.0 and np.array_equal(out, c)
+
+
+# --- I2: zero conductance / zero step / zero iterations is the identity -------
+@pytest.mark.parametrize("cond", CONDS)
+def test_zero_conductance_identity(oracle_lib, cond):
+    c = igsynth.random_cube((6, 5, 4), seed=3).astype(np.float64)
+    for kw in (dict(C=(0, 0, 0), n_iter=4), dict(tau=0.0, n_iter=4), dict(n_iter=0)):
+        out, _ = oracle_lib.run(c, cond, **kw)
+        assert np.array_equal(out, c), kw
+
+
+# --- I3: per-edge forms conserve the sum under reflecting faces ---------------
+@pytest.mark.parametrize("cond", ["pm_exp", "pm_rational"])
+def test_flux_conservation(oracle_lib, cond):
+    c = igsynth.cube_small(seed=5).astype(np.float64)
+    out, _ = oracle_lib.run(c, cond, K=2.0, tau=1 / 16, n_iter=20, C=(1.0, 0.7, 1.3))
+    s0, s1 = c.sum(), out.sum()
+    assert abs(s1 - s0) <= 1e-12 * np.abs(c).sum()
+    assert np.abs(out - c).max() > 0.1   # and the cube did change
+
+
+# --- I4: the intensity form conserves the S-weighted change in one step -------
+def test_intensity_weighted_identity(oracle_lib):
+    c = igsynth.cube_small(seed=6).astype(np.float64)
+    K, tau = 1.5, 0.0325
+    out, rho = oracle_lib.run(c, "intensity", K=K, tau=tau, n_iter=1, C=(5, 5, 5))
+    w = 1.0 + c * c / (K * rho) ** 2
+    lhs = ((out - c) * w).sum()
+    assert abs(lhs) <= 1e-12 * (np.abs(out - c) * w).sum()
+    # while the plain sum is not conserved (the paper's remark that the flux
+    # scale is not kept)
+    assert abs(out.sum() - c.sum()) > 1e-3
+
+
+# --- I5: impulse closed forms -------------------------------------------------
+def _impulse(shape, pos, h):
+    c = np.zeros(shape)
+    c[pos] = h
+    return c
+
+
+@pytest.mark.parametrize("cond", CONDS)
+def test_impulse_interior(oracle_lib, cond):
+    h, K, tau, C = 3.0, 2.0, 1 / 16, (0.5, 1.0, 2.0)   # distinct C pins the axis mapping
+    c = _impulse((4, 4, 4), (1, 2, 1), h)
+    out, _ = oracle_lib.run(c, cond, K=K, tau=tau, n_iter=1, C=C, rms=1.0)
+    if cond == "pm_exp":
+        g = math.exp(-(h / K) ** 2)
+        centre = h * (1 - 2 * tau * sum(C) * g)
+        nb = [tau * Ca * g * h for Ca in C]
+    elif cond == "pm_rational":
+        g = 1.0 / (1 + (h / K) ** 2)
+        centre = h * (1 - 2 * tau * sum(C) * g)
+        nb = [tau * Ca * g * h for Ca in C]
+    else:
+        S = 1.0 / (1 + h * h / K ** 2)
+        centre = h * (1 - 2 * tau * sum(C) * S)
+        nb = [tau * Ca * h for Ca in C]      # S(0) = 1 at the neighbours
+    exp = np.zeros_like(c)
+    z, y, x = 1, 2, 1
+    exp[z, y, x] = centre
+    exp[z, y, x - 1] = exp[z, y, x + 1] = nb[0]
+    exp[z, y - 1, x] = exp[z, y + 1, x] = nb[1]
+    exp[z - 1, y, x] = exp[z + 1, y, x] = nb[2]
+    np.testing.assert_allclose(out, exp, rtol=0, atol=1e-15)
+
+
+def test_impulse_known_values(oracle_lib):
+    # h = 3, K = 2, tau = 1/16, C = 1 (exponential weight): centre h(1 - 6 tau g),
+    # neighbour tau g h with g = exp(-(h/K)^2).
+    out, _ = oracle_lib.run(_impulse((4, 4, 4), (1, 1, 1), 3.0), "pm_exp", K=2.0, tau=1 / 16,
+                            n_iter=1, rms=1.0)
+    assert out[1, 1, 1] == pytest.approx(2.8814258723679025, abs=1e-15)
+    assert out[1, 1, 2] == pytest.approx(0.01976235460534956, abs=1e-16)
+
+
+@pytest.mark.parametrize("cond", CONDS)
+def test_impulse_corner(oracle_lib, cond):
+    h, K, tau = 2.5, 1.5, 0.05
+    c = _impulse((4, 4, 4), (0, 0, 0), h)
+    out, _ = oracle_lib.run(c, cond, K=K, tau=tau, n_iter=1, C=(1, 1, 1), rms=1.0)
+    w = {"pm_exp": math.exp(-(h / K) ** 2), "pm_rational": 1 / (1 + (h / K) ** 2),
+         "intensity": 1 / (1 + h * h / K ** 2)}[cond]
+    assert out[0, 0, 0] == pytest.approx(h * (1 - 3 * tau * w), abs=1e-15)   # 3 neighbours only
+    nbw = 1.0 if cond == "intensity" else w
+    for idx in [(0, 0, 1), (0, 1, 0), (1, 0, 0)]:
+        assert out[idx] == pytest.approx(tau * nbw * h, abs=1e-15)
+    rest = out.copy()
+    for idx in [(0, 0, 0), (0, 0, 1), (0, 1, 0), (1, 0, 0)]:
+        rest[idx] = 0.0
+    assert not rest.any()
+
+
+# --- I6: brute-force cross-check on random tiny cubes -------------------------
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 6), (1, 5, 1), (4, 1, 1), (4, 4, 4),
+                                   (3, 5, 7), (8, 3, 2)])
+@pytest.mark.parametrize("cond", CONDS)
+def test_bruteforce_crosscheck(oracle_lib, shape, cond):
+    from oracle import brute
+    rng = np.random.default_rng(hash((shape, cond)) % 2**32)
+    c = rng.standard_normal(shape) * rng.uniform(0.5, 4) + rng.uniform(-1, 1)
+    K, tau = rng.uniform(0.5, 3), rng.uniform(0.0025, 0.0625)
+    C = tuple(rng.uniform(0, 3, 3))
+    for n_iter in (1, 3):
+        a, ra = oracle_lib.run(c, cond, K=K, tau=tau, n_iter=n_iter, C=C)
+        b, rb = brute.run(c, cond, K=K, tau=tau, n_iter=n_iter, C=C)
+        assert ra == pytest.approx(rb, rel=1e-14)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * np.abs(c).max())
+
+
+# --- I7: linear limit, diagonalised by the orthonormal DCT-II -----------------
+@pytest.mark.parametrize("cond", CONDS)
+def test_linear_limit_dct(oracle_lib, cond):
+    # K -> infinity: every weight is 1 and the step is I + tau sum_a C_a D_a I,
+    # with D_a the second difference whose face ghost is the edge voxel itself.
+    # That operator is diagonal in the DCT-II basis with eigenvalue
+    # -4 sin^2(pi k / (2 n)) per axis.
+    shape = (6, 9, 11)
+    c = igsynth.random_cube(shape, seed=11).astype(np.float64)
+    tau, C, n = 0.03, (1.5, 0.75, 2.5), 9     # C is (Cx, Cy, Cz)
+    out, _ = oracle_lib.run(c, cond, K=1e30, tau=tau, n_iter=n, C=C, rms=1.0)
+    lam = np.zeros(shape)
+    for axis, Ca in zip((2, 1, 0), C):        # array axis 2 is x
+        k = np.arange(shape[axis])
+        e = -4.0 * np.sin(np.pi * k / (2 * shape[axis])) ** 2
+        sh = [1, 1, 1]
+        sh[axis] = shape[axis]
+        lam = lam + Ca * e.reshape(sh)
+    spec = scipy.fft.dctn(c, type=2, norm="ortho")
+    ref = scipy.fft.idctn(spec * (1 + tau * lam) ** n, type=2, norm="ortho")
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12)
+
+
+# --- I8: maximum principle when 2 tau (Cx + Cy + Cz) <= 1 ----------------------
+@pytest.mark.parametrize("cond", CONDS)
+def test_maximum_principle(oracle_lib, cond):
+    c = igsynth.cube_small(seed=8).astype(np.float64)
+    out, _ = oracle_lib.run(c, cond, K=1.0, tau=1 / 6, n_iter=15, C=(1, 1, 1))
+    assert out.max() <= c.max() and out.min() >= c.min()
+
+
+def test_stability_bound_violated_oscillates(oracle_lib):
+    # tau = 0.0625 with C = 5 breaks the bound (2 * 0.0625 * 15 = 1.875): the
+    # linear part amplifies the checkerboard mode ("web structures").
+    c = igsynth.random_cube((8, 8, 8), seed=9).astype(np.float64) * 0.05
+    out, _ = oracle_lib.run(c, "intensity", K=10.0, tau=0.0625, n_iter=20, C=(5, 5, 5), rms=1.0)
+    assert np.abs(out).max() > 10 * np.abs(c).max()
+
+
+# --- I9: symmetries -----------------------------------------------------------
+@pytest.mark.parametrize("cond", CONDS)
+def test_symmetries(oracle_lib, cond):
+    c = igsynth.cube_small(seed=10).astype(np.float64)[:, :40, :40]
+    kw = dict(K=1.8, tau=0.05, n_iter=6, C=(1.2, 1.2, 0.6))
+    f, r = oracle_lib.run(c, cond, **kw)
+    fn, _ = oracle_lib.run(-c, cond, **kw)
+    assert np.array_equal(fn, -f)
+    f2, r2 = oracle_lib.run(2 * c, cond, **kw)
+    assert r2 == 2 * r and np.array_equal(f2, 2 * f)
+    fx, _ = oracle_lib.run(c[:, :, ::-1], cond, **kw)
+    np.testing.assert_allclose(fx[:, :, ::-1], f, rtol=0, atol=1e-13)
+    ft, _ = oracle_lib.run(np.ascontiguousarray(c.transpose(0, 2, 1)), cond, **kw)
+    np.testing.assert_allclose(ft.transpose(0, 2, 1), f, rtol=0, atol=1e-13)
+
+
+# --- I10: composition (Jacobi steps in sequence) -------------------------------
+@pytest.mark.parametrize("cond", CONDS)
+def test_composition(oracle_lib, cond):
+    c = igsynth.random_cube((7, 9, 10), seed=12).astype(np.float64)
+    kw = dict(K=1.3, tau=0.04, C=(1, 2, 1), rms=1.1)
+    a, _ = oracle_lib.run(c, cond, n_iter=5, **kw)
+    b, _ = oracle_lib.run(c, cond, n_iter=2, **kw)
+    b, _ = oracle_lib.run(b, cond, n_iter=3, **kw)
+    assert np.array_equal(a, b)
+
+
+def test_jacobi_not_gauss_seidel(oracle_lib):
+    # A 1-D pair [h, 0] along x: a synchronous step gives
+    # [h - tau C g h, tau C g h]; an in-place sweep would give another second value.
+    h, K, tau = 2.0, 1.0, 0.1
+    c = np.array([[[h, 0.0]]])
+    out, _ = oracle_lib.run(c, "pm_exp", K=K, tau=tau, n_iter=1, C=(1, 1, 1), rms=1.0)
+    g = math.exp(-(h / K) ** 2)
+    assert out[0, 0, 0] == pytest.approx(h - tau * g * h, abs=1e-16)
+    assert out[0, 0, 1] == pytest.approx(tau * g * h, abs=1e-16)
+
+
+# --- noise level --------------------------------------------------------------
+def test_rms_estimate(oracle_lib):
+    c = igsynth.cube_small(seed=13)
+    r, s, bad = oracle_lib.rms(c)
+    x = c.astype(np.float64)
+    assert r == pytest.approx(math.sqrt(np.mean(x * x)), rel=1e-14)
+    assert s == pytest.approx(x.sum(), rel=1e-12) and bad == 0
+    _, used = oracle_lib.run(c, "pm_exp", n_iter=0)
+    assert used == pytest.approx(r, rel=1e-15)
+    # and the estimate enters the weight: rho from the cube == rho given
+    a, _ = oracle_lib.run(c, "pm_exp", n_iter=2)
+    b, _ = oracle_lib.run(c, "pm_exp", n_iter=2, rms=r)
+    assert np.array_equal(a, b)
+    c2 = c.astype(np.float64).copy()
+    c2[1, 2, 3] = np.nan
+    assert oracle_lib.rms(c2)[2] == 1
+    with pytest.raises(oracle_lib.OracleError):
+        oracle_lib.run(c2, "pm_exp", n_iter=1)
+
+
+# --- storage rounding ---------------------------------------------------------
+def test_round_f16_matches_ieee_cast(oracle_lib):
+    rng = np.random.default_rng(14)
+    x = np.concatenate([rng.standard_normal(4000) * 10, rng.standard_normal(1000) * 1e-5,
+                        np.array([0.0, -0.0, 65504.0, 6.1e-5, 5.96e-8, 2.0 ** -25, 3 * 2.0 ** -25])])
+    # exact ties between binary16 neighbours
+    ties = (np.arange(1024, 2048, dtype=np.float64) + 0.5) * 2.0 ** -10
+    x = np.concatenate([x, ties, -ties])
+    np.testing.assert_array_equal(oracle_lib.round_f16(x), x.astype(np.float16).astype(np.float64))
+
+
+def test_round_bf16_matches_torch_cast(oracle_lib):
+    import torch
+    rng = np.random.default_rng(15)
+    x = (rng.standard_normal(5000) * 10).astype(np.float32).astype(np.float64)
+    ties = ((np.arange(128, 256, dtype=np.float64) + 0.5) * 2.0 ** -7).astype(np.float32)
+    x = np.concatenate([x, ties.astype(np.float64), -ties.astype(np.float64), [0.0, 1e-30]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(oracle_lib.round_bf16(x), ref)
+
+
+def test_rounded_run_stays_on_grid(oracle_lib):
+    c = igsynth.cube_small(seed=16).astype(np.float64)[:8]
+    for mode, fn in (("bf16", oracle_lib.round_bf16), ("f16", oracle_lib.round_f16)):
+        q = fn(c)
+        out, _ = oracle_lib.run(q, "pm_exp", n_iter=3, round_to=mode)
+        assert np.array_equal(fn(out), out)
+        ref, _ = oracle_lib.run(q, "pm_exp", n_iter=3)
+        assert np.abs(out - ref).max() < 0.05
+
+
+# --- sampled values on large cubes --------------------------------------------
+def test_run_points_matches_full_run(oracle_lib):
+    c = igsynth.random_cube((20, 23, 26), seed=17).astype(np.float64)
+    n = 4
+    full, rho = oracle_lib.run(c, "pm_exp", n_iter=n, rms=1.2)
+    pts = [(0, 0, 0), (19, 22, 25), (10, 11, 12), (0, 11, 25), (5, 0, 3), (19, 4, 0)]
+    vals = oracle_lib.run_points(c, pts, "pm_exp", n_iter=n, rms=1.2)
+    assert np.array_equal(vals, np.array([full[p] for p in pts]))
+
+
+# --- I11: behaviour the paper describes ----------------------------------------
+def test_bright_structure_changes_less(oracle_lib):
+    c, model = igsynth.cube_small(seed=1, with_model=True)
+    out, _ = oracle_lib.run(c, "intensity", K=1.5, tau=0.0325, n_iter=20, C=(5, 5, 5))
+    c = c.astype(np.float64)
+    rel = np.abs(out - c) / np.abs(c)
+    bright = c > 6.0                              # galaxy core, S/N > 6
+    spikes = (np.abs(c) > 2.0) & (np.abs(c) < 3.0) & (model < 0.1)   # pure-noise 2-3 rms
+    assert bright.sum() > 10 and spikes.sum() > 100
+    # adaptive smoothing: the bright core keeps most of its value while noise
+    # spikes of a few rms are flattened
+    assert np.median(rel[bright]) < 0.3 < 0.8 < np.median(rel[spikes])
