@@ -1,0 +1,194 @@
+/*
+ * igfilter.h - C ABI of the MI355X (gfx950) intensity-driven gradient filter.
+ *
+ * The filter (Punzo, van der Hulst & Roerdink, "Finding faint H I structure
+ * in and around galaxies: scraping the barrel", Section 3.3, Eqs. 5-7) runs
+ * n explicit, synchronous (Jacobi) steps of anisotropic diffusion on a 3-D
+ * data cube:
+ *
+ *   I_{i+1}(v) = I_i(v) + tau * sum_{a in x,y,z} C_a * sum_{s=+-1} w(v,u) (I_i(u) - I_i(v)),
+ *
+ * with u = v + s e_a and the weight w chosen by ig_conductance.  A neighbour
+ * outside the cube takes the voxel's own value (no flux through the faces).
+ * rho, the cube's noise level, scales K: it is the caller's value, or the
+ * root mean square of the input over all voxels, computed once (FP64).
+ *
+ * Conventions shared by every entry point
+ *   - Layout: a cube is nz planes of ny rows of nx voxels, x fastest
+ *     (right ascension, declination, velocity channel: Section 2 of the
+ *     paper), index x + nx * (y + ny * z), densely packed.
+ *   - Pointers named d_* are device pointers on the handle's device (e.g.
+ *     torch tensors' data_ptr()).  The caller owns them; the library never
+ *     frees them.  Handles own their scratch memory.
+ *   - hip_stream is a hipStream_t cast to void*; NULL means the null stream.
+ *     Work is enqueued on that stream and the call returns without waiting,
+ *     unless an output argument that lives on the host (stats, latency) is
+ *     requested: then the call waits for the stream.
+ *   - Errors: every entry point returns an ig_status; no exception crosses
+ *     the ABI.  Arguments are validated before any device work is enqueued.
+ *     ig_last_error() gives a thread-local message for the last failure.
+ *   - Threads: a handle is not re-entrant; distinct handles may be used from
+ *     distinct threads.
+ */
+#ifndef IGFILTER_H
+#define IGFILTER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IG_OK = 0,
+    IG_ERR_INVALID_ARG = 1,    /* bad size, parameter, enum, pointer or overlap */
+    IG_ERR_OUT_OF_MEMORY = 2,  /* device allocation failed */
+    IG_ERR_DEVICE = 3,         /* a HIP call failed */
+    IG_ERR_NONFINITE = 4,      /* the input holds NaN or Inf; output untouched */
+    IG_ERR_UNSUPPORTED = 5     /* valid request this build cannot serve */
+} ig_status;
+
+/* Storage type of the cube in device memory.  Arithmetic is FP32 for every
+ * storage type; 16-bit storage rounds (to nearest, ties to even) after every
+ * step, including steps kept on chip. */
+typedef enum { IG_F32 = 0, IG_BF16 = 1, IG_F16 = 2 } ig_dtype;
+
+/* The weight w of the update (Section 3.3):
+ *   IG_COND_INTENSITY   : w = 1 / (1 + I_i(v)^2 / (K rho)^2), the paper's
+ *                         intensity-driven conductance (Eq. 6), evaluated at
+ *                         the centre voxel, i.e. the discretised filter of Eq. 7.
+ *   IG_COND_PM_EXP      : w = exp(-((I_i(u) - I_i(v)) / (K rho))^2) per edge,
+ *                         the exponential Perona-Malik edge-stopping function.
+ *   IG_COND_PM_RATIONAL : w = 1 / (1 + ((I_i(u) - I_i(v)) / (K rho))^2) per
+ *                         edge, Eq. 5 with K in rms units. */
+typedef enum { IG_COND_INTENSITY = 0, IG_COND_PM_EXP = 1, IG_COND_PM_RATIONAL = 2 } ig_conductance;
+
+/* Filter parameters (Section 3.3: K, tau, n, C_x, C_y, C_z and rms).
+ * The paper's slider ranges (tau in [0.0025, 0.0625], C in [0, 10],
+ * K in [0.5, 10]) are not enforced; only mathematical validity is. */
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(ig_params); guards against ABI skew */
+    int32_t dtype;          /* ig_dtype */
+    int32_t cond;           /* ig_conductance */
+    int32_t n_iter;         /* number of steps n >= 0 */
+    int64_t nx, ny, nz;     /* >= 1 each; nx*ny*nz < 2^31 */
+    float K;                /* > 0 and finite, in units of rho */
+    float tau;              /* >= 0 and finite */
+    float C[3];             /* C_x, C_y, C_z >= 0 and finite */
+    float reserved0;        /* must be 0 */
+    double rms;             /* > 0 (finite): use as rho; <= 0: estimate from the input */
+} ig_params;
+
+/* How the steps are scheduled on the GPU.  The result is bitwise the same
+ * for every schedule: each voxel's arithmetic does not depend on it. */
+typedef enum {
+    IG_SCHED_AUTO = 0,      /* library choice (tuned table, else heuristic) */
+    IG_SCHED_NAIVE = 1,     /* one step per launch, one voxel per thread */
+    IG_SCHED_BLOCKED = 2    /* t_block steps per launch, z-streaming tiles */
+} ig_sched_kind;
+
+typedef struct {
+    int32_t kind;      /* ig_sched_kind */
+    int32_t t_block;   /* steps per pass, 1..4 (BLOCKED) */
+    int32_t rows;      /* rows of a tile per wavefront: 1, 2 or 4 (BLOCKED) */
+    int32_t waves;     /* wavefronts per workgroup, 1..16 (BLOCKED) */
+    int32_t zchunk;    /* output planes per workgroup, >= 1 (BLOCKED) */
+    int32_t vec;       /* x voxels per lane: 1, 2, 4 or 8; 0 = smallest covering nx */
+} ig_schedule;
+
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(ig_stats), set by the caller */
+    int32_t passes;         /* kernel launches of the step loop */
+    double rms_used;        /* rho */
+    double sum_in;          /* sum of the input voxels (FP64) */
+    double sum_out;         /* sum of the output voxels (FP64) */
+    int64_t nonfinite;      /* NaN / Inf voxels found in the input */
+    int32_t monotone;       /* 1 if 2 tau (C_x + C_y + C_z) <= 1 (maximum principle) */
+    int32_t reserved;
+    ig_schedule schedule;   /* schedule used */
+} ig_stats;
+
+typedef struct ig_filter ig_filter;
+
+/* Create a handle for cubes of the given parameters on `device`.  Allocates
+ * one scratch cube (ping-pong partner) and small reduction buffers.
+ * On error *out is set to NULL. */
+ig_status ig_filter_create(const ig_params* p, int device, ig_filter** out);
+
+/* Filter d_in into d_out (both nx*ny*nz elements of p->dtype).  d_in == d_out
+ * is allowed (2 cubes of device memory in total, the paper's two-buffer GPU
+ * model of Section 5); any other overlap is IG_ERR_INVALID_ARG.  d_in is not
+ * modified unless it equals d_out.  If stats != NULL the call waits for the
+ * stream and fills it.  A non-finite input voxel leaves d_out untouched; it is
+ * reported as IG_ERR_NONFINITE when stats != NULL (the scan runs whenever the
+ * rms is estimated or stats are requested). */
+ig_status ig_filter_run(ig_filter* f, const void* d_in, void* d_out, void* hip_stream,
+                        ig_stats* stats);
+
+/* Override the schedule (NULL restores IG_SCHED_AUTO).  Rejects shapes the
+ * schedule cannot serve with IG_ERR_INVALID_ARG. */
+ig_status ig_filter_set_schedule(ig_filter* f, const ig_schedule* s);
+ig_status ig_filter_get_schedule(const ig_filter* f, ig_schedule* s);
+
+/* Host-only check (no device work, no handle): IG_OK if schedule s can serve
+ * cubes described by p, else IG_ERR_INVALID_ARG with the reason in
+ * ig_last_error(). */
+ig_status ig_schedule_check(const ig_params* p, const ig_schedule* s);
+
+/* Release the handle and its device memory (NULL is a no-op). */
+void ig_filter_destroy(ig_filter* f);
+
+/* One cube of a batch: its own parameters and caller-owned buffers.
+ * d_in == d_out is allowed; items must not share buffers otherwise. */
+typedef struct {
+    ig_params p;
+    const void* d_in;
+    void* d_out;
+} ig_batch_item;
+
+/* Filter `count` independent cubes of uneven sizes and parameters in one
+ * persistent launch (all items: FP32 storage, same device).  The launch,
+ * together with the upload of its work descriptors, is captured once per
+ * batch signature into a HIP graph and replayed on later calls with the same
+ * signature (item shapes, parameters and buffer addresses).  Scratch cubes
+ * for the ping-pong are owned by that cached plan (ig_batch_cache_clear frees
+ * them).  per_item (nullable, `count` entries) receives each item's stats;
+ * latency_ms (nullable, `count` entries) receives each cube's completion time
+ * measured on the GPU clock from the start of the launch.  Either makes the
+ * call wait for the stream. */
+ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
+                          ig_stats* per_item, double* latency_ms);
+
+/* Free every cached batch plan (graphs and scratch) on every device. */
+void ig_batch_cache_clear(void);
+
+/* Comparison of a device cube with an FP64 device reference (both n
+ * elements): maximum |x - ref|, root mean square of x - ref, count of
+ * |x - ref| > tol, maximum |ref|, sum of x and of ref; FP64 accumulation in
+ * a fixed order.  Waits for the stream. */
+typedef struct {
+    double max_abs;
+    double rms;
+    double max_ref;
+    double sum_x;
+    double sum_ref;
+    int64_t n_over;
+} ig_compare_result;
+
+ig_status ig_compare(const void* d_x, int32_t x_dtype, const double* d_ref, int64_t n, double tol,
+                     int device, void* hip_stream, ig_compare_result* res);
+
+/* FP64 sum, sum of squares and non-finite count of a device cube (the
+ * reductions behind the rms estimate and the conservation check).  Waits. */
+ig_status ig_reduce(const void* d_x, int32_t x_dtype, int64_t n, int device, void* hip_stream,
+                    double* sum, double* sumsq, int64_t* nonfinite);
+
+const char* ig_status_string(ig_status s);
+const char* ig_last_error(void);
+/* Library version as "major.minor.patch". */
+const char* ig_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGFILTER_H */

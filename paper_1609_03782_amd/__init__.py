@@ -1,0 +1,269 @@
+"""Python binding of libigfilter (the MI355X intensity-driven gradient filter).
+
+Argument marshalling only: every step of the filter runs in the library's HIP
+kernels, reached through the C ABI declared in include/igfilter.h.  PyTorch
+supplies device memory (tensor data pointers) and the current HIP stream.
+There is no fallback: if the built library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libigfilter.so")
+
+IG_OK, IG_ERR_INVALID_ARG, IG_ERR_OUT_OF_MEMORY, IG_ERR_DEVICE, IG_ERR_NONFINITE, IG_ERR_UNSUPPORTED = range(6)
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+CONDS = {"intensity": 0, "pm_exp": 1, "pm_rational": 2}
+SCHED = {"auto": 0, "naive": 1, "blocked": 2}
+
+
+class IgParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("dtype", ctypes.c_int32), ("cond", ctypes.c_int32),
+                ("n_iter", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("K", ctypes.c_float), ("tau", ctypes.c_float),
+                ("C", ctypes.c_float * 3), ("reserved0", ctypes.c_float), ("rms", ctypes.c_double)]
+
+
+class IgSchedule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("t_block", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("zchunk", ctypes.c_int32), ("vec", ctypes.c_int32)]
+
+
+class IgStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("passes", ctypes.c_int32), ("rms_used", ctypes.c_double),
+                ("sum_in", ctypes.c_double), ("sum_out", ctypes.c_double), ("nonfinite", ctypes.c_int64),
+                ("monotone", ctypes.c_int32), ("reserved", ctypes.c_int32), ("schedule", IgSchedule)]
+
+
+class IgBatchItem(ctypes.Structure):
+    _fields_ = [("p", IgParams), ("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p)]
+
+
+class IgCompareResult(ctypes.Structure):
+    _fields_ = [("max_abs", ctypes.c_double), ("rms", ctypes.c_double), ("max_ref", ctypes.c_double),
+                ("sum_x", ctypes.c_double), ("sum_ref", ctypes.c_double), ("n_over", ctypes.c_int64)]
+
+
+# name -> (restype, argtypes); the exported C ABI
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "ig_filter_create": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.c_int, ctypes.POINTER(_P)]),
+    "ig_filter_run": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(IgStats)]),
+    "ig_filter_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(IgSchedule)]),
+    "ig_filter_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(IgSchedule)]),
+    "ig_filter_destroy": (None, [_P]),
+    "ig_schedule_check": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSchedule)]),
+    "ig_filter_batch": (ctypes.c_int, [ctypes.POINTER(IgBatchItem), ctypes.c_int32, ctypes.c_int, _P,
+                                       ctypes.POINTER(IgStats), ctypes.POINTER(ctypes.c_double)]),
+    "ig_batch_cache_clear": (None, []),
+    "ig_compare": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_int, _P,
+                                  ctypes.POINTER(IgCompareResult)]),
+    "ig_reduce": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int, _P,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int64)]),
+    "ig_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ig_last_error": (ctypes.c_char_p, []),
+    "ig_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libigfilter.so (built by build.py); raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1609_03782_amd.build` "
+                               "(or __graft_entry__.build()) first; there is no fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class IgError(RuntimeError):
+    def __init__(self, status, where):
+        L = lib()
+        msg = L.ig_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {L.ig_status_string(status).decode()} ({msg})")
+        self.status = status
+
+
+def _check(status, where):
+    if status != IG_OK:
+        raise IgError(status, where)
+
+
+def make_params(shape, K=2.0, tau=1.0 / 16, n_iter=50, C=(1.0, 1.0, 1.0), rms=None, cond="pm_exp",
+                dtype="f32") -> IgParams:
+    nz, ny, nx = shape
+    p = IgParams()
+    p.struct_size = ctypes.sizeof(IgParams)
+    p.dtype = DTYPES[dtype]
+    p.cond = CONDS[cond]
+    p.n_iter = int(n_iter)
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.K, p.tau = float(K), float(tau)
+    for a in range(3):
+        p.C[a] = float(C[a])
+    p.reserved0 = 0.0
+    p.rms = float(rms) if rms is not None else 0.0
+    return p
+
+
+def schedule_check(shape, sched: dict, **params) -> str | None:
+    """None if `sched` can serve cubes of `shape`, else the reason (host only)."""
+    p = make_params(shape, **params)
+    s = IgSchedule(SCHED[sched.get("kind", "blocked")], sched.get("t_block", 2), sched.get("rows", 2),
+                   sched.get("waves", 8), sched.get("zchunk", 64), sched.get("vec", 0))
+    rc = lib().ig_schedule_check(ctypes.byref(p), ctypes.byref(s))
+    return None if rc == IG_OK else lib().ig_last_error().decode()
+
+
+def _torch_dtype_name(t):
+    import torch
+    return {torch.float32: "f32", torch.bfloat16: "bf16", torch.float16: "f16"}[t.dtype]
+
+
+def _stream_ptr(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+@dataclass
+class Stats:
+    passes: int
+    rms_used: float
+    sum_in: float
+    sum_out: float
+    nonfinite: int
+    monotone: bool
+    schedule: dict
+
+
+def _sched_dict(s: IgSchedule):
+    return {"kind": {v: k for k, v in SCHED.items()}[s.kind], "t_block": s.t_block, "rows": s.rows,
+            "waves": s.waves, "zchunk": s.zchunk, "vec": s.vec}
+
+
+class Filter:
+    """Handle for cubes of one shape and parameter set (ig_filter_create).
+
+    shape is (nz, ny, nx), x fastest.  `run(x, out)` filters a CUDA tensor of
+    that shape (float32 / bfloat16 / float16 matching `dtype`).
+    """
+
+    def __init__(self, shape, K=2.0, tau=1.0 / 16, n_iter=50, C=(1.0, 1.0, 1.0), rms=None, cond="pm_exp",
+                 dtype="f32", device=0):
+        self.shape = tuple(int(s) for s in shape)
+        self.params = make_params(self.shape, K, tau, n_iter, C, rms, cond, dtype)
+        self.dtype = dtype
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib().ig_filter_create(ctypes.byref(self.params), self.device, ctypes.byref(h)),
+               "ig_filter_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ig_filter_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_schedule(self, kind="blocked", t_block=2, rows=2, waves=8, zchunk=64, vec=0):
+        if kind == "auto":
+            _check(lib().ig_filter_set_schedule(self._h, None), "ig_filter_set_schedule")
+            return
+        s = IgSchedule(SCHED[kind], t_block, rows, waves, zchunk, vec)
+        _check(lib().ig_filter_set_schedule(self._h, ctypes.byref(s)), "ig_filter_set_schedule")
+
+    def schedule(self):
+        s = IgSchedule()
+        _check(lib().ig_filter_get_schedule(self._h, ctypes.byref(s)), "ig_filter_get_schedule")
+        return _sched_dict(s)
+
+    def _check_tensor(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {self.shape}")
+        if _torch_dtype_name(t) != self.dtype:
+            raise TypeError(f"{name} dtype {t.dtype} does not match the handle's {self.dtype}")
+
+    def run(self, x, out=None, stats=False):
+        import torch
+        self._check_tensor(x, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "out")
+        st = None
+        if stats:
+            st = IgStats()
+            st.struct_size = ctypes.sizeof(IgStats)
+        rc = lib().ig_filter_run(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 _stream_ptr(x), ctypes.byref(st) if st is not None else None)
+        _check(rc, "ig_filter_run")
+        if stats:
+            return out, Stats(st.passes, st.rms_used, st.sum_in, st.sum_out, st.nonfinite, bool(st.monotone),
+                              _sched_dict(st.schedule))
+        return out
+
+
+def batch(items, device=0, want_stats=False, want_latency=False):
+    """items: list of (x, out, params-dict).  One persistent launch (ig_filter_batch)."""
+    import torch
+    n = len(items)
+    arr = (IgBatchItem * n)()
+    for k, (x, out, kw) in enumerate(items):
+        arr[k].p = make_params(tuple(x.shape), dtype=_torch_dtype_name(x), **kw)
+        arr[k].d_in = x.data_ptr()
+        arr[k].d_out = out.data_ptr()
+    st = (IgStats * n)() if want_stats else None
+    if st is not None:
+        for k in range(n):
+            st[k].struct_size = ctypes.sizeof(IgStats)
+    lat = (ctypes.c_double * n)() if want_latency else None
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    _check(lib().ig_filter_batch(arr, n, device, stream, st, lat), "ig_filter_batch")
+    res = {}
+    if st is not None:
+        res["stats"] = [Stats(s.passes, s.rms_used, s.sum_in, s.sum_out, s.nonfinite, bool(s.monotone),
+                              _sched_dict(s.schedule)) for s in st]
+    if lat is not None:
+        res["latency_ms"] = list(lat)
+    return res
+
+
+def batch_cache_clear():
+    lib().ig_batch_cache_clear()
+
+
+def compare(x, ref, tol=0.0):
+    """FP64 error norms of device tensor x against FP64 device tensor ref (ig_compare)."""
+    import torch
+    assert ref.dtype == torch.float64 and ref.is_contiguous() and x.is_contiguous()
+    assert x.numel() == ref.numel()
+    r = IgCompareResult()
+    _check(lib().ig_compare(ctypes.c_void_p(x.data_ptr()), DTYPES[_torch_dtype_name(x)],
+                            ctypes.c_void_p(ref.data_ptr()), x.numel(), float(tol), x.device.index or 0,
+                            _stream_ptr(x), ctypes.byref(r)), "ig_compare")
+    return {"max_abs": r.max_abs, "rms": r.rms, "max_ref": r.max_ref, "sum_x": r.sum_x,
+            "sum_ref": r.sum_ref, "n_over": r.n_over}
+
+
+def reduce(x):
+    """(sum, sum of squares, non-finite count) of a device tensor, FP64 (ig_reduce)."""
+    s, q, b = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check(lib().ig_reduce(ctypes.c_void_p(x.data_ptr()), DTYPES[_torch_dtype_name(x)], x.numel(),
+                           x.device.index or 0, _stream_ptr(x), ctypes.byref(s), ctypes.byref(q),
+                           ctypes.byref(b)), "ig_reduce")
+    return s.value, q.value, b.value
