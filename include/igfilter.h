@@ -90,10 +90,12 @@ typedef enum {
 typedef struct {
     int32_t kind;      /* ig_sched_kind */
     int32_t t_block;   /* steps per pass, 1..4 (BLOCKED) */
-    int32_t rows;      /* rows of a tile per wavefront: 1, 2 or 4 (BLOCKED) */
-    int32_t waves;     /* wavefronts per workgroup, 1..16 (BLOCKED) */
-    int32_t zchunk;    /* output planes per workgroup, >= 1 (BLOCKED) */
+    int32_t waves;     /* wavefronts per workgroup = rows of a tile, 1..16 (BLOCKED) */
+    int32_t zchunk;    /* 0: split the cube into pieces of equal work, a whole number of
+                          rounds of the workgroups the GPU holds at once; > 0: pieces
+                          of zchunk output planes (BLOCKED) */
     int32_t vec;       /* x voxels per lane: 1, 2, 4 or 8; 0 = smallest covering nx */
+    int32_t rounds;    /* zchunk == 0: rounds of resident workgroups; 0 = as few as possible */
 } ig_schedule;
 
 typedef struct {
@@ -135,6 +137,13 @@ ig_status ig_filter_get_schedule(const ig_filter* f, ig_schedule* s);
  * ig_last_error(). */
 ig_status ig_schedule_check(const ig_params* p, const ig_schedule* s);
 
+/* Kernel timing: while enabled, every launch of the step loop (the passes of
+ * ig_filter_run) is bracketed by HIP events recorded on the run's stream.
+ * ig_filter_get_timing waits for those events and returns the summed device
+ * time in ms and the number of timed launches since the last reset. */
+ig_status ig_filter_set_timing(ig_filter* f, int enable);
+ig_status ig_filter_get_timing(ig_filter* f, double* total_ms, int64_t* launches, int reset);
+
 /* Release the handle and its device memory (NULL is a no-op). */
 void ig_filter_destroy(ig_filter* f);
 
@@ -161,6 +170,11 @@ ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, int device,
 
 /* Free every cached batch plan (graphs and scratch) on every device. */
 void ig_batch_cache_clear(void);
+
+/* Schedule of later ig_filter_batch plans: steps per pass t_block (1..4; 0 =
+ * library default) and wavefronts per workgroup (1..16, > 2 t_block).  All
+ * items of a batch must have nx <= 256 and share one conductance. */
+ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves);
 
 /* Comparison of a device cube with an FP64 device reference (both n
  * elements): maximum |x - ref|, root mean square of x - ref, count of

@@ -64,6 +64,8 @@ def _load():
         lib.oracle_round_bf16.restype = d
         lib.oracle_round_f16.argtypes = [d]
         lib.oracle_round_f16.restype = d
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = i32
         _lib = lib
     return _lib
 
@@ -99,6 +101,11 @@ def rms(cube):
     bad = ctypes.c_int64(0)
     r = lib.oracle_rms(a.ctypes.data, a.size, ctypes.byref(s), ctypes.byref(bad))
     return r, s.value, bad.value
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_load().oracle_threads())
 
 
 def round_bf16(x):

@@ -28,8 +28,8 @@ class IgParams(ctypes.Structure):
 
 
 class IgSchedule(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("t_block", ctypes.c_int32), ("rows", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("zchunk", ctypes.c_int32), ("vec", ctypes.c_int32)]
+    _fields_ = [("kind", ctypes.c_int32), ("t_block", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("zchunk", ctypes.c_int32), ("vec", ctypes.c_int32), ("rounds", ctypes.c_int32)]
 
 
 class IgStats(ctypes.Structure):
@@ -55,10 +55,14 @@ SIGNATURES = {
     "ig_filter_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(IgSchedule)]),
     "ig_filter_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(IgSchedule)]),
     "ig_filter_destroy": (None, [_P]),
+    "ig_filter_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "ig_filter_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.c_int]),
     "ig_schedule_check": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSchedule)]),
     "ig_filter_batch": (ctypes.c_int, [ctypes.POINTER(IgBatchItem), ctypes.c_int32, ctypes.c_int, _P,
                                        ctypes.POINTER(IgStats), ctypes.POINTER(ctypes.c_double)]),
     "ig_batch_cache_clear": (None, []),
+    "ig_batch_set_schedule": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
     "ig_compare": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_int, _P,
                                   ctypes.POINTER(IgCompareResult)]),
     "ig_reduce": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int, _P,
@@ -121,8 +125,8 @@ def make_params(shape, K=2.0, tau=1.0 / 16, n_iter=50, C=(1.0, 1.0, 1.0), rms=No
 def schedule_check(shape, sched: dict, **params) -> str | None:
     """None if `sched` can serve cubes of `shape`, else the reason (host only)."""
     p = make_params(shape, **params)
-    s = IgSchedule(SCHED[sched.get("kind", "blocked")], sched.get("t_block", 2), sched.get("rows", 2),
-                   sched.get("waves", 8), sched.get("zchunk", 64), sched.get("vec", 0))
+    s = IgSchedule(SCHED[sched.get("kind", "blocked")], sched.get("t_block", 2), sched.get("waves", 16),
+                   sched.get("zchunk", 0), sched.get("vec", 0), sched.get("rounds", 0))
     rc = lib().ig_schedule_check(ctypes.byref(p), ctypes.byref(s))
     return None if rc == IG_OK else lib().ig_last_error().decode()
 
@@ -149,8 +153,8 @@ class Stats:
 
 
 def _sched_dict(s: IgSchedule):
-    return {"kind": {v: k for k, v in SCHED.items()}[s.kind], "t_block": s.t_block, "rows": s.rows,
-            "waves": s.waves, "zchunk": s.zchunk, "vec": s.vec}
+    return {"kind": {v: k for k, v in SCHED.items()}[s.kind], "t_block": s.t_block, "waves": s.waves,
+            "zchunk": s.zchunk, "vec": s.vec, "rounds": s.rounds}
 
 
 class Filter:
@@ -178,12 +182,22 @@ class Filter:
 
     __del__ = close
 
-    def set_schedule(self, kind="blocked", t_block=2, rows=2, waves=8, zchunk=64, vec=0):
+    def set_schedule(self, kind="blocked", t_block=2, waves=16, zchunk=0, vec=0, rounds=0):
         if kind == "auto":
             _check(lib().ig_filter_set_schedule(self._h, None), "ig_filter_set_schedule")
             return
-        s = IgSchedule(SCHED[kind], t_block, rows, waves, zchunk, vec)
+        s = IgSchedule(SCHED[kind], t_block, waves, zchunk, vec, rounds)
         _check(lib().ig_filter_set_schedule(self._h, ctypes.byref(s)), "ig_filter_set_schedule")
+
+    def set_timing(self, enable=True):
+        _check(lib().ig_filter_set_timing(self._h, int(bool(enable))), "ig_filter_set_timing")
+
+    def timing(self, reset=True):
+        """(summed device ms, launches) of the step-loop kernels since the last reset."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().ig_filter_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n), int(reset)),
+               "ig_filter_get_timing")
+        return ms.value, n.value
 
     def schedule(self):
         s = IgSchedule()
@@ -245,6 +259,10 @@ def batch(items, device=0, want_stats=False, want_latency=False):
 
 def batch_cache_clear():
     lib().ig_batch_cache_clear()
+
+
+def batch_set_schedule(t_block=0, waves=16):
+    _check(lib().ig_batch_set_schedule(int(t_block), int(waves)), "ig_batch_set_schedule")
 
 
 def compare(x, ref, tol=0.0):

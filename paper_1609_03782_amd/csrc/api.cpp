@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "igfilter.h"
 #include "internal.h"
@@ -41,8 +42,7 @@ const StencilLaunch* stencil_table(int cond, int dtype) {
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
 
-static ig_status fail(ig_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-static ig_status fail(ig_status s, const char* fmt, ...) {
+ig_status igk_fail(ig_status s, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -52,6 +52,7 @@ static ig_status fail(ig_status s, const char* fmt, ...) {
     return s;
 }
 
+#define fail igk_fail
 #define HIP_TRY(expr)                                                                              \
     do {                                                                                           \
         hipError_t e_ = (expr);                                                                    \
@@ -89,10 +90,10 @@ struct DeviceGuard {
     }
 };
 
-size_t dtype_size(int dt) { return dt == IG_F32 ? 4 : 2; }
-
 bool finite_f(float v) { return std::isfinite(v); }
 }  // namespace
+
+size_t dtype_size(int dt) { return dt == IG_F32 ? 4 : 2; }
 
 // ------------------------------------------------------------------ validation
 ig_status igk_validate_params(const ig_params* p) {
@@ -120,48 +121,119 @@ ig_status igk_validate_params(const ig_params* p) {
 }
 
 // ------------------------------------------------------------------ schedule
-struct Plan {
-    ig_schedule s;
-    BlockGeom g;
-    int nblocks;
-};
-
-static int pick_vec(int64_t nx) {
+int pick_vec(int64_t nx) {
     for (int v : {1, 2, 4, 8})
         if (64 * v >= nx) return v;
     return 8;
 }
 
-// Fill the blocked geometry for schedule s; false if s cannot serve the shape.
-static bool make_geom(const ig_params* p, const ig_schedule& s, int T, BlockGeom* g, int* nblocks) {
-    const int nx = (int)p->nx, ny = (int)p->ny, nz = (int)p->nz;
-    const int V = s.vec, R = s.rows, W = s.waves;
-    if (!(V == 1 || V == 2 || V == 4 || V == 8)) return false;
-    if (!(R == 1 || R == 2 || R == 4)) return false;
-    if (W < 1 || W > 8 || T < 1 || T > 4 || s.zchunk < 1) return false;
-    const int RX = 64 * V, RY = W * R;
-    g->nx = nx; g->ny = ny; g->nz = nz;
-    g->W = W;
-    if (nx <= RX) { g->ntx = 1; g->ox = nx; }
+// Workgroups of the streaming kernel one CU holds at once: 16 wavefronts of
+// at most 128 VGPRs each (launch bound of 1024 threads) and 160 KB of LDS.
+int resident_per_cu(int W, size_t lds) {
+    const int by_waves = 16 / W;
+    const int by_lds = (int)(kMaxLds / std::max<size_t>(lds, 1));
+    return std::max(1, std::min(by_waves, by_lds));
+}
+
+// Plan the pass of depth T for schedule s; returns nullptr or the reason it
+// cannot serve the shape.
+const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp) {
+    const int nx = (int)p.nx, ny = (int)p.ny, nz = (int)p.nz;
+    const int V = s.vec ? s.vec : pick_vec(p.nx), W = s.waves;
+    if (!(V == 1 || V == 2 || V == 4 || V == 8)) return "vec must be 1, 2, 4 or 8";
+    if (W < 1 || W > 16) return "waves must be in 1..16";
+    if (T < 1 || T > 4) return "t_block must be in 1..4";
+    if (s.zchunk < 0 || s.rounds < 0) return "zchunk and rounds must be >= 0";
+    const size_t lds = stream_lds_bytes(V, T, W);
+    if (lds > kMaxLds) return "tile needs more LDS than a CU has (reduce waves, vec or t_block)";
+    BlockGeom& g = pp->g;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.W = W;
+    const int RX = 64 * V;
+    if (nx <= RX) { g.ntx = 1; g.ox = nx; }
     else {
-        g->ox = RX - 2 * T;
-        if (g->ox < 1) return false;
-        g->ntx = (nx + g->ox - 1) / g->ox;
+        g.ox = RX - 2 * T;
+        if (g.ox < 1) return "x tile too narrow for t_block";
+        g.ntx = (nx + g.ox - 1) / g.ox;
     }
-    if (ny <= RY) { g->nty = 1; g->oy = ny; }
+    if (ny <= W) { g.nty = 1; g.oy = ny; }
     else {
-        g->oy = RY - 2 * T;
-        if (g->oy < 1) return false;
-        g->nty = (ny + g->oy - 1) / g->oy;
+        g.oy = W - 2 * T;
+        if (g.oy < 1) return "too few waves for t_block (need waves > 2 * t_block)";
+        g.nty = (ny + g.oy - 1) / g.oy;
     }
-    g->oz = std::min(s.zchunk, nz);
-    g->nzc = (nz + g->oz - 1) / g->oz;
-    const long nb = (long)g->ntx * g->nty * g->nzc;
-    if (nb > 0x7fffffff) return false;
-    *nblocks = (int)nb;
-    g->remap = (nb % 8 == 0 && nb >= 64) ? 1 : 0;
-    g->vec = (g->ntx == 1 && nx % V == 0) ? 1 : 0;
-    return true;
+    g.vec = (g.ntx == 1 && nx % V == 0) ? 1 : 0;
+    pp->V = V;
+    pp->T = T;
+    auto& pcs = pp->pieces;
+    pcs.clear();
+    const long ntiles = (long)g.ntx * g.nty;
+    if (s.zchunk > 0) {
+        const int nzc = (nz + s.zchunk - 1) / s.zchunk;
+        if (ntiles * nzc > (1L << 30)) return "too many pieces";
+        for (int tz = 0; tz < nzc; ++tz)
+            for (int ty = 0; ty < g.nty; ++ty)
+                for (int tx = 0; tx < g.ntx; ++tx)
+                    pcs.push_back(Piece{tx, ty, tz * s.zchunk, std::min(nz, (tz + 1) * s.zchunk)});
+        return nullptr;
+    }
+    // balanced split: G pieces of (nearly) equal output volume, G a whole
+    // number of rounds of the resident workgroups
+    const long slots = (long)ncu * resident_per_cu(W, lds);
+    long rounds = s.rounds > 0 ? s.rounds : std::max<long>(1, (ntiles + slots - 1) / slots);
+    long G = std::min<long>(slots * rounds, ntiles * (long)nz);
+    if (G > (1L << 24)) return "too many pieces";
+    std::vector<double> area(ntiles);
+    double total = 0.0;
+    for (int ty = 0; ty < g.nty; ++ty)
+        for (int tx = 0; tx < g.ntx; ++tx) {
+            const int ex = std::min(g.ox, nx - tx * g.ox), ey = std::min(g.oy, ny - ty * g.oy);
+            area[(long)ty * g.ntx + tx] = (double)ex * ey;
+            total += (double)ex * ey;
+        }
+    std::vector<int> cnt(ntiles);
+    long used = 0;
+    for (long i = 0; i < ntiles; ++i) {
+        cnt[i] = (int)std::max<double>(1.0, std::min<double>(nz, std::floor(G * area[i] / total)));
+        used += cnt[i];
+    }
+    while (used < G) {   // give the next piece to the tile with the most work per piece
+        long best = -1;
+        double bw = -1.0;
+        for (long i = 0; i < ntiles; ++i)
+            if (cnt[i] < nz && area[i] / cnt[i] > bw) { bw = area[i] / cnt[i]; best = i; }
+        if (best < 0) break;
+        ++cnt[best];
+        ++used;
+    }
+    struct Item { Piece pc; double key; };
+    std::vector<Item> items;
+    items.reserve(used);
+    for (long i = 0; i < ntiles; ++i) {
+        const int tx = (int)(i % g.ntx), ty = (int)(i / g.ntx);
+        for (int k = 0; k < cnt[i]; ++k) {
+            const int z0 = (int)((long)k * nz / cnt[i]), z1 = (int)((long)(k + 1) * nz / cnt[i]);
+            items.push_back(Item{Piece{tx, ty, z0, z1}, 0.5 * (z0 + z1)});
+        }
+    }
+    // neighbouring pieces (same z range, adjacent tiles) next to each other ...
+    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
+        const double qa = std::floor(a.key * 8.0 / nz), qb = std::floor(b.key * 8.0 / nz);
+        if (qa != qb) return qa < qb;
+        if (a.pc.ty != b.pc.ty) return a.pc.ty < b.pc.ty;
+        return a.pc.tx < b.pc.tx;
+    });
+    // ... and each contiguous eighth of that order on one XCD: workgroups are
+    // dispatched to the 8 XCDs round-robin, so XCD j runs workgroups j, j+8, ...
+    const long n = (long)items.size();
+    pcs.resize(n);
+    if (n % 8 == 0) {
+        const long per = n / 8;
+        for (long j = 0; j < 8; ++j)
+            for (long k = 0; k < per; ++k) pcs[8 * k + j] = items[j * per + k].pc;
+    } else {
+        for (long k = 0; k < n; ++k) pcs[k] = items[k].pc;
+    }
+    return nullptr;
 }
 
 // Heuristic schedule when no tuned entry exists.
@@ -169,16 +241,11 @@ static ig_schedule auto_schedule(const ig_params* p) {
     ig_schedule s{};
     s.kind = IG_SCHED_BLOCKED;
     s.vec = pick_vec(p->nx);
-    s.rows = 2;
-    s.waves = 8;
     s.t_block = std::max(1, std::min(2, p->n_iter));
-    // z chunk: enough workgroups to fill 256 CUs a few times over
-    const int RY = s.waves * s.rows;
-    const long tiles_xy = (long)((p->nx + 64 * s.vec - 1) / (64 * s.vec)) * ((p->ny + RY - 1) / std::max(1, RY - 2 * s.t_block));
-    long zc = p->nz;
-    const long want = 1024;
-    if (tiles_xy * 1 < want) zc = std::max<long>(16, (p->nz * tiles_xy + want - 1) / want);
-    s.zchunk = (int)std::min<long>(zc, p->nz);
+    s.waves = 16;
+    if (stream_lds_bytes(s.vec, s.t_block, s.waves) > kMaxLds) s.waves = 8;
+    s.zchunk = 0;
+    s.rounds = 0;
     return s;
 }
 
@@ -191,6 +258,29 @@ struct ig_filter {
     double* parts = nullptr;     // kPartBlocks * 6 doubles
     double* results = nullptr;   // 8 doubles
     ig_schedule sched{};         // kind == AUTO: heuristic
+    int ncu = 256;               // compute units of the device
+    // piece tables per pass depth T (index T), for the current schedule
+    PassPlan plans[5];
+    Piece* dpieces[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool planned[5] = {false, false, false, false, false};
+    bool timing = false;         // bracket each stencil launch with events
+    std::vector<hipEvent_t> ev;  // pool, pairs (start, end)
+    size_t ev_used = 0;          // events recorded since the last reset
+};
+
+// Timing hooks used by enqueue_run (null when timing is off).
+struct TimingHook {
+    ig_filter* f;
+    hipStream_t s;
+    hipError_t record() {
+        if (f->ev_used == f->ev.size()) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            f->ev.push_back(e);
+        }
+        return hipEventRecord(f->ev[f->ev_used++], s);
+    }
 };
 
 extern "C" ig_status ig_filter_create(const ig_params* p, int device, ig_filter** out) {
@@ -216,6 +306,9 @@ extern "C" ig_status ig_filter_create(const ig_params* p, int device, ig_filter*
         return fail(e == hipErrorOutOfMemory ? IG_ERR_OUT_OF_MEMORY : IG_ERR_DEVICE, "allocation: %s",
                     hipGetErrorString(e));
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        f->ncu = ncu;
     f->sched.kind = IG_SCHED_AUTO;
     *out = f;
     return IG_OK;
@@ -228,6 +321,9 @@ extern "C" void ig_filter_destroy(ig_filter* f) {
     if (f->dparams) (void)hipFree(f->dparams);
     if (f->parts) (void)hipFree(f->parts);
     if (f->results) (void)hipFree(f->results);
+    for (hipEvent_t e : f->ev) (void)hipEventDestroy(e);
+    for (Piece* d : f->dpieces)
+        if (d) (void)hipFree(d);
     delete f;
 }
 
@@ -238,18 +334,19 @@ static ig_schedule resolve_schedule(const ig_filter* f) {
     return s;
 }
 
-static ig_status check_schedule(const ig_params* p, const ig_schedule* s) {
+static ig_status check_schedule(const ig_params* p, const ig_schedule* s, int ncu) {
     if (s->kind == IG_SCHED_AUTO || s->kind == IG_SCHED_NAIVE) return IG_OK;
     if (s->kind != IG_SCHED_BLOCKED) return fail(IG_ERR_INVALID_ARG, "bad schedule kind %d", s->kind);
-    ig_schedule t = *s;
-    if (t.vec == 0) t.vec = pick_vec(p->nx);
-    BlockGeom g;
-    int nb;
-    for (int T = 1; T <= std::max(1, t.t_block); ++T)
-        if (!make_geom(p, t, T, &g, &nb))
-            return fail(IG_ERR_INVALID_ARG,
-                        "schedule (T=%d rows=%d waves=%d zchunk=%d vec=%d) cannot serve %lldx%lldx%lld", T,
-                        t.rows, t.waves, t.zchunk, t.vec, (long long)p->nx, (long long)p->ny, (long long)p->nz);
+    if (s->t_block < 1 || s->t_block > 4) return fail(IG_ERR_INVALID_ARG, "t_block must be in 1..4");
+    PassPlan pp;
+    // every depth a pass of this schedule may have (the remainder pass is shallower)
+    for (int T = 1; T <= s->t_block; ++T) {
+        const char* why = plan_pass(*p, *s, T, ncu, &pp);
+        if (why)
+            return fail(IG_ERR_INVALID_ARG, "schedule (t_block=%d waves=%d zchunk=%d vec=%d) cannot serve %lldx%lldx%lld: %s",
+                        s->t_block, s->waves, s->zchunk, s->vec, (long long)p->nx, (long long)p->ny,
+                        (long long)p->nz, why);
+    }
     return IG_OK;
 }
 
@@ -257,15 +354,29 @@ extern "C" ig_status ig_schedule_check(const ig_params* p, const ig_schedule* s)
     ig_status st = igk_validate_params(p);
     if (st != IG_OK) return st;
     if (!s) return fail(IG_ERR_INVALID_ARG, "schedule is NULL");
-    return check_schedule(p, s);
+    return check_schedule(p, s, 256);
+}
+
+static void drop_plans(ig_filter* f) {
+    for (int T = 0; T < 5; ++T) {
+        if (f->dpieces[T]) (void)hipFree(f->dpieces[T]);
+        f->dpieces[T] = nullptr;
+        f->planned[T] = false;
+    }
 }
 
 extern "C" ig_status ig_filter_set_schedule(ig_filter* f, const ig_schedule* s) {
     if (!f) return fail(IG_ERR_INVALID_ARG, "handle is NULL");
-    if (!s) { f->sched = ig_schedule{}; f->sched.kind = IG_SCHED_AUTO; return IG_OK; }
-    ig_status st = check_schedule(&f->p, s);
-    if (st != IG_OK) return st;
-    f->sched = *s;
+    ig_schedule next{};
+    next.kind = IG_SCHED_AUTO;
+    if (s) {
+        ig_status st = check_schedule(&f->p, s, f->ncu);
+        if (st != IG_OK) return st;
+        next = *s;
+    }
+    DeviceGuard dg(f->device);
+    drop_plans(f);
+    f->sched = next;
     return IG_OK;
 }
 
@@ -275,9 +386,27 @@ extern "C" ig_status ig_filter_get_schedule(const ig_filter* f, ig_schedule* s) 
     return IG_OK;
 }
 
-// Enqueue the whole filter: parameters (+ scan), passes, optional output sum.
-ig_status igk_enqueue(const ig_params& p, const ig_schedule& sched, const void* d_in, void* d_out, void* scratch,
-                      DevParams* dparams, double* parts, bool scan, hipStream_t stream, int* passes_out) {
+// Plan (once) and upload the piece table of the pass of depth T.
+static ig_status get_plan(ig_filter* f, const ig_schedule& sched, int T, const PassPlan** out, const Piece** dev) {
+    if (!f->planned[T]) {
+        const char* why = plan_pass(f->p, sched, T, f->ncu, &f->plans[T]);
+        if (why) return fail(IG_ERR_INVALID_ARG, "schedule cannot serve this shape: %s", why);
+        const size_t bytes = f->plans[T].pieces.size() * sizeof(Piece);
+        if (f->dpieces[T]) (void)hipFree(f->dpieces[T]);
+        f->dpieces[T] = nullptr;
+        HIP_TRY(hipMalloc((void**)&f->dpieces[T], bytes));
+        HIP_TRY(hipMemcpy(f->dpieces[T], f->plans[T].pieces.data(), bytes, hipMemcpyHostToDevice));
+        f->planned[T] = true;
+    }
+    *out = &f->plans[T];
+    *dev = f->dpieces[T];
+    return IG_OK;
+}
+
+// Enqueue the whole filter: parameters (+ scan), then the passes.
+static ig_status enqueue_run(ig_filter* f, const ig_schedule& sched, const void* d_in, void* d_out, bool scan,
+                             hipStream_t stream, int* passes_out, TimingHook* hook) {
+    const ig_params& p = f->p;
     const long n = (long)(p.nx * p.ny * p.nz);
     ParamIn in{};
     in.K = p.K; in.tau = p.tau;
@@ -286,64 +415,66 @@ ig_status igk_enqueue(const ig_params& p, const ig_schedule& sched, const void* 
     in.abort_on_nonfinite = 1;
     in.rms = p.rms;
     if (scan) {
-        HIP_TRY(launch_sum_partial(p.dtype, d_in, n, parts, kPartBlocks, stream));
-        HIP_TRY(launch_params_final(parts, kPartBlocks, n, in, dparams, stream));
+        HIP_TRY(launch_sum_partial(p.dtype, d_in, n, f->parts, kPartBlocks, stream));
+        HIP_TRY(launch_params_final(f->parts, kPartBlocks, n, in, f->dparams, stream));
     } else {
-        HIP_TRY(launch_params_final(nullptr, 0, n, in, dparams, stream));
+        HIP_TRY(launch_params_final(nullptr, 0, n, in, f->dparams, stream));
     }
     const StencilLaunch* L = stencil_table(p.cond, p.dtype);
     if (!L) return fail(IG_ERR_UNSUPPORTED, "no kernels for cond %d dtype %d", p.cond, p.dtype);
 
     // pass depths
-    int depths[4096];
-    int P = 0;
+    std::vector<int> depths;
     const int T = sched.kind == IG_SCHED_BLOCKED ? std::max(1, sched.t_block) : 1;
     if (p.n_iter > 0) {
         const int full = p.n_iter / T, rem = p.n_iter % T;
-        if (full + (rem ? 1 : 0) > 4096) return fail(IG_ERR_UNSUPPORTED, "too many passes");
-        for (int k = 0; k < full; ++k) depths[P++] = T;
-        if (rem) depths[P++] = rem;
+        depths.assign(full, T);
+        if (rem) depths.push_back(rem);
     }
+    void* scratch = f->scratch;
     const void* src = d_in;
-    if (P == 0) {
-        if (d_in != d_out) HIP_TRY(launch_copy(p.dtype, d_in, d_out, n, dparams, stream));
+    if (depths.empty()) {
+        if (d_in != d_out) HIP_TRY(launch_copy(p.dtype, d_in, d_out, n, f->dparams, stream));
         if (passes_out) *passes_out = 0;
         return IG_OK;
     }
-    // buffers: pass k writes out if (P - k) is even, else scratch; the last pass writes d_out.
-    if (d_in == d_out && (P % 2 == 1)) {
-        // pass 1 would write the buffer it reads: split a pass if possible, else stage through scratch
+    // pass k (1-based) of P writes d_out if (P - k) is even, else scratch, so
+    // the last pass writes d_out.  In place, pass 1 must not write d_in.
+    if (d_in == d_out && depths.size() % 2 == 1) {
         int k = -1;
-        for (int j = 0; j < P; ++j) if (depths[j] >= 2) { k = j; break; }
-        if (k >= 0 && P < 4096) {
-            for (int j = P; j > k + 1; --j) depths[j] = depths[j - 1];
+        for (size_t j = 0; j < depths.size(); ++j)
+            if (depths[j] >= 2) { k = (int)j; break; }
+        if (k >= 0) {   // split one pass in two: results do not depend on the split
             const int d = depths[k];
             depths[k] = d / 2;
-            depths[k + 1] = d - d / 2;
-            ++P;
-        } else {
-            HIP_TRY(launch_copy(p.dtype, d_in, scratch, n, dparams, stream));
+            depths.insert(depths.begin() + k + 1, d - d / 2);
+        } else {        // all passes are single steps: stage the input through scratch
+            HIP_TRY(launch_copy(p.dtype, d_in, scratch, n, f->dparams, stream));
             src = scratch;
-            // with src == scratch, pass 1 must write d_out: (P - 1) even holds for odd P
         }
     }
+    const int P = (int)depths.size();
     for (int k = 1; k <= P; ++k) {
         void* dst = ((P - k) % 2 == 0) ? d_out : scratch;
         const int D = depths[k - 1];
         hipError_t e;
         if (sched.kind == IG_SCHED_NAIVE) {
-            e = L->naive(src, dst, (int)p.nx, (int)p.ny, (int)p.nz, dparams, stream);
+            if (hook) HIP_TRY(hook->record());
+            e = L->naive(src, dst, (int)p.nx, (int)p.ny, (int)p.nz, f->dparams, stream);
         } else {
-            BlockGeom g;
-            int nb;
-            if (!make_geom(&p, sched, D, &g, &nb))
-                return fail(IG_ERR_INVALID_ARG, "schedule cannot serve this shape");
+            const PassPlan* pp;
+            const Piece* dev;
+            ig_status st = get_plan(f, sched, D, &pp, &dev);
+            if (st != IG_OK) return st;
+            BlockGeom g = pp->g;
             // vector I/O also needs both buffers aligned to a lane chunk
-            const size_t al = (size_t)sched.vec * dtype_size(p.dtype);
+            const size_t al = (size_t)pp->V * dtype_size(p.dtype);
             if (((uintptr_t)src % al) || ((uintptr_t)dst % al)) g.vec = 0;
-            e = L->blocked(src, dst, g, sched.vec, sched.rows, D, dparams, stream, nb);
+            if (hook) HIP_TRY(hook->record());
+            e = L->blocked(src, dst, g, pp->V, D, dev, (int)pp->pieces.size(), f->dparams, stream);
         }
         if (e != hipSuccess) return fail(IG_ERR_DEVICE, "stencil launch: %s", hipGetErrorString(e));
+        if (hook) HIP_TRY(hook->record());
         src = dst;
     }
     if (passes_out) *passes_out = P;
@@ -375,7 +506,8 @@ extern "C" ig_status ig_filter_run(ig_filter* f, const void* d_in, void* d_out, 
     const ig_schedule sched = resolve_schedule(f);
     const bool scan = p.rms <= 0.0 || stats != nullptr;
     int passes = 0;
-    ig_status st = igk_enqueue(p, sched, d_in, d_out, f->scratch, f->dparams, f->parts, scan, s, &passes);
+    TimingHook hook{f, s};
+    ig_status st = enqueue_run(f, sched, d_in, d_out, scan, s, &passes, f->timing ? &hook : nullptr);
     if (st != IG_OK) return st;
     if (!stats) return IG_OK;
 
@@ -402,6 +534,28 @@ extern "C" ig_status ig_filter_run(ig_filter* f, const void* d_in, void* d_out, 
     HIP_TRY(hipMemcpyAsync(&ho, tmp, sizeof ho, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     stats->sum_out = ho.sum;
+    return IG_OK;
+}
+
+extern "C" ig_status ig_filter_set_timing(ig_filter* f, int enable) {
+    if (!f) return fail(IG_ERR_INVALID_ARG, "handle is NULL");
+    f->timing = enable != 0;
+    return IG_OK;
+}
+
+extern "C" ig_status ig_filter_get_timing(ig_filter* f, double* total_ms, int64_t* launches, int reset) {
+    if (!f) return fail(IG_ERR_INVALID_ARG, "handle is NULL");
+    DeviceGuard dg(f->device);
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < f->ev_used; k += 2) {
+        HIP_TRY(hipEventSynchronize(f->ev[k + 1]));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, f->ev[k], f->ev[k + 1]));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)(f->ev_used / 2);
+    if (reset) f->ev_used = 0;
     return IG_OK;
 }
 

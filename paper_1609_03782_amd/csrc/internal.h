@@ -4,7 +4,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
+#include "igfilter.h"
 #include "stencil_common.h"
+#include "stencil_kernels.h"
 
 namespace igk {
 
@@ -19,6 +23,12 @@ struct ParamIn {
 
 struct NaiveGeom;
 struct BlockGeom;
+struct Piece;
+
+// LDS bytes of the streaming kernel: current rows and up-edge terms of every
+// level, for every wavefront.
+inline size_t stream_lds_bytes(int V, int T, int W) { return (size_t)2 * T * W * 64 * V * sizeof(float); }
+constexpr size_t kMaxLds = 160 * 1024;
 
 hipError_t launch_sum_partial(int dtype, const void* x, long n, double* part, int nblk, hipStream_t s);
 hipError_t launch_params_final(const double* part, int nparts, long n, const ParamIn& in, DevParams* out,
@@ -28,14 +38,29 @@ hipError_t launch_compare(int dtype, const void* x, const double* ref, long n, d
 hipError_t launch_copy(int dtype, const void* a, void* b, long n, const DevParams* dp, hipStream_t s);
 
 // Stencil launchers; one translation unit per (conductance, storage type).
-// V in {1,2,4,8}, R in {1,2,4}, T in {1..4}.
+// V in {1,2,4,8}, T in {1..4}.
 struct StencilLaunch {
     hipError_t (*naive)(const void* src, void* dst, int nx, int ny, int nz, const DevParams* dp, hipStream_t s);
-    hipError_t (*blocked)(const void* src, void* dst, const BlockGeom& g, int V, int R, int T,
-                          const DevParams* dp, hipStream_t s, int nblocks);
+    hipError_t (*blocked)(const void* src, void* dst, const BlockGeom& g, int V, int T, const Piece* pieces,
+                          int npieces, const DevParams* dp, hipStream_t s);
 };
 const StencilLaunch* stencil_table(int cond, int dtype);
 
-constexpr int kPartBlocks = 1024;   // partials of the FP64 reductions
+constexpr int kPartBlocks = 2048;   // partials of the FP64 reductions
 
 }  // namespace igk
+
+// ------------------------------------------------------------ host planner
+// One pass of the streaming kernel, fully planned: geometry and piece table.
+struct PassPlan {
+    igk::BlockGeom g{};
+    std::vector<igk::Piece> pieces;
+    int V = 0, T = 0;
+};
+int pick_vec(int64_t nx);
+int resident_per_cu(int W, size_t lds);
+// nullptr on success, else the reason schedule s cannot serve p at depth T
+const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp);
+ig_status igk_validate_params(const ig_params* p);
+ig_status igk_fail(ig_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+size_t dtype_size(int dt);

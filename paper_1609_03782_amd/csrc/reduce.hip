@@ -56,18 +56,70 @@ __device__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV]) {
 }
 
 // ---------------------------------------------------------------- sums
+// 16-byte loads (4 FP32 or 8 16-bit values), four in flight per thread.
+template <typename ST> struct Pack;
+template <> struct Pack<float> { using T = float4; static constexpr int N = 4; };
+template <> struct Pack<__hip_bfloat16> { using T = uint4; static constexpr int N = 8; };
+template <> struct Pack<__half> { using T = uint4; static constexpr int N = 8; };
+
+template <typename ST>
+__device__ __forceinline__ void unpack(const typename Pack<ST>::T& q, float (&o)[Pack<ST>::N]) {
+    if constexpr (sizeof(ST) == 4) {
+        o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+    } else {
+        const unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const unsigned short h = (unsigned short)(w[k >> 1] >> (16 * (k & 1)));
+            ST v;
+            __builtin_memcpy(&v, &h, 2);
+            o[k] = Store<ST>::load(v);
+        }
+    }
+}
+
+__device__ __forceinline__ void acc3(float f, double& s1, double& s2, double& bad) {
+    if (!isfinite(f)) { bad += 1.0; return; }
+    const double d = f;
+    s1 += d;
+    s2 += d * d;
+}
+
+// vec: x is 16-byte aligned; n_vec packs are read as vectors, the rest singly
 template <typename ST>
 __global__ void __launch_bounds__(RED_THREADS)
-k_sum_partial(const ST* __restrict__ x, long n, double* __restrict__ part) {
+k_sum_partial(const ST* __restrict__ x, long n, int vec, double* __restrict__ part) {
+    using PT = typename Pack<ST>::T;
+    constexpr int NP = Pack<ST>::N;
     double s1 = 0.0, s2 = 0.0, bad = 0.0;
-    const long stride = (long)gridDim.x * RED_THREADS;
-    for (long i = (long)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += stride) {
-        const float f = Store<ST>::load(x[i]);
-        if (!isfinite(f)) { bad += 1.0; continue; }
-        const double d = f;
-        s1 += d;
-        s2 += d * d;
+    const long tid = (long)blockIdx.x * RED_THREADS + threadIdx.x;
+    const long nth = (long)gridDim.x * RED_THREADS;
+    long done = 0;
+    if (vec) {
+        const long nv = n / NP;
+        const PT* xv = reinterpret_cast<const PT*>(x);
+        long i = tid;
+        for (; i + 3 * nth < nv; i += 4 * nth) {
+            PT q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = xv[i + u * nth];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                float f[NP];
+                unpack<ST>(q[u], f);
+#pragma unroll
+                for (int k = 0; k < NP; ++k) acc3(f[k], s1, s2, bad);
+            }
+        }
+        for (; i < nv; i += nth) {
+            float f[NP];
+            unpack<ST>(xv[i], f);
+#pragma unroll
+            for (int k = 0; k < NP; ++k) acc3(f[k], s1, s2, bad);
+        }
+        done = nv * NP;
     }
+    for (long i = done + tid; i < n; i += nth) acc3(Store<ST>::load(x[i]), s1, s2, bad);
     double v[3] = {s1, s2, bad};
     const bool mx[3] = {false, false, false};
     block_reduce<3>(v, mx);
@@ -174,7 +226,8 @@ k_copy(const ST* __restrict__ src, ST* __restrict__ dst, long n, const DevParams
 // ---------------------------------------------------------------- launchers
 template <typename ST>
 static hipError_t sum_partial_t(const void* x, long n, double* part, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partial<ST>, dim3(nblk), dim3(RED_THREADS), 0, s, (const ST*)x, n, part);
+    const int vec = ((uintptr_t)x % 16 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_sum_partial<ST>, dim3(nblk), dim3(RED_THREADS), 0, s, (const ST*)x, n, vec, part);
     return hipGetLastError();
 }
 

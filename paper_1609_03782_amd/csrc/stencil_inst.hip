@@ -34,49 +34,44 @@ static hipError_t naive_launch(const void* src, void* dst, int nx, int ny, int n
     return hipGetLastError();
 }
 
-template <int V, int R, int T>
-static hipError_t blocked_one(const void* src, void* dst, const BlockGeom& g, const DevParams* dp,
-                              hipStream_t s, int nblocks) {
-    auto kern = k_blocked<IG_COND, ST, V, R, T>;
-    const size_t lds = (size_t)T * g.W * 2 * 64 * V * sizeof(float);
+template <int V, int T, bool VEC>
+static hipError_t stream_one(const void* src, void* dst, const BlockGeom& g, const Piece* pieces, int npieces,
+                             const DevParams* dp, hipStream_t s) {
+    auto kern = k_stream<IG_COND, ST, V, T, VEC>;
+    const size_t lds = stream_lds_bytes(V, T, g.W);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(64, g.W), lds, s, (const ST*)src, (ST*)dst, g, dp);
+    hipLaunchKernelGGL(kern, dim3(npieces), dim3(64, g.W), lds, s, (const ST*)src, (ST*)dst, g, pieces, dp);
     return hipGetLastError();
 }
 
-template <int V, int R>
-static hipError_t blocked_T(const void* src, void* dst, const BlockGeom& g, int T, const DevParams* dp,
-                            hipStream_t s, int nb) {
+template <int V, bool VEC>
+static hipError_t stream_T(const void* src, void* dst, const BlockGeom& g, int T, const Piece* pc, int np,
+                           const DevParams* dp, hipStream_t s) {
     switch (T) {
-        case 1: return blocked_one<V, R, 1>(src, dst, g, dp, s, nb);
-        case 2: return blocked_one<V, R, 2>(src, dst, g, dp, s, nb);
-        case 3: return blocked_one<V, R, 3>(src, dst, g, dp, s, nb);
-        case 4: return blocked_one<V, R, 4>(src, dst, g, dp, s, nb);
+        case 1: return stream_one<V, 1, VEC>(src, dst, g, pc, np, dp, s);
+        case 2: return stream_one<V, 2, VEC>(src, dst, g, pc, np, dp, s);
+        case 3: return stream_one<V, 3, VEC>(src, dst, g, pc, np, dp, s);
+        case 4: return stream_one<V, 4, VEC>(src, dst, g, pc, np, dp, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int V>
-static hipError_t blocked_R(const void* src, void* dst, const BlockGeom& g, int R, int T, const DevParams* dp,
-                            hipStream_t s, int nb) {
-    switch (R) {
-        case 1: return blocked_T<V, 1>(src, dst, g, T, dp, s, nb);
-        case 2: return blocked_T<V, 2>(src, dst, g, T, dp, s, nb);
-        case 4: return blocked_T<V, 4>(src, dst, g, T, dp, s, nb);
-        default: return hipErrorInvalidValue;
-    }
+static hipError_t stream_V(const void* src, void* dst, const BlockGeom& g, int T, const Piece* pc, int np,
+                           const DevParams* dp, hipStream_t s) {
+    return g.vec ? stream_T<V, true>(src, dst, g, T, pc, np, dp, s) : stream_T<V, false>(src, dst, g, T, pc, np, dp, s);
 }
 
-static hipError_t blocked_launch(const void* src, void* dst, const BlockGeom& g, int V, int R, int T,
-                                 const DevParams* dp, hipStream_t s, int nb) {
+static hipError_t blocked_launch(const void* src, void* dst, const BlockGeom& g, int V, int T, const Piece* pc,
+                                 int np, const DevParams* dp, hipStream_t s) {
     switch (V) {
-        case 1: return blocked_R<1>(src, dst, g, R, T, dp, s, nb);
-        case 2: return blocked_R<2>(src, dst, g, R, T, dp, s, nb);
-        case 4: return blocked_R<4>(src, dst, g, R, T, dp, s, nb);
-        case 8: return blocked_R<8>(src, dst, g, R, T, dp, s, nb);
+        case 1: return stream_V<1>(src, dst, g, T, pc, np, dp, s);
+        case 2: return stream_V<2>(src, dst, g, T, pc, np, dp, s);
+        case 4: return stream_V<4>(src, dst, g, T, pc, np, dp, s);
+        case 8: return stream_V<8>(src, dst, g, T, pc, np, dp, s);
         default: return hipErrorInvalidValue;
     }
 }

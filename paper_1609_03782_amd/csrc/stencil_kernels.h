@@ -34,10 +34,9 @@ struct NaiveGeom {
 
 struct BlockGeom {
     int nx, ny, nz;
-    int ntx, nty, nzc;    // tile counts in x, y, z
-    int ox, oy, oz;       // output extent of a tile in x, y, z
-    int W;                // wavefronts per workgroup (== blockDim.y)
-    int remap;            // spread consecutive tiles over one XCD's L2
+    int ntx, nty;         // tile counts in x, y
+    int ox, oy;           // output extent of a tile in x, y
+    int W;                // wavefronts (= rows) per workgroup (== blockDim.y)
     int vec;              // 1: lane chunks are whole and aligned (vector I/O)
 };
 
@@ -154,213 +153,203 @@ template <typename ST, int V> struct Vec16 {
 template <int V> struct Vec<__hip_bfloat16, V> : Vec16<__hip_bfloat16, V> {};
 template <int V> struct Vec<__half, V> : Vec16<__half, V> {};
 
-// ---------------------------------------------------------------- blocked
-template <int COND, typename ST, int V, int R, int T>
-__global__ void __launch_bounds__(512)
-k_blocked(const ST* __restrict__ src, ST* __restrict__ dst, BlockGeom g,
-          const DevParams* __restrict__ dp) {
-    extern __shared__ float lds[];   // [T][W][2][64*V]: first/last row of each level's current plane
-    const DevParams P = *dp;
-    if (P.abort) return;
+// ---------------------------------------------------------------- streaming
+// One workgroup = W wavefronts = W consecutive rows of a tile; one row per
+// wavefront, V voxels per lane (a row spans 64*V voxels).  Work comes from a
+// host-built piece table: piece b is (x tile, y tile, z0, z1) with outputs in
+// planes [z0, z1).  Per step s the workgroup
+//   phase 1: takes the input plane loaded two steps earlier, issues the load
+//            of plane s+2, and advances every level by one plane: level L
+//            turns plane p of level L-1 into plane p of level L from its own
+//            row (x edges via DPP), the y edge terms to the rows below
+//            (LDS, computed by the wavefront below) and above (own, from the
+//            previous step), and the z edge terms (registers);
+//   phase 2: publishes each level's new current row to LDS;   barrier
+//   phase 3: computes the y edge term to the row above for each level's new
+//            current row and publishes it;                      barrier
+// so every edge term of the pass is evaluated exactly once per level.
+struct Piece {
+    int tx, ty, z0, z1;
+};
 
+// One piece of one pass: the whole per-workgroup algorithm above.  `lds`
+// must hold stream_lds_bytes(V, T, W) bytes.  Called by k_stream (one cube)
+// and by the persistent batch kernel.
+template <int COND, typename ST, int V, int T, bool VEC>
+__device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __restrict__ dst, const BlockGeom& g,
+                                             const Piece pc, const DevParams& P, float* __restrict__ lds) {
+    constexpr int RX = 64 * V;
     const int lane = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int W = g.W;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    constexpr int RX = 64 * V;
-    const int RY = W * R;
 
-    int bid = blockIdx.x;
-    if (g.remap) {                       // consecutive tiles -> same XCD (round-robin dispatch)
-        const int nb = gridDim.x;
-        bid = (bid & 7) * (nb >> 3) + (bid >> 3);
-    }
-    const int tx = bid % g.ntx;
-    const int rest = bid / g.ntx;
-    const int ty = rest % g.nty;
-    const int tz = rest / g.nty;
-
-    const int ox0 = tx * g.ox, oy0 = ty * g.oy, oz0 = tz * g.oz;
-    const int ox1 = min(ox0 + g.ox, nx), oy1 = min(oy0 + g.oy, ny), oz1 = min(oz0 + g.oz, nz);
+    const int ox0 = pc.tx * g.ox, oy0 = pc.ty * g.oy;
+    const int ox1 = min(ox0 + g.ox, nx), oy1 = min(oy0 + g.oy, ny);
+    const int oz0 = pc.z0, oz1 = pc.z1;
     const int rx0 = g.ntx > 1 ? ox0 - T : 0;
     const int ry0 = g.nty > 1 ? oy0 - T : 0;
     const int zin0 = max(oz0 - T, 0), zin1 = min(oz1 + T, nz);
     const int nin = zin1 - zin0;
+    const int y = ry0 + w;                        // this wavefront's row
+    const int xl0 = rx0 + lane * V;
 
-    const int xl0 = rx0 + lane * V;           // first x of this lane
-    const int yw0 = ry0 + w * R;              // first y of this wavefront
-
-    // edge coefficients: x edge i joins xl0+i and xl0+i+1; y edge k joins yw0+k-1 and yw0+k
-    float cx[V], cy[R + 1];
+    // x edge coefficients.  Vector path (one x tile, nx a multiple of V): the
+    // edges inside a lane's chunk are open (or belong to a lane past the end
+    // of the row, whose values are never used); only the edge to the next
+    // lane can be closed.  Scalar path: per edge.
+    float cx[VEC ? 1 : V];
+    if constexpr (VEC) {
+        cx[0] = (xl0 + V < nx) ? P.coef[0] : P.closed;
+    } else {
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-        const int x = xl0 + i;
-        cx[i] = (x >= 0 && x + 1 < nx) ? P.coef[0] : P.closed;
-    }
-#pragma unroll
-    for (int k = 0; k <= R; ++k) {
-        const int y = yw0 + k - 1;
-        cy[k] = (y >= 0 && y + 1 < ny) ? P.coef[1] : P.closed;
-    }
-
-    // x offsets of the lane's voxels clamped into the cube (halo lanes read
-    // real, finite data; their results are never used)
-    const bool vec = g.vec;
-    const int xv = min(max(xl0, 0), nx - V);  // vector path: whole chunk inside
-    int xs[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) xs[i] = min(max(xl0 + i, 0), nx - 1);
-
-    auto load_plane = [&](int z, float (&o)[R][V]) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int y = min(max(yw0 + r, 0), ny - 1);
-            const ST* row = src + ((long)z * ny + y) * nx;
-            if (vec) {
-                Vec<ST, V>::load(row + xv, o[r]);
-            } else {
-#pragma unroll
-                for (int i = 0; i < V; ++i) o[r][i] = Store<ST>::load(row[xs[i]]);
-            }
+        for (int i = 0; i < V; ++i) {
+            const int x = xl0 + i;
+            cx[i] = (x >= 0 && x + 1 < nx) ? P.coef[0] : P.closed;
         }
-    };
+    }
+    const float cyu = (y >= 0 && y + 1 < ny) ? P.coef[1] : P.closed;   // edge (y, y+1)
+    const bool row_in = y >= 0 && y < ny;
+    const bool row_store = y >= oy0 && y < oy1;
+    const int lo_base = ry0 <= 0 ? 0 : ry0;
+    const int hi_base = ry0 + W >= ny ? ny : ry0 + W;
+    const int lo_step = ry0 <= 0 ? 0 : 1;
+    const int hi_step = ry0 + W >= ny ? 0 : 1;
 
-    float cur[T][R][V];   // level t: current plane of level t-1 (awaiting its z+ neighbour)
-    float fzm[T][R][V];   // level t: edge term to the plane below
+    const int ycl = min(max(y, 0), ny - 1);
+    const long plane = (long)nx * ny;
+    const ST* rowp = src + (long)ycl * nx;
+    const int xv = min(max(xl0, 0), nx - V);
+
+    // element i of this lane's chunk sits at i*64 + lane: consecutive lanes
+    // hit consecutive banks (no bank conflicts)
+    const int row_off = w * RX + lane;                   // + t * W * RX + i * 64
+    const int edge_base = T * W * RX;
+    const int lvl = W * RX;
+
+    float cur[T][V], fzm[T][V];
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int i = 0; i < V; ++i) { cur[t][i] = 0.0f; fzm[t][i] = 0.0f; }
 #pragma unroll
-            for (int i = 0; i < V; ++i) { cur[t][r][i] = 0.0f; fzm[t][r][i] = 0.0f; }
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int i = 0; i < V; ++i) lds[edge_base + t * lvl + row_off + 64 * i] = 0.0f;
 
-    float pf[R][V];
-    if (nin > 0) load_plane(zin0, pf);
-
-    float* lds_lvl = lds;  // base
-    const int row_stride = RX;
-    auto lds_row = [&](int t, int wave, int side) -> float* {
-        return lds_lvl + ((t * W + wave) * 2 + side) * row_stride;
+    float pf[V];
+    auto load = [&](int z) {
+        const ST* r = rowp + (long)z * plane;
+        if constexpr (VEC) {
+            Vec<ST, V>::load(r + xv, pf);
+        } else {
+#pragma unroll
+            for (int i = 0; i < V; ++i) pf[i] = Store<ST>::load(r[min(max(xl0 + i, 0), nx - 1)]);
+        }
     };
+    if (nin > 0) load(zin0);
+    __syncthreads();
 
     const int nsteps = nin + T;
     for (int s = 0; s < nsteps; ++s) {
-        float nxt[R][V];
+        float nxt[V];
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int i = 0; i < V; ++i) nxt[r][i] = pf[r][i];
-        if (s + 1 < nin) load_plane(zin0 + s + 1, pf);
+        for (int i = 0; i < V; ++i) nxt[i] = pf[i];
+        if (s + 1 < nin) load(zin0 + s + 1);
 
+        // phase 1: every level advances one plane
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            // level t+1 of the pass; `nxt` holds plane zin0+s-t of level t (if any)
             const bool has_nxt = (s - t >= 0) && (s - t < nin);
             const bool compute = (s - t - 1 >= 0) && (s - t - 1 < nin);
-            const int p = zin0 + s - t - 1;   // plane computed by this level
-            float outv[R][V];
+            const int p = zin0 + s - t - 1;
             if (compute) {
-                const int L = t + 1;          // level number
-                const int lo = ry0 <= 0 ? 0 : ry0 + L;
-                const int hi = ry0 + RY >= ny ? ny : ry0 + RY - L;
-                const float czp = (p + 1 < nz && has_nxt) ? P.coef[2] : P.closed;
-                // rows next to this wavefront, from its neighbours (same level, same plane)
-                float dn[V], up[V];
-                if (w > 0) {
-                    const float* q = lds_row(t, w - 1, 1) + lane * V;
-#pragma unroll
-                    for (int i = 0; i < V; ++i) dn[i] = q[i];
-                } else {
-#pragma unroll
-                    for (int i = 0; i < V; ++i) dn[i] = cur[t][0][i];
-                }
-                if (w + 1 < W) {
-                    const float* q = lds_row(t, w + 1, 0) + lane * V;
-#pragma unroll
-                    for (int i = 0; i < V; ++i) up[i] = q[i];
-                } else {
-#pragma unroll
-                    for (int i = 0; i < V; ++i) up[i] = cur[t][R - 1][i];
-                }
-                // y edge terms: ey[k] joins row k-1 and row k (row -1 = dn, row R = up)
-                float ey[R + 1][V];
-#pragma unroll
-                for (int i = 0; i < V; ++i) {
-                    ey[0][i] = edge_term<COND>(cur[t][0][i] - dn[i], cy[0], P.kap);
-#pragma unroll
-                    for (int k = 1; k < R; ++k)
-                        ey[k][i] = edge_term<COND>(cur[t][k][i] - cur[t][k - 1][i], cy[k], P.kap);
-                    ey[R][i] = edge_term<COND>(up[i] - cur[t][R - 1][i], cy[R], P.kap);
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int y = yw0 + r;
-                    if (y < lo || y >= hi) {
-#pragma unroll
-                        for (int i = 0; i < V; ++i) outv[r][i] = cur[t][r][i];
-                        continue;
-                    }
+                const int L = t + 1;
+                const bool valid = row_in && y >= lo_base + L * lo_step && y < hi_base - L * hi_step;
+                float out[V];
+                if (valid) {
+                    const float czp = (p + 1 < nz && has_nxt) ? P.coef[2] : P.closed;
                     float ex[V];
 #pragma unroll
                     for (int i = 0; i < V - 1; ++i)
-                        ex[i] = edge_term<COND>(cur[t][r][i + 1] - cur[t][r][i], cx[i], P.kap);
-                    const float right = lane_shl1(cur[t][r][0]);
-                    ex[V - 1] = edge_term<COND>(right - cur[t][r][V - 1], cx[V - 1], P.kap);
+                        ex[i] = edge_term<COND>(cur[t][i + 1] - cur[t][i], VEC ? P.coef[0] : cx[i], P.kap);
+                    const float right = lane_shl1(cur[t][0]);
+                    ex[V - 1] = edge_term<COND>(right - cur[t][V - 1], cx[VEC ? 0 : V - 1], P.kap);
                     const float exm0 = lane_shr1(ex[V - 1]);
+                    const int eo = edge_base + t * lvl + row_off;
 #pragma unroll
                     for (int i = 0; i < V; ++i) {
-                        const float n_up = has_nxt ? nxt[r][i] : cur[t][r][i];
-                        const float ezp = edge_term<COND>(n_up - cur[t][r][i], czp, P.kap);
-                        const float exm = i == 0 ? exm0 : ex[i - 1];
-                        const float o = combine<COND>(cur[t][r][i], exm, ex[i], ey[r][i], ey[r + 1][i],
-                                                      fzm[t][r][i], ezp, P.kap, P.tau);
-                        outv[r][i] = Store<ST>::quant(o);
-                        fzm[t][r][i] = ezp;
+                        const float eyd = w > 0 ? lds[eo - RX + 64 * i] : 0.0f;
+                        const float eyu = lds[eo + 64 * i];
+                        const float up_z = has_nxt ? nxt[i] : cur[t][i];
+                        const float ezp = edge_term<COND>(up_z - cur[t][i], czp, P.kap);
+                        const float o = combine<COND>(cur[t][i], i == 0 ? exm0 : ex[i - 1], ex[i], eyd, eyu,
+                                                      fzm[t][i], ezp, P.kap, P.tau);
+                        out[i] = Store<ST>::quant(o);
+                        fzm[t][i] = ezp;
                     }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < V; ++i) out[i] = cur[t][i];
                 }
-            }
-            if (has_nxt) {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int i = 0; i < V; ++i) cur[t][r][i] = nxt[r][i];
-            }
-            if (compute) {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int i = 0; i < V; ++i) nxt[r][i] = outv[r][i];
-            }
-            if (t == T - 1 && compute && p >= oz0 && p < oz1) {
-                // write the last level's plane: rows [oy0, oy1), columns [ox0, ox1)
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int y = yw0 + r;
-                    if (y < oy0 || y >= oy1) continue;
-                    ST* row = dst + ((long)p * ny + y) * nx;
-                    if (vec && xl0 >= ox0 && xl0 + V <= ox1) {
-                        Vec<ST, V>::store(row + xl0, outv[r]);
+                if (t == T - 1 && row_store && p >= oz0 && p < oz1) {
+                    ST* r = dst + (long)p * plane + (long)y * nx;
+                    if constexpr (VEC) {
+                        if (xl0 >= ox0 && xl0 + V <= ox1) Vec<ST, V>::store(r + xl0, out);
                     } else {
 #pragma unroll
                         for (int i = 0; i < V; ++i) {
                             const int x = xl0 + i;
-                            if (x >= ox0 && x < ox1) row[x] = Store<ST>::store(outv[r][i]);
+                            if (x >= ox0 && x < ox1) r[x] = Store<ST>::store(out[i]);
                         }
                     }
                 }
+                if (has_nxt) {
+#pragma unroll
+                    for (int i = 0; i < V; ++i) cur[t][i] = nxt[i];
+                }
+#pragma unroll
+                for (int i = 0; i < V; ++i) nxt[i] = out[i];
+            } else if (has_nxt) {
+#pragma unroll
+                for (int i = 0; i < V; ++i) cur[t][i] = nxt[i];
             }
         }
-        // publish the new current planes' edge rows for the next step
-        __syncthreads();
+        // phase 2: publish each level's new current row
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            float* q0 = lds_row(t, w, 0) + lane * V;
-            float* q1 = lds_row(t, w, 1) + lane * V;
+            if ((s - t >= 0) && (s - t < nin)) {
 #pragma unroll
-            for (int i = 0; i < V; ++i) { q0[i] = cur[t][0][i]; q1[i] = cur[t][R - 1][i]; }
+                for (int i = 0; i < V; ++i) lds[t * lvl + row_off + 64 * i] = cur[t][i];
+            }
+        }
+        __syncthreads();
+        // phase 3: y edge term from the new current row to the row above
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            if ((s - t >= 0) && (s - t < nin)) {
+                const int ro = t * lvl + row_off;
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    const float up = w + 1 < W ? lds[ro + RX + 64 * i] : cur[t][i];
+                    lds[edge_base + ro + 64 * i] = edge_term<COND>(up - cur[t][i], cyu, P.kap);
+                }
+            }
         }
         __syncthreads();
     }
+}
+
+template <int COND, typename ST, int V, int T, bool VEC>
+__global__ void __launch_bounds__(1024)
+k_stream(const ST* __restrict__ src, ST* __restrict__ dst, BlockGeom g, const Piece* __restrict__ pieces,
+         const DevParams* __restrict__ dp) {
+    // LDS: rows[T][W][64V] (current row of each level) then edges[T][W][64V]
+    // (y edge term from that row to the row above)
+    extern __shared__ float lds[];
+    const DevParams P = *dp;
+    if (P.abort) return;
+    stream_piece<COND, ST, V, T, VEC>(src, dst, g, pieces[blockIdx.x], P, lds);
 }
 
 }  // namespace igk

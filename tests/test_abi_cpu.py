@@ -101,4 +101,5 @@ def test_gpu_test_schedules_are_valid():
             assert ig.schedule_check(shape, s, n_iter=7) is None, (shape, s)
     for s in g.INPLACE_SCHEDS:
         assert ig.schedule_check(g.INPLACE_SHAPE, s, n_iter=5) is None, s
-    assert ig.schedule_check((17, 33, 66), dict(kind="blocked", t_block=4, rows=2, waves=4)) is not None
+    assert ig.schedule_check((17, 33, 66), dict(kind="blocked", t_block=4, waves=8)) is not None
+    assert ig.schedule_check((17, 33, 600), dict(kind="blocked", t_block=4, waves=16, vec=8)) is not None

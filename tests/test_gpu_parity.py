@@ -76,12 +76,14 @@ def test_paper_defaults_parity(dev, oracle_lib, cond):
 
 SCHEDS = [
     dict(kind="naive"),
-    dict(kind="blocked", t_block=1, rows=1, waves=3, zchunk=3, vec=1),
-    dict(kind="blocked", t_block=2, rows=2, waves=3, zchunk=5, vec=1),
-    dict(kind="blocked", t_block=3, rows=4, waves=2, zchunk=7, vec=2),
-    dict(kind="blocked", t_block=4, rows=2, waves=8, zchunk=64, vec=0),
-    dict(kind="blocked", t_block=2, rows=1, waves=6, zchunk=4, vec=4),
-    dict(kind="blocked", t_block=3, rows=2, waves=5, zchunk=9, vec=8),
+    dict(kind="blocked", t_block=1, waves=3, zchunk=3, vec=1),
+    dict(kind="blocked", t_block=2, waves=5, zchunk=5, vec=1),
+    dict(kind="blocked", t_block=3, waves=8, zchunk=7, vec=2),
+    dict(kind="blocked", t_block=4, waves=9, zchunk=0, vec=0),
+    dict(kind="blocked", t_block=2, waves=6, zchunk=4, vec=4),
+    dict(kind="blocked", t_block=3, waves=10, zchunk=9, vec=8),
+    dict(kind="blocked", t_block=2, waves=16, zchunk=0, vec=0, rounds=3),
+    dict(kind="blocked", t_block=1, waves=16, zchunk=0, vec=0),
 ]
 
 
@@ -128,9 +130,9 @@ def test_identity_cases_bitwise(dev):
 
 
 INPLACE_SHAPE = (17, 33, 66)
-INPLACE_SCHEDS = [dict(kind="naive"), dict(kind="blocked", t_block=1, rows=2, waves=4, zchunk=8),
-                  dict(kind="blocked", t_block=2, rows=2, waves=4, zchunk=8),
-                  dict(kind="blocked", t_block=4, rows=2, waves=8, zchunk=8)]
+INPLACE_SCHEDS = [dict(kind="naive"), dict(kind="blocked", t_block=1, waves=4, zchunk=8),
+                  dict(kind="blocked", t_block=2, waves=8, zchunk=8),
+                  dict(kind="blocked", t_block=4, waves=9, zchunk=0)]
 
 
 def test_in_place_and_odd_passes(dev, oracle_lib):
