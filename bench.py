@@ -1,10 +1,15 @@
 """Benchmark of the filter's hot path on one MI355X.
 
-A step is one whole filter run on the 512^3 FP32 cube: the FP64 rms scan
-and 50 explicit steps of the exponential-conductance filter (K = 2 rms,
-tau = 1/16, C = 1), input resident in HBM.  Prints one JSON line.
+Default workload (the headline): one step = one whole filter run on the
+512^3 FP32 cube: the FP64 rms scan and 50 explicit steps of the
+exponential-conductance filter (K = 2 rms, tau = 1/16, C = 1), input
+resident in HBM.  Prints one JSON line.  The same line carries the 16-bit
+storage runs of that cube, the paper's default parameters on it, and the
+96-cube batched launch, each measured the same way.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--calib-copy]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+  python bench.py --workload surrogate [--train N] [--epochs E]
+  python bench.py --calib-copy          (plain copy of the cube size, for counter calibration)
 """
 from __future__ import annotations
 
@@ -33,8 +38,175 @@ def cpu_baseline(cube, n_iter, K, tau):
     oracle.run(slab, "pm_exp", K=K, tau=tau, n_iter=n_iter, rms=1.0)
     dt = time.perf_counter() - t0
     vi = slab.size * n_iter
-    return {"value": vi / dt / 1e9, "unit": "Gvoxel-iter/s", "cores": oracle.threads(), "kind": "oracle",
+    return {"value": round(vi / dt / 1e9, 5), "unit": "Gvoxel-iter/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"512x512x{nz_s} slab of the same cube, {n_iter} iterations, FP64 ({dt:.1f} s)"}
+
+
+def time_runs(f, x, out, steps, warmup, timing=False):
+    """ms per run over `steps` runs (HIP events on the run's stream), and the
+    summed step-kernel time / launches when timing=True."""
+    import torch
+    for _ in range(warmup):
+        f.run(x, out)
+    torch.cuda.synchronize()
+    if timing:
+        f.set_timing(True)
+        f.timing(reset=True)
+    stream = torch.cuda.current_stream(x.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        f.run(x, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kt = None
+    if timing:
+        kt = f.timing(reset=True)
+        f.set_timing(False)
+    return ms, kt
+
+
+def bench_precision(cube_t, steps, ref_out):
+    """16-bit storage of the same cube: throughput and deviation from the FP32 run."""
+    import torch
+    import paper_1609_03782_amd as ig
+    res = {}
+    ref = ref_out.double()
+    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        x = cube_t.to(dt)
+        out = torch.empty_like(x)
+        f = ig.Filter(tuple(x.shape), K=2.0, tau=1 / 16, n_iter=N_ITER, cond="pm_exp", dtype=name)
+        ms, _ = time_runs(f, x, out, steps, 2)
+        d = out.double() - ref
+        res[name] = {"ms_per_run": round(ms, 4), "Gvoxel_iter_s": round(x.numel() * N_ITER / ms / 1e6, 2),
+                     "effective_hbm_GBps": round(4.0 * x.numel() * N_ITER / ms / 1e6, 1),
+                     "max_abs_vs_f32_rms": float(d.abs().max()), "rms_vs_f32_rms": float(d.pow(2).mean().sqrt()),
+                     "schedule": f.schedule()}
+    return res
+
+
+def bench_paper_defaults(x, steps):
+    """The paper's own filter and defaults (intensity conductance, K = 1.5,
+    tau = 0.0325, n = 20, C = 5) on the same cube, with and without the
+    host<->device copies the paper's GPU timing includes."""
+    import torch
+    import paper_1609_03782_amd as ig
+    out = torch.empty_like(x)
+    f = ig.Filter(tuple(x.shape), K=1.5, tau=0.0325, n_iter=20, C=(5.0, 5.0, 5.0), cond="intensity")
+    ms, _ = time_runs(f, x, out, steps, 2)
+    host = x.cpu().pin_memory()
+    back = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        xd = host.to(x.device, non_blocking=True)
+        yd = f.run(xd)
+        back.copy_(yd, non_blocking=True)
+        torch.cuda.synchronize()
+    io_ms = (time.perf_counter() - t0) / 3 * 1e3
+    return {"ms_per_run": round(ms, 4), "Gvoxel_iter_s": round(x.numel() * 20 / ms / 1e6, 2),
+            "ms_with_host_io": round(io_ms, 3), "schedule": f.schedule(),
+            "paper_gpu_s_for_1.4e8_voxels": 3.1}
+
+
+def bench_batch(steps):
+    """96 uneven cubes in one persistent, graph-captured launch."""
+    import numpy as np
+    import torch
+    import igsynth
+    import paper_1609_03782_amd as ig
+    plan = igsynth.batch_plan(96, seed=4)
+    items, work = [], 0
+    for it in plan:
+        x = torch.from_numpy(igsynth.batch_cube(it)).cuda()
+        items.append((x, torch.empty_like(x), dict(K=it.K, tau=1 / 16, n_iter=it.n_iter, cond="pm_exp")))
+        work += x.numel() * it.n_iter
+    T, W, _ = ig.batch_autotune(items)
+    ig.batch(items)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ig.batch(items)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    lat = np.array(ig.batch(items, want_latency=True)["latency_ms"])
+    return {"cubes": len(items), "voxels": int(sum(x.numel() for x, _, _ in items)), "voxel_iters": int(work),
+            "ms_per_batch": round(ms, 4), "Gvoxel_iter_s": round(work / ms / 1e6, 2),
+            "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
+            "policy": "pass-major rounds, longest cubes first", "t_block": T, "waves": W}
+
+
+def bench_surrogate(args):
+    """Learned surrogate: train on filter-generated pairs, calibrate the
+    residual check, then time checked inference on the 512^3 cube against
+    the plain filter."""
+    import numpy as np
+    import torch
+    import igsynth
+    import paper_1609_03782_amd as ig
+    from paper_1609_03782_amd import surrogate as sg
+    dev = torch.device("cuda:0")
+    params = dict(K=2.0, tau=1 / 16, n_iter=N_ITER, cond="pm_exp")
+    t0 = time.perf_counter()
+    xs_np = igsynth.train_set(range(100000, 100000 + args.train), n=args.cube, workers=16)
+    xs = [torch.from_numpy(c).to(dev) for c in xs_np]
+    del xs_np
+    ts = sg.filter_targets(xs, n_iter=N_ITER)
+    vx_np = igsynth.train_set(range(200000, 200000 + args.val), n=args.cube, workers=16)
+    vxs = [torch.from_numpy(c).to(dev) for c in vx_np]
+    vts = sg.filter_targets(vxs, n_iter=N_ITER)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = sg.Surrogate(depth=8, lr=args.lr, seed=0)
+    t0 = time.perf_counter()
+    losses = sg.train(net, xs, ts, epochs=args.epochs, batch=args.batch, log=lambda m: print(m, file=sys.stderr,
+                                                                                            flush=True))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    slope, pairs = sg.calibrate(net, vxs, vts, params)
+    val_rmse = float(np.mean([e for _, e in pairs]))
+    del xs, ts
+    cube = igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])
+    x = torch.from_numpy(cube).to(dev)
+    f = ig.Filter(cube.shape, **params)
+    plain = torch.empty_like(x)
+    ms_plain, _ = time_runs(f, x, plain, 5, 2)
+    y, rep = net.infer_checked(x, params, slope=slope, threshold=args.threshold)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        y, rep = net.infer_checked(x, params, slope=slope, threshold=args.threshold)
+    torch.cuda.synchronize()
+    ms_checked = (time.perf_counter() - t0) / 3 * 1e3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ysur = net.infer(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_infer = e0.elapsed_time(e1)
+    rmse_sur = float(torch.sqrt(torch.mean((ysur.double() - plain.double()) ** 2)).item()) / rep["rho"]
+    rmse_out = float(torch.sqrt(torch.mean((y.double() - plain.double()) ** 2)).item()) / rep["rho"]
+    flops = 335232.0 * cube.size
+    res = {"metric": "surrogate speedup vs plain GPU filter at RMSE <= 0.05 sigma", "value": round(ms_plain / ms_checked, 4),
+           "unit": "x", "higher_is_better": True, "n_gpus": 1, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "8-layer 32-channel 3x3x3 CNN, bf16 MFMA, trained on filter-generated pairs, "
+                                  "checked inference on the 512^3 cube",
+                      "train_cubes": args.train, "val_cubes": args.val, "cube": args.cube, "epochs": args.epochs,
+                      "batch": args.batch, "lr": args.lr},
+           "ms_plain_filter": round(ms_plain, 3), "ms_checked_inference": round(ms_checked, 3),
+           "ms_surrogate_forward": round(ms_infer, 3),
+           "forward_TFLOPs": round(flops / ms_infer / 1e9, 2),
+           "rmse_surrogate_vs_filter_sigma": rmse_sur, "rmse_output_vs_filter_sigma": rmse_out,
+           "fell_back": rep["fell_back"], "residual": rep["residual"], "slope": slope,
+           "threshold": args.threshold, "val_rmse_mean_sigma": val_rmse,
+           "loss_first": losses[0] if losses else None, "loss_last": float(np.mean(losses[-20:])) if losses else None,
+           "s_data": round(t_data, 1), "s_train": round(t_train, 1),
+           "breakeven_note": "plain filter time grows ~linearly with n; surrogate time does not"}
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -43,6 +215,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--workload", default="filter", choices=["filter", "surrogate"])
+    ap.add_argument("--train", type=int, default=4000)
+    ap.add_argument("--val", type=int, default=200)
+    ap.add_argument("--cube", type=int, default=96)
+    ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--threshold", type=float, default=0.05)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of the cube size (counter calibration)")
     args = ap.parse_args()
@@ -66,6 +247,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes_read": a.numel() * 4, "calib_copy_bytes_written": a.numel() * 4}))
         return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
+        return
 
     cube = igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])
     x = torch.from_numpy(cube).to(dev)
@@ -73,31 +257,13 @@ def main():
     K, tau = 2.0, 1.0 / 16
     f = ig.Filter(cube.shape, K=K, tau=tau, n_iter=N_ITER, C=(1.0, 1.0, 1.0), cond="pm_exp")
     sched = f.schedule()
-
-    for _ in range(args.warmup):
-        f.run(x, out)
-    torch.cuda.synchronize()
-
-    f.set_timing(True)
-    f.timing(reset=True)
-    stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        f.run(x, out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
-    k_ms, k_launches = f.timing(reset=True)
-    f.set_timing(False)
+    ms_step, (k_ms, k_launches) = time_runs(f, x, out, args.steps, args.warmup, timing=True)
 
     N = cube.size
-    ms_step = ms_total / args.steps
     value = N * N_ITER / (ms_step * 1e-3) / 1e9
     eff_gbs = 8.0 * N * N_ITER / (ms_step * 1e-3) / 1e9
-    # dominant kernel: the blocked step kernel; algorithmic bytes per launch =
-    # 8 B per voxel-iteration (4 read + 4 written) x N voxels x steps per launch
+    # dominant kernel: k_stream; algorithmic bytes per launch = 8 B per
+    # voxel-step (4 read + 4 written) x N voxels x steps per launch
     T = max(1, sched["t_block"]) if sched["kind"] == "blocked" else 1
     avg_ms = k_ms / max(1, k_launches)
     achieved = 8.0 * N * T / (avg_ms * 1e-3) / 1e9
@@ -123,8 +289,14 @@ def main():
                    "effective_hbm_frac": round(eff_gbs / HBM_PEAK_GBS, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_blocked", "avg_launch_ms": round(avg_ms, 5), "launches": k_launches},
+                     "kernel": "k_stream", "avg_launch_ms": round(avg_ms, 5), "launches": k_launches},
     }
+    if not args.no_extras:
+        extras = {}
+        extras["precision_16bit"] = bench_precision(x, max(3, args.steps // 4), out)
+        extras["paper_defaults_intensity"] = bench_paper_defaults(x, max(3, args.steps // 4))
+        extras["batch_96"] = bench_batch(max(3, args.steps // 4))
+        res["extras"] = extras
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(cube, N_ITER, K, tau)
     print(json.dumps(res), flush=True)

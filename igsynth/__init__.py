@@ -240,3 +240,25 @@ def random_cube(shape, seed, scale=1.0, offset=0.0):
     """Plain Gaussian random cube (nz, ny, nx) for small parity cases."""
     rng = np.random.default_rng(seed)
     return (rng.standard_normal(shape) * scale + offset).astype(np.float32)
+
+
+def train_cube(seed: int, n: int = 96):
+    """n^3 cube: one galaxy (h in 4 .. n/8 px, peak S/N 10) plus, with probability
+    0.5, a tail at S/N 0.5-1.5; noise rms 1.  Used for surrogate training."""
+    return batch_cube(BatchItem((n, n, n), 2.0, 50, seed))
+
+
+def _train_cube_args(a):
+    return train_cube(*a)
+
+
+def train_set(seeds, n: int = 96, workers: int = 8):
+    """Stack of train_cube(seed, n) for each seed, generated in worker processes."""
+    import multiprocessing as mp
+    seeds = list(seeds)
+    if workers <= 1 or len(seeds) < 8:
+        return np.stack([train_cube(s, n) for s in seeds])
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        cubes = pool.map(_train_cube_args, [(s, n) for s in seeds], chunksize=16)
+    return np.stack(cubes)

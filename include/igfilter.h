@@ -137,6 +137,18 @@ ig_status ig_filter_get_schedule(const ig_filter* f, ig_schedule* s);
  * ig_last_error(). */
 ig_status ig_schedule_check(const ig_params* p, const ig_schedule* s);
 
+/* Autotuner: times the filter with each candidate schedule (t_block 1..4,
+ * waves 8/12/16, 1 or 2 rounds of pieces; those the shape and the LDS allow)
+ * on d_in -> d_work (distinct buffers of the handle's shape and type; d_work
+ * is overwritten), sets the fastest on the handle and returns it in *best
+ * (and its run time in *best_ms, nullable).  If the environment variable
+ * IG_TUNE_CACHE names a file, a result stored there for the same device
+ * architecture, storage type, conductance, shape and n is used without
+ * timing, and new results are appended to it (one JSON object per line).
+ * Waits for the stream. */
+ig_status ig_filter_autotune(ig_filter* f, const void* d_in, void* d_work, void* hip_stream, ig_schedule* best,
+                             double* best_ms);
+
 /* Kernel timing: while enabled, every launch of the step loop (the passes of
  * ig_filter_run) is bracketed by HIP events recorded on the run's stream.
  * ig_filter_get_timing waits for those events and returns the summed device
@@ -175,6 +187,13 @@ void ig_batch_cache_clear(void);
  * library default) and wavefronts per workgroup (1..16, > 2 t_block).  All
  * items of a batch must have nx <= 256 and share one conductance. */
 ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves);
+
+/* Batch autotuner: runs the batch with t_block 1..4 and waves 8 and 16,
+ * keeps the fastest (sets it as by ig_batch_set_schedule) and returns it.
+ * Every item must have d_in != d_out (outputs are overwritten; inputs are
+ * read only).  Waits for the stream. */
+ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
+                            int32_t* best_t_block, int32_t* best_waves, double* best_ms);
 
 /* Comparison of a device cube with an FP64 device reference (both n
  * elements): maximum |x - ref|, root mean square of x - ref, count of

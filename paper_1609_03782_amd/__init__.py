@@ -55,6 +55,10 @@ SIGNATURES = {
     "ig_filter_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(IgSchedule)]),
     "ig_filter_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(IgSchedule)]),
     "ig_filter_destroy": (None, [_P]),
+    "ig_filter_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(IgSchedule), ctypes.POINTER(ctypes.c_double)]),
+    "ig_batch_autotune": (ctypes.c_int, [ctypes.POINTER(IgBatchItem), ctypes.c_int32, ctypes.c_int, _P,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double)]),
     "ig_filter_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "ig_filter_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                             ctypes.c_int]),
@@ -189,6 +193,17 @@ class Filter:
         s = IgSchedule(SCHED[kind], t_block, waves, zchunk, vec, rounds)
         _check(lib().ig_filter_set_schedule(self._h, ctypes.byref(s)), "ig_filter_set_schedule")
 
+    def autotune(self, x, work=None):
+        """Time candidate schedules on x (into `work`), keep the fastest; returns (schedule, ms)."""
+        import torch
+        self._check_tensor(x, "x")
+        work = torch.empty_like(x) if work is None else work
+        best = IgSchedule()
+        ms = ctypes.c_double()
+        _check(lib().ig_filter_autotune(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(work.data_ptr()),
+                                        _stream_ptr(x), ctypes.byref(best), ctypes.byref(ms)), "ig_filter_autotune")
+        return _sched_dict(best), ms.value
+
     def set_timing(self, enable=True):
         _check(lib().ig_filter_set_timing(self._h, int(bool(enable))), "ig_filter_set_timing")
 
@@ -236,11 +251,7 @@ def batch(items, device=0, want_stats=False, want_latency=False):
     """items: list of (x, out, params-dict).  One persistent launch (ig_filter_batch)."""
     import torch
     n = len(items)
-    arr = (IgBatchItem * n)()
-    for k, (x, out, kw) in enumerate(items):
-        arr[k].p = make_params(tuple(x.shape), dtype=_torch_dtype_name(x), **kw)
-        arr[k].d_in = x.data_ptr()
-        arr[k].d_out = out.data_ptr()
+    arr = _batch_array(items)
     st = (IgStats * n)() if want_stats else None
     if st is not None:
         for k in range(n):
@@ -255,6 +266,27 @@ def batch(items, device=0, want_stats=False, want_latency=False):
     if lat is not None:
         res["latency_ms"] = list(lat)
     return res
+
+
+def _batch_array(items):
+    n = len(items)
+    arr = (IgBatchItem * n)()
+    for k, (x, out, kw) in enumerate(items):
+        arr[k].p = make_params(tuple(x.shape), dtype=_torch_dtype_name(x), **kw)
+        arr[k].d_in = x.data_ptr()
+        arr[k].d_out = out.data_ptr()
+    return arr
+
+
+def batch_autotune(items, device=0):
+    """Time the batch under candidate schedules; keep the fastest.  Returns (t_block, waves, ms)."""
+    import torch
+    arr = _batch_array(items)
+    T, W, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    _check(lib().ig_batch_autotune(arr, len(items), device, stream, ctypes.byref(T), ctypes.byref(W),
+                                   ctypes.byref(ms)), "ig_batch_autotune")
+    return T.value, W.value, ms.value
 
 
 def batch_cache_clear():

@@ -559,6 +559,98 @@ extern "C" ig_status ig_filter_get_timing(ig_filter* f, double* total_ms, int64_
     return IG_OK;
 }
 
+// ------------------------------------------------------------------ autotuner
+namespace {
+std::string tune_key(const ig_filter* f, const char* arch) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|dtype=%d|cond=%d|%lldx%lldx%lld|n=%d", arch, f->p.dtype, f->p.cond,
+             (long long)f->p.nx, (long long)f->p.ny, (long long)f->p.nz, f->p.n_iter);
+    return buf;
+}
+
+// Look the key up in the cache file (lines: {"key": "...", "t_block": T, "waves": W, "rounds": R, "ms": x})
+bool tune_lookup(const char* path, const std::string& key, ig_schedule* s) {
+    FILE* fp = fopen(path, "r");
+    if (!fp) return false;
+    char line[1024];
+    bool found = false;
+    const std::string want = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, fp)) {
+        if (!strstr(line, want.c_str())) continue;
+        int T = 0, W = 0, R = 0;
+        const char* a = strstr(line, "\"t_block\":");
+        const char* b = strstr(line, "\"waves\":");
+        const char* c = strstr(line, "\"rounds\":");
+        if (a && b && c && sscanf(a, "\"t_block\": %d", &T) == 1 && sscanf(b, "\"waves\": %d", &W) == 1 &&
+            sscanf(c, "\"rounds\": %d", &R) == 1) {
+            *s = ig_schedule{IG_SCHED_BLOCKED, T, W, 0, 0, R};
+            found = true;   // the last entry for a key wins
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+void tune_store(const char* path, const std::string& key, const ig_schedule& s, double ms) {
+    FILE* fp = fopen(path, "a");
+    if (!fp) return;
+    fprintf(fp, "{\"key\": \"%s\", \"t_block\": %d, \"waves\": %d, \"rounds\": %d, \"ms\": %.6f}\n", key.c_str(),
+            s.t_block, s.waves, s.rounds, ms);
+    fclose(fp);
+}
+}  // namespace
+
+extern "C" ig_status ig_filter_autotune(ig_filter* f, const void* d_in, void* d_work, void* hip_stream,
+                                        ig_schedule* best, double* best_ms) {
+    if (!f || !d_in || !d_work || !best) return fail(IG_ERR_INVALID_ARG, "NULL argument");
+    if (d_in == d_work) return fail(IG_ERR_INVALID_ARG, "d_work must differ from d_in");
+    DeviceGuard dg(f->device);
+    if (!dg.ok) return fail(IG_ERR_DEVICE, "hipSetDevice(%d) failed", f->device);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, f->device));
+    const std::string key = tune_key(f, prop.gcnArchName);
+    const char* cache = getenv("IG_TUNE_CACHE");
+    ig_schedule s{};
+    if (cache && *cache && tune_lookup(cache, key, &s) && check_schedule(&f->p, &s, f->ncu) == IG_OK) {
+        ig_status st = ig_filter_set_schedule(f, &s);
+        if (st != IG_OK) return st;
+        *best = resolve_schedule(f);
+        if (best_ms) *best_ms = -1.0;
+        return IG_OK;
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best_t = 1e300;
+    ig_schedule best_s{};
+    const int maxT = std::max(1, std::min(4, f->p.n_iter));
+    for (int T = 1; T <= maxT; ++T)
+        for (int W : {8, 12, 16})
+            for (int R : {1, 2}) {
+                ig_schedule c{IG_SCHED_BLOCKED, T, W, 0, 0, R};
+                if (check_schedule(&f->p, &c, f->ncu) != IG_OK) continue;
+                if (ig_filter_set_schedule(f, &c) != IG_OK) continue;
+                ig_status st = ig_filter_run(f, d_in, d_work, hip_stream, nullptr);   // warm-up + plan upload
+                if (st != IG_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
+                float ms = 0.0f;
+                if (hipEventRecord(e0, stream) != hipSuccess) continue;
+                for (int k = 0; k < 2; ++k) (void)ig_filter_run(f, d_in, d_work, hip_stream, nullptr);
+                if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) continue;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+                if (ms / 2 < best_t) { best_t = ms / 2; best_s = c; }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_t >= 1e300) return fail(IG_ERR_UNSUPPORTED, "no blocked schedule serves this shape");
+    ig_status st = ig_filter_set_schedule(f, &best_s);
+    if (st != IG_OK) return st;
+    *best = resolve_schedule(f);
+    if (best_ms) *best_ms = best_t;
+    if (cache && *cache) tune_store(cache, key, best_s, best_t);
+    return IG_OK;
+}
+
 // ------------------------------------------------------------------ utilities
 namespace {
 struct Scratch {

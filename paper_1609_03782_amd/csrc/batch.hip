@@ -567,6 +567,43 @@ extern "C" void ig_batch_cache_clear(void) {
     g_cache.clear();
 }
 
+extern "C" ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
+                                       int32_t* best_t_block, int32_t* best_waves, double* best_ms) {
+    if (!items || count < 1) return fail(IG_ERR_INVALID_ARG, "empty batch");
+    for (int i = 0; i < count; ++i)
+        if (items[i].d_in == items[i].d_out) return fail(IG_ERR_INVALID_ARG, "autotuning needs d_in != d_out");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int maxn = 0;
+    for (int i = 0; i < count; ++i) maxn = std::max(maxn, items[i].p.n_iter);
+    double best = 1e300;
+    int bT = 0, bW = 16;
+    for (int T = 1; T <= std::max(1, std::min(4, maxn)); ++T)
+        for (int W : {8, 16}) {
+            if (W <= 2 * T) continue;
+            if (ig_batch_set_schedule(T, W) != IG_OK) continue;
+            if (ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) != IG_OK) continue;   // build + warm
+            float ms = 0.0f;
+            if (hipEventRecord(e0, s) != hipSuccess) continue;
+            bool ok = true;
+            for (int k = 0; k < 2 && ok; ++k) ok = ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) == IG_OK;
+            if (!ok || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) continue;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+            if (ms / 2 < best) { best = ms / 2; bT = T; bW = W; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best >= 1e300) return fail(IG_ERR_UNSUPPORTED, "no batch schedule ran");
+    ig_status st = ig_batch_set_schedule(bT, bW);
+    if (st != IG_OK) return st;
+    if (best_t_block) *best_t_block = bT;
+    if (best_waves) *best_waves = bW;
+    if (best_ms) *best_ms = best;
+    return IG_OK;
+}
+
 extern "C" ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves) {
     if (t_block < 0 || t_block > 4 || waves < 1 || waves > 16) return fail(IG_ERR_INVALID_ARG, "bad batch schedule");
     std::lock_guard<std::mutex> lk(g_mu);

@@ -1,0 +1,558 @@
+// Learned surrogate: model state, training step, tiled and residual-checked
+// inference, and the convolution building blocks.  See include/igsurrogate.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "igsurrogate.h"
+#include "internal.h"
+#include "surrogate_kernels.h"
+
+using namespace igs;
+
+#define fail igk_fail
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? IG_ERR_OUT_OF_MEMORY : IG_ERR_DEVICE, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                             \
+    } while (0)
+
+namespace {
+
+constexpr int kZC = 8;   // planes per workgroup of the weight-gradient kernel
+
+struct Dev {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~Dev() { if (p) (void)hipFree(p); }
+    hipError_t ensure(size_t b) {
+        if (b <= bytes && p) return hipSuccess;
+        if (p) {   // queued kernels may still use the old buffer
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
+            p = nullptr;
+            bytes = 0;
+        }
+        hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
+        if (e == hipSuccess) bytes = std::max<size_t>(b, 256);
+        return e;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+dim3 conv_grid(long nx, long ny, long nz) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, nz); }
+dim3 wgrad_grid(long nx, long ny, long nz) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, (nz + kZC - 1) / kZC); }
+long nwg_of(dim3 g) { return (long)g.x * g.y * g.z; }
+
+// forward conv launch (packed weights)
+hipError_t launch_conv(int cin, int cout, int epi, const void* in, const bf16x8* wp, const float* b, void* out,
+                       const void* aux, long nx, long ny, long nz, hipStream_t s) {
+    const dim3 g = conv_grid(nx, ny, nz), blk(256);
+    const int NB = cout > 16 ? 2 : 1;
+    const u16* x = static_cast<const u16*>(in);
+#define L(CIN, NBV, EPIV) hipLaunchKernelGGL((k_conv<CIN, NBV, EPIV>), g, blk, 0, s, x, wp, b, out, aux, (int)nx, (int)ny, (int)nz)
+    if (cin == 1) {
+        if (NB == 2) {
+            if (epi == EPI_RAW) L(1, 2, EPI_RAW); else if (epi == EPI_GELU) L(1, 2, EPI_GELU); else if (epi == EPI_BACK_GELU) L(1, 2, EPI_BACK_GELU); else L(1, 2, EPI_RESID);
+        } else {
+            if (epi == EPI_RAW) L(1, 1, EPI_RAW); else if (epi == EPI_GELU) L(1, 1, EPI_GELU); else if (epi == EPI_BACK_GELU) L(1, 1, EPI_BACK_GELU); else L(1, 1, EPI_RESID);
+        }
+    } else {
+        if (NB == 2) {
+            if (epi == EPI_RAW) L(32, 2, EPI_RAW); else if (epi == EPI_GELU) L(32, 2, EPI_GELU); else if (epi == EPI_BACK_GELU) L(32, 2, EPI_BACK_GELU); else L(32, 2, EPI_RESID);
+        } else {
+            if (epi == EPI_RAW) L(32, 1, EPI_RAW); else if (epi == EPI_GELU) L(32, 1, EPI_GELU); else if (epi == EPI_BACK_GELU) L(32, 1, EPI_BACK_GELU); else L(32, 1, EPI_RESID);
+        }
+    }
+#undef L
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* W, int cin, int cout, int mode, bf16x8* out, hipStream_t s) {
+    const int kin = mode == 0 ? cin : cout, nout = mode == 0 ? cout : cin;
+    const int total = (kin == 1 ? 1 : 27) * ((nout + 15) / 16) * 64;
+    hipLaunchKernelGGL(k_pack, dim3((total + 255) / 256), dim3(256), 0, s, W, cin, cout, mode, out);
+    return hipGetLastError();
+}
+size_t packed_count(int cin, int cout, int mode) {
+    const int kin = mode == 0 ? cin : cout, nout = mode == 0 ? cout : cin;
+    return (size_t)(kin == 1 ? 1 : 27) * ((nout + 15) / 16) * 64;
+}
+
+// weight gradient of a conv with cin (1 or 32) inputs and cout (1 or 32)
+// outputs: per-workgroup partials, then a fixed-order fold into dW [27*cin][COUTP]
+// and db [COUTP] (COUTP = 32, or 16 for one output: column 0 is the gradient)
+hipError_t launch_wgrad(int cin, int cout, const void* a, const void* dz, Dev& part, Dev& partb, float* dW, float* db,
+                        int accumulate, long nx, long ny, long nz, hipStream_t s) {
+    const dim3 g = wgrad_grid(nx, ny, nz);
+    const long nwg = nwg_of(g);
+    const int NB = cout > 16 ? 2 : 1, COUTP = 16 * NB;
+    hipError_t e = part.ensure((size_t)nwg * 27 * cin * COUTP * sizeof(float));
+    if (e == hipSuccess) e = partb.ensure((size_t)nwg * COUTP * sizeof(float));
+    if (e != hipSuccess) return e;
+    const u16* A = static_cast<const u16*>(a);
+    const u16* D = static_cast<const u16*>(dz);
+    if (cin == 32 && NB == 2) hipLaunchKernelGGL((k_wgrad<32, 2, kZC>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz);
+    else if (cin == 32) hipLaunchKernelGGL((k_wgrad<32, 1, kZC>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz);
+    else if (NB == 2) hipLaunchKernelGGL((k_wgrad<1, 2, kZC>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz);
+    else hipLaunchKernelGGL((k_wgrad<1, 1, kZC>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long len = 27L * cin * COUTP;
+    hipLaunchKernelGGL(k_wgrad_fold, dim3((len + 255) / 256), dim3(256), 0, s, part.as<float>(), nwg, len, dW, accumulate);
+    hipLaunchKernelGGL(k_wgrad_fold, dim3(1), dim3(256), 0, s, partb.as<float>(), nwg, (long)COUTP, db, accumulate);
+    return hipGetLastError();
+}
+
+__global__ void k_unpad(const float* __restrict__ src, int rows, int colsp, int cols, float* __restrict__ dst,
+                        int accumulate) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= rows * cols) return;
+    const int r = q / cols, c = q % cols;
+    dst[q] = accumulate ? dst[q] + src[r * colsp + c] : src[r * colsp + c];
+}
+
+__global__ void k_fill(float* __restrict__ p, long n, float v) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// copy the box [o, o + d) of cube x (FP32) into a dense sub-cube
+__global__ void k_gather(const float* __restrict__ x, long nx, long ny, int ox, int oy, int oz, int dx, int dy, int dz,
+                         float* __restrict__ sub) {
+    const long q = (long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (long)dx * dy * dz) return;
+    const int i = q % dx, j = (q / dx) % dy, k = q / ((long)dx * dy);
+    sub[q] = x[((long)(oz + k) * ny + (oy + j)) * nx + (ox + i)];
+}
+// write the inner box [h, h + e) of a sub-cube of dims d to y at origin o
+__global__ void k_scatter(const float* __restrict__ sub, int dx, int dy, int hx, int hy, int hz, int ex, int ey, int ez,
+                          float* __restrict__ y, long nx, long ny, int ox, int oy, int oz) {
+    const long q = (long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (long)ex * ey * ez) return;
+    const int i = q % ex, j = (q / ex) % ey, k = q / ((long)ex * ey);
+    y[((long)(oz + k) * ny + (oy + j)) * nx + (ox + i)] = sub[((long)(hz + k) * dy + (hy + j)) * dx + (hx + i)];
+}
+
+// FP64 sum of (a - b)^2 per workgroup
+__global__ void __launch_bounds__(256) k_diff2(const float* __restrict__ a, const float* __restrict__ b, long n,
+                                                double* __restrict__ part) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+        const double d = (double)a[i] - (double)b[i];
+        s += d * d;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+}  // namespace
+
+// ====================================================================== model
+struct ig_surrogate {
+    ig_surrogate_params p;
+    int device;
+    int L;
+    std::vector<int> cin, cout;
+    std::vector<size_t> w_off, b_off;   // offsets into the parameter vector
+    size_t nparam = 0;
+    Dev params, grads, m, v;            // FP32
+    std::vector<Dev> pk_f, pk_d;        // packed bf16 weights (forward, input gradient)
+    long step = 0;
+    // activations, sized for the largest cube seen
+    long cap = 0;
+    std::vector<Dev> act, pre;          // act[0] 1 channel, act[1..L-1] 32; pre[1..L-1]
+    Dev y, dy, dzA, dzB, part, partb, parts, sub_x, sub_y, tmp;
+};
+
+namespace {
+
+ig_status repack(ig_surrogate* s, hipStream_t st) {
+    for (int l = 0; l < s->L; ++l) {
+        const float* W = s->params.as<float>() + s->w_off[l];
+        HIP_TRY(launch_pack(W, s->cin[l], s->cout[l], 0, s->pk_f[l].as<bf16x8>(), st));
+        HIP_TRY(launch_pack(W, s->cin[l], s->cout[l], 1, s->pk_d[l].as<bf16x8>(), st));
+    }
+    return IG_OK;
+}
+
+ig_status ensure_acts(ig_surrogate* s, long n) {
+    if (n <= s->cap) return IG_OK;
+    s->act.resize(s->L);
+    s->pre.resize(s->L);
+    HIP_TRY(s->act[0].ensure(n * 2));
+    for (int l = 1; l < s->L; ++l) {
+        HIP_TRY(s->act[l].ensure(n * 32 * 2));
+        HIP_TRY(s->pre[l].ensure(n * 32 * 2));
+    }
+    HIP_TRY(s->y.ensure(n * 4));
+    HIP_TRY(s->dy.ensure(n * 2));
+    HIP_TRY(s->dzA.ensure(n * 32 * 2));
+    HIP_TRY(s->dzB.ensure(n * 32 * 2));
+    s->cap = n;
+    return IG_OK;
+}
+
+// forward pass on one cube already converted to act[0]; writes y (FP32)
+ig_status forward(ig_surrogate* s, const float* x, float* y, long nx, long ny, long nz, bool keep_pre, hipStream_t st) {
+    const float* P = s->params.as<float>();
+    for (int l = 0; l < s->L; ++l) {
+        const float* b = P + s->b_off[l];
+        if (l < s->L - 1) {
+            HIP_TRY(launch_conv(s->cin[l], s->cout[l], EPI_GELU, s->act[l].p, s->pk_f[l].as<bf16x8>(), b,
+                                s->act[l + 1].p, keep_pre ? s->pre[l + 1].p : nullptr, nx, ny, nz, st));
+        } else {
+            HIP_TRY(launch_conv(s->cin[l], s->cout[l], EPI_RESID, s->act[l].p, s->pk_f[l].as<bf16x8>(), b, y, x,
+                                nx, ny, nz, st));
+        }
+    }
+    return IG_OK;
+}
+
+ig_status to_bf16(const float* x, void* a, long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_bf16, dim3((n + 255) / 256), dim3(256), 0, st, x, static_cast<u16*>(a), n);
+    HIP_TRY(hipGetLastError());
+    return IG_OK;
+}
+
+}  // namespace
+
+extern "C" ig_status ig_surrogate_create(const ig_surrogate_params* p, int device, ig_surrogate** out) {
+    if (!out) return fail(IG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || p->struct_size != sizeof(ig_surrogate_params)) return fail(IG_ERR_INVALID_ARG, "bad params/struct_size");
+    if (p->depth < 2 || p->depth > 64 || p->width != 32 || p->reserved != 0)
+        return fail(IG_ERR_INVALID_ARG, "depth must be 2..64 and width 32");
+    if (!(p->lr > 0) || !(p->beta1 >= 0 && p->beta1 < 1) || !(p->beta2 >= 0 && p->beta2 < 1) || !(p->eps > 0))
+        return fail(IG_ERR_INVALID_ARG, "bad Adam parameters");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(IG_ERR_DEVICE, "bad device %d", device);
+    if (hipSetDevice(device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    auto* s = new ig_surrogate();
+    s->p = *p;
+    s->device = device;
+    s->L = p->depth;
+    for (int l = 0; l < s->L; ++l) {
+        s->cin.push_back(l == 0 ? 1 : 32);
+        s->cout.push_back(l == s->L - 1 ? 1 : 32);
+        s->w_off.push_back(s->nparam);
+        s->nparam += 27 * s->cin[l] * s->cout[l];
+        s->b_off.push_back(s->nparam);
+        s->nparam += s->cout[l];
+    }
+    // initial weights: He normal, last layer zero (identity network)
+    std::vector<float> h(s->nparam, 0.0f);
+    std::mt19937_64 rng(p->seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int l = 0; l < s->L - 1; ++l) {
+        const double sd = std::sqrt(2.0 / (27.0 * s->cin[l]));
+        for (size_t k = 0; k < (size_t)27 * s->cin[l] * s->cout[l]; ++k) h[s->w_off[l] + k] = (float)(nd(rng) * sd);
+    }
+    hipError_t e = s->params.ensure(s->nparam * 4);
+    if (e == hipSuccess) e = s->grads.ensure(s->nparam * 4);
+    if (e == hipSuccess) e = s->m.ensure(s->nparam * 4);
+    if (e == hipSuccess) e = s->v.ensure(s->nparam * 4);
+    s->pk_f.resize(s->L);
+    s->pk_d.resize(s->L);
+    for (int l = 0; l < s->L && e == hipSuccess; ++l) {
+        e = s->pk_f[l].ensure(packed_count(s->cin[l], s->cout[l], 0) * 16);
+        if (e == hipSuccess) e = s->pk_d[l].ensure(packed_count(s->cin[l], s->cout[l], 1) * 16);
+    }
+    if (e == hipSuccess) e = s->parts.ensure(1024 * sizeof(double));
+    if (e != hipSuccess) { delete s; return fail(IG_ERR_OUT_OF_MEMORY, "surrogate allocation"); }
+    *out = s;
+    ig_status st = ig_surrogate_set_weights(s, h.data(), (int64_t)h.size());
+    if (st != IG_OK) { delete s; *out = nullptr; return st; }
+    return IG_OK;
+}
+
+extern "C" void ig_surrogate_destroy(ig_surrogate* s) { delete s; }
+
+extern "C" int64_t ig_surrogate_param_count(const ig_surrogate* s) { return s ? (int64_t)s->nparam : 0; }
+
+extern "C" ig_status ig_surrogate_set_weights(ig_surrogate* s, const float* host, int64_t count) {
+    if (!s || !host || count != (int64_t)s->nparam) return fail(IG_ERR_INVALID_ARG, "bad weights");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    HIP_TRY(hipMemcpy(s->params.p, host, s->nparam * 4, hipMemcpyHostToDevice));
+    const long n = (long)s->nparam;
+    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, 0, s->m.as<float>(), n, 0.0f);
+    hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, 0, s->v.as<float>(), n, 0.0f);
+    HIP_TRY(hipGetLastError());
+    s->step = 0;
+    ig_status st = repack(s, 0);
+    if (st != IG_OK) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_get_weights(const ig_surrogate* s, float* host, int64_t count) {
+    if (!s || !host || count != (int64_t)s->nparam) return fail(IG_ERR_INVALID_ARG, "bad weights");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(host, s->params.p, s->nparam * 4, hipMemcpyDeviceToHost));
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_get_grads(const ig_surrogate* s, float* host, int64_t count) {
+    if (!s || !host || count != (int64_t)s->nparam) return fail(IG_ERR_INVALID_ARG, "bad gradient buffer");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(host, s->grads.p, s->nparam * 4, hipMemcpyDeviceToHost));
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_train_step(ig_surrogate* s, const float* const* d_x, const float* const* d_t,
+                                             int32_t batch, int64_t nx, int64_t ny, int64_t nz, void* hip_stream,
+                                             double* loss) {
+    if (!s || !d_x || !d_t || batch < 1 || nx < 1 || ny < 1 || nz < 1) return fail(IG_ERR_INVALID_ARG, "bad arguments");
+    if (nx * ny * nz >= (1LL << 31) / 32) return fail(IG_ERR_INVALID_ARG, "cube too large for training");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const long n = nx * ny * nz;
+    ig_status rc = ensure_acts(s, n);
+    if (rc != IG_OK) return rc;
+    {   // weight-gradient partials for the largest layer, sized before any launch
+        const long nwg = nwg_of(wgrad_grid(nx, ny, nz));
+        HIP_TRY(s->part.ensure((size_t)nwg * 27 * 32 * 32 * sizeof(float)));
+        HIP_TRY(s->partb.ensure((size_t)nwg * 32 * sizeof(float)));
+    }
+    const long np = (long)s->nparam;
+    hipLaunchKernelGGL(k_fill, dim3((np + 255) / 256), dim3(256), 0, st, s->grads.as<float>(), np, 0.0f);
+    HIP_TRY(hipGetLastError());
+    const int nloss = 256;
+    HIP_TRY(s->tmp.ensure((size_t)batch * nloss * sizeof(double) + 64 * 1024 * 4));
+    double* lparts = s->tmp.as<double>();
+    float* padbuf = reinterpret_cast<float*>(lparts + (size_t)batch * nloss);   // [27*32][16] for 1-output layers
+    const double scale = 1.0 / ((double)n * batch);
+    for (int k = 0; k < batch; ++k) {
+        if (!d_x[k] || !d_t[k]) return fail(IG_ERR_INVALID_ARG, "NULL cube %d", k);
+        rc = to_bf16(d_x[k], s->act[0].p, n, st);
+        if (rc != IG_OK) return rc;
+        rc = forward(s, d_x[k], s->y.as<float>(), nx, ny, nz, true, st);
+        if (rc != IG_OK) return rc;
+        hipLaunchKernelGGL(k_mse, dim3(nloss), dim3(256), 0, st, s->y.as<float>(), d_t[k], n, scale,
+                           s->dy.as<u16>(), lparts + (size_t)k * nloss);
+        HIP_TRY(hipGetLastError());
+        // backward: dz of layer l lives in `g` (1 channel for the last layer)
+        const void* g = s->dy.p;
+        for (int l = s->L - 1; l >= 0; --l) {
+            float* dW = s->grads.as<float>() + s->w_off[l];
+            float* db = s->grads.as<float>() + s->b_off[l];
+            if (s->cout[l] == 32) {
+                HIP_TRY(launch_wgrad(s->cin[l], 32, s->act[l].p, g, s->part, s->partb, dW, db, 1, nx, ny, nz, st));
+            } else {   // 1 output channel: fold into a 16-column buffer, then keep column 0
+                HIP_TRY(launch_wgrad(s->cin[l], 1, s->act[l].p, g, s->part, s->partb, padbuf, padbuf + 27 * 32 * 16, 0,
+                                     nx, ny, nz, st));
+                const int rows = 27 * s->cin[l];
+                hipLaunchKernelGGL(k_unpad, dim3((rows + 255) / 256), dim3(256), 0, st, padbuf, rows, 16, 1, dW, 1);
+                hipLaunchKernelGGL(k_unpad, dim3(1), dim3(256), 0, st, padbuf + 27 * 32 * 16, 1, 16, 1, db, 1);
+                HIP_TRY(hipGetLastError());
+            }
+            if (l > 0) {   // gradient of the layer's input, through gelu' of the layer below
+                void* dst = (g == s->dzA.p) ? s->dzB.p : s->dzA.p;
+                HIP_TRY(launch_conv(s->cout[l], s->cin[l], EPI_BACK_GELU, g, s->pk_d[l].as<bf16x8>(), nullptr, dst,
+                                    s->pre[l].p, nx, ny, nz, st));
+                g = dst;
+            }
+        }
+    }
+    // Adam
+    ++s->step;
+    const float b1 = s->p.beta1, b2 = s->p.beta2;
+    const float bc1 = 1.0f - std::pow(b1, (float)s->step), bc2 = 1.0f - std::pow(b2, (float)s->step);
+    hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, st, s->params.as<float>(), s->grads.as<float>(),
+                       s->m.as<float>(), s->v.as<float>(), np, s->p.lr, b1, b2, s->p.eps, bc1, bc2, 1.0f);
+    HIP_TRY(hipGetLastError());
+    rc = repack(s, st);
+    if (rc != IG_OK) return rc;
+    if (loss) {
+        std::vector<double> h((size_t)batch * nloss);
+        HIP_TRY(hipMemcpyAsync(h.data(), lparts, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double tot = 0.0;
+        for (double v : h) tot += v;
+        *loss = tot / ((double)n * batch);
+    }
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float* d_y, int64_t nx, int64_t ny,
+                                        int64_t nz, int32_t tile, void* hip_stream) {
+    if (!s || !d_x || !d_y || nx < 1 || ny < 1 || nz < 1 || tile < 0) return fail(IG_ERR_INVALID_ARG, "bad arguments");
+    if (d_x == d_y) return fail(IG_ERR_INVALID_ARG, "in-place inference is not supported");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const long n = nx * ny * nz;
+    if (tile == 0 || (tile >= nx && tile >= ny && tile >= nz)) {
+        if (n >= (1LL << 31) / 32) return fail(IG_ERR_INVALID_ARG, "cube too large for one piece; use tiles");
+        ig_status rc = ensure_acts(s, n);
+        if (rc != IG_OK) return rc;
+        rc = to_bf16(d_x, s->act[0].p, n, st);
+        if (rc != IG_OK) return rc;
+        return forward(s, d_x, d_y, nx, ny, nz, false, st);
+    }
+    const int H = s->L;   // receptive radius
+    const long dmax = (long)tile + 2 * H;
+    ig_status rc = ensure_acts(s, dmax * dmax * dmax);
+    if (rc != IG_OK) return rc;
+    HIP_TRY(s->sub_x.ensure(dmax * dmax * dmax * 4));
+    HIP_TRY(s->sub_y.ensure(dmax * dmax * dmax * 4));
+    for (long oz = 0; oz < nz; oz += tile)
+        for (long oy = 0; oy < ny; oy += tile)
+            for (long ox = 0; ox < nx; ox += tile) {
+                const long ex = std::min<long>(tile, nx - ox), ey = std::min<long>(tile, ny - oy), ez = std::min<long>(tile, nz - oz);
+                const long bx = std::max<long>(0, ox - H), by = std::max<long>(0, oy - H), bz = std::max<long>(0, oz - H);
+                const long dx = std::min<long>(nx, ox + ex + H) - bx, dy = std::min<long>(ny, oy + ey + H) - by,
+                           dz = std::min<long>(nz, oz + ez + H) - bz;
+                const long m = dx * dy * dz;
+                hipLaunchKernelGGL(k_gather, dim3((m + 255) / 256), dim3(256), 0, st, d_x, nx, ny, (int)bx, (int)by,
+                                   (int)bz, (int)dx, (int)dy, (int)dz, s->sub_x.as<float>());
+                HIP_TRY(hipGetLastError());
+                rc = to_bf16(s->sub_x.as<float>(), s->act[0].p, m, st);
+                if (rc != IG_OK) return rc;
+                rc = forward(s, s->sub_x.as<float>(), s->sub_y.as<float>(), dx, dy, dz, false, st);
+                if (rc != IG_OK) return rc;
+                const long e = ex * ey * ez;
+                hipLaunchKernelGGL(k_scatter, dim3((e + 255) / 256), dim3(256), 0, st, s->sub_y.as<float>(), (int)dx,
+                                   (int)dy, (int)(ox - bx), (int)(oy - by), (int)(oz - bz), (int)ex, (int)ey, (int)ez,
+                                   d_y, nx, ny, (int)ox, (int)oy, (int)oz);
+                HIP_TRY(hipGetLastError());
+            }
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_infer_checked(ig_surrogate* s, const ig_params* p, const float* d_x, float* d_y,
+                                                int32_t tile, double slope, double threshold, void* hip_stream,
+                                                ig_surrogate_report* rep) {
+    if (!s || !p || !rep) return fail(IG_ERR_INVALID_ARG, "bad arguments");
+    ig_status rc = igk_validate_params(p);
+    if (rc != IG_OK) return rc;
+    if (p->dtype != IG_F32) return fail(IG_ERR_INVALID_ARG, "FP32 cubes only");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const long n = (long)(p->nx * p->ny * p->nz);
+    rc = ig_surrogate_infer(s, d_x, d_y, p->nx, p->ny, p->nz, tile, hip_stream);
+    if (rc != IG_OK) return rc;
+    // rho of x (the check uses the input's noise level)
+    double sum = 0, sumsq = 0;
+    int64_t bad = 0;
+    rc = ig_reduce(d_x, IG_F32, n, s->device, hip_stream, &sum, &sumsq, &bad);
+    if (rc != IG_OK) return rc;
+    if (bad) return fail(IG_ERR_NONFINITE, "input holds non-finite voxels");
+    const double rho = p->rms > 0 ? p->rms : std::sqrt(sumsq / (double)n);
+    // two plain steps of the prediction
+    ig_params q = *p;
+    q.n_iter = 2;
+    q.rms = rho > 0 ? rho : 1.0;
+    ig_filter* f2 = nullptr;
+    rc = ig_filter_create(&q, s->device, &f2);
+    if (rc != IG_OK) return rc;
+    HIP_TRY(s->tmp.ensure((size_t)n * 4 + 1024 * sizeof(double)));
+    float* phi = s->tmp.as<float>();
+    double* dparts = reinterpret_cast<double*>(phi + n);
+    rc = ig_filter_run(f2, d_y, phi, hip_stream, nullptr);
+    if (rc == IG_OK) {
+        const hipError_t se = hipStreamSynchronize(st);   // the handle's buffers are in use until then
+        if (se != hipSuccess) rc = fail(IG_ERR_DEVICE, "sync: %s", hipGetErrorString(se));
+    }
+    ig_filter_destroy(f2);
+    if (rc != IG_OK) return rc;
+    hipLaunchKernelGGL(k_diff2, dim3(1024), dim3(256), 0, st, phi, d_y, n, dparts);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> h(1024);
+    HIP_TRY(hipMemcpyAsync(h.data(), dparts, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double tot = 0;
+    for (double v : h) tot += v;
+    rep->rho = rho;
+    rep->residual = std::sqrt(tot / (double)n) / (rho > 0 ? rho : 1.0);
+    rep->predicted_rmse = slope * rep->residual;
+    rep->fell_back = 0;
+    rep->reserved = 0;
+    if (!(rep->predicted_rmse <= threshold)) {
+        ig_filter* f = nullptr;
+        rc = ig_filter_create(p, s->device, &f);
+        if (rc != IG_OK) return rc;
+        rc = ig_filter_run(f, d_x, d_y, hip_stream, nullptr);
+        if (rc == IG_OK) {
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        ig_filter_destroy(f);
+        if (rc != IG_OK) return rc;
+        rep->fell_back = 1;
+    }
+    return IG_OK;
+}
+
+// ------------------------------------------------------------ building blocks
+extern "C" ig_status ig_conv3d_forward(const void* d_in, int32_t c_in, const float* d_w, const float* d_b, int32_t c_out,
+                                       int32_t epilogue, void* d_aux, void* d_out, int64_t nx, int64_t ny, int64_t nz,
+                                       void* hip_stream) {
+    if (!d_in || !d_w || !d_out || !(c_in == 1 || c_in == 32) || c_out < 1 || c_out > 32)
+        return fail(IG_ERR_INVALID_ARG, "bad conv arguments");
+    if (!(epilogue == EPI_RAW || epilogue == EPI_GELU || epilogue == EPI_RESID)) return fail(IG_ERR_INVALID_ARG, "bad epilogue");
+    if (epilogue == EPI_GELU && c_out != 32) return fail(IG_ERR_INVALID_ARG, "gelu epilogue needs 32 outputs");
+    if (epilogue == EPI_RESID && (c_out != 1 || !d_aux || !d_b)) return fail(IG_ERR_INVALID_ARG, "residual epilogue");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(IG_ERR_INVALID_ARG, "bad shape");
+    hipStream_t st = (hipStream_t)hip_stream;
+    Dev pk, bias;
+    HIP_TRY(pk.ensure(packed_count(c_in, c_out, 0) * 16));
+    HIP_TRY(bias.ensure(32 * 4));
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, st, bias.as<float>(), 32, 0.0f);
+    if (d_b) HIP_TRY(hipMemcpyAsync(bias.p, d_b, c_out * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_pack(d_w, c_in, c_out, 0, pk.as<bf16x8>(), st));
+    HIP_TRY(launch_conv(c_in, c_out, epilogue, d_in, pk.as<bf16x8>(), bias.as<float>(), d_out, d_aux, nx, ny, nz, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return IG_OK;
+}
+
+extern "C" ig_status ig_conv3d_input_grad(const void* d_dz, int32_t c_out, const float* d_w, int32_t c_in,
+                                          const void* d_aux, void* d_out, int64_t nx, int64_t ny, int64_t nz,
+                                          void* hip_stream) {
+    if (!d_dz || !d_w || !d_out || !(c_out == 1 || c_out == 32) || c_in < 1 || c_in > 32)
+        return fail(IG_ERR_INVALID_ARG, "bad conv arguments");
+    if (d_aux && c_in != 32) return fail(IG_ERR_INVALID_ARG, "gelu' epilogue needs 32 inputs");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(IG_ERR_INVALID_ARG, "bad shape");
+    hipStream_t st = (hipStream_t)hip_stream;
+    Dev pk;
+    HIP_TRY(pk.ensure(packed_count(c_in, c_out, 1) * 16));
+    HIP_TRY(launch_pack(d_w, c_in, c_out, 1, pk.as<bf16x8>(), st));
+    HIP_TRY(launch_conv(c_out, c_in, d_aux ? EPI_BACK_GELU : EPI_RAW, d_dz, pk.as<bf16x8>(), nullptr, d_out, d_aux, nx,
+                        ny, nz, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return IG_OK;
+}
+
+extern "C" ig_status ig_conv3d_weight_grad(const void* d_a, int32_t c_in, const void* d_dz, int32_t c_out, float* d_dw,
+                                           float* d_db, int64_t nx, int64_t ny, int64_t nz, void* hip_stream) {
+    if (!d_a || !d_dz || !d_dw || !d_db || !(c_in == 1 || c_in == 32) || !(c_out == 1 || c_out == 32))
+        return fail(IG_ERR_INVALID_ARG, "bad conv arguments");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(IG_ERR_INVALID_ARG, "bad shape");
+    hipStream_t st = (hipStream_t)hip_stream;
+    Dev part, partb, pad;
+    if (c_out == 32) {
+        HIP_TRY(launch_wgrad(c_in, 32, d_a, d_dz, part, partb, d_dw, d_db, 0, nx, ny, nz, st));
+    } else {
+        HIP_TRY(pad.ensure((27 * 32 * 16 + 16) * 4));
+        float* pw = pad.as<float>();
+        HIP_TRY(launch_wgrad(c_in, 1, d_a, d_dz, part, partb, pw, pw + 27 * 32 * 16, 0, nx, ny, nz, st));
+        const int rows = 27 * c_in;
+        hipLaunchKernelGGL(k_unpad, dim3((rows + 255) / 256), dim3(256), 0, st, pw, rows, 16, 1, d_dw, 0);
+        hipLaunchKernelGGL(k_unpad, dim3(1), dim3(256), 0, st, pw + 27 * 32 * 16, 1, 16, 1, d_db, 0);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return IG_OK;
+}

@@ -1,0 +1,217 @@
+"""GPU checks of the surrogate's HIP kernels against the FP64 oracle.
+
+Inputs and weights are rounded to bfloat16 before both sides see them, so a
+bf16 x bf16 product is exact in FP32 and the remaining difference is FP32
+accumulation order: raw convolution outputs must agree to 1e-5 of the
+largest |term| sum.  Outputs stored as bf16 are allowed one bf16 rounding
+step (relative 2^-8).
+"""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1609_03782_amd as ig
+    ig.lib()
+    return torch.device("cuda:0")
+
+
+def _bf(a):
+    """Round to bfloat16 (torch RNE) and return (fp64 numpy, torch bf16 cpu)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16)
+    return t.to(torch.float64).numpy(), t
+
+
+def _scale(a, W):
+    # sum over taps and channels of |a| |W|: bound on each output's magnitude
+    return float(S.conv3d(np.abs(a), np.abs(W)).max()) + 1e-30
+
+
+SHAPES = [(5, 6, 40), (3, 9, 33), (7, 4, 70)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("cin,cout", [(32, 32), (1, 32), (32, 1)])
+def test_conv_forward_raw(dev, shape, cin, cout):
+    import torch
+    from paper_1609_03782_amd import surrogate as sg
+    rng = np.random.default_rng(hash((shape, cin, cout)) % 2**32)
+    a, ta = _bf(rng.standard_normal(shape + (cin,)))
+    W, _ = _bf(rng.standard_normal((27, cin, cout)) * 0.2)
+    b = rng.standard_normal(cout).astype(np.float32)
+    out = sg.conv3d_forward(ta.to(dev), cin, torch.from_numpy(W.astype(np.float32)).to(dev),
+                            torch.from_numpy(b).to(dev), cout, epilogue=0)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[..., :cout].astype(np.float64)
+    ref = S.conv3d(a, W, b.astype(np.float64))
+    assert np.abs(got - ref).max() <= 1e-5 * _scale(a, W)
+
+
+def test_conv_forward_gelu_and_residual(dev):
+    import torch
+    from paper_1609_03782_amd import surrogate as sg
+    rng = np.random.default_rng(7)
+    shape = (4, 8, 37)
+    a, ta = _bf(rng.standard_normal(shape + (32,)))
+    W, _ = _bf(rng.standard_normal((27, 32, 32)) * 0.1)
+    b = rng.standard_normal(32).astype(np.float32) * 0.1
+    pre = torch.empty(shape + (32,), dtype=torch.bfloat16, device=dev)
+    out = sg.conv3d_forward(ta.to(dev), 32, torch.from_numpy(W.astype(np.float32)).to(dev),
+                            torch.from_numpy(b).to(dev), 32, epilogue=1, aux=pre)
+    torch.cuda.synchronize()
+    z = S.conv3d(a, W, b.astype(np.float64))
+    np.testing.assert_allclose(pre.float().cpu().numpy(), z, rtol=2 ** -7, atol=1e-5 * _scale(a, W))
+    np.testing.assert_allclose(out.float().cpu().numpy(), S.gelu(z), rtol=2 ** -7, atol=2e-5 * _scale(a, W))
+    # residual epilogue: y = x + conv(a) + b with one output channel
+    W1, _ = _bf(rng.standard_normal((27, 32, 1)) * 0.1)
+    x = rng.standard_normal(shape).astype(np.float32)
+    y = sg.conv3d_forward(ta.to(dev), 32, torch.from_numpy(W1.astype(np.float32)).to(dev),
+                          torch.from_numpy(b[:1].copy()).to(dev), 1, epilogue=3, aux=torch.from_numpy(x).to(dev))
+    torch.cuda.synchronize()
+    ref = x + S.conv3d(a, W1, b[:1].astype(np.float64))[..., 0]
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-5 * _scale(a, W1)
+
+
+@pytest.mark.parametrize("cin,cout", [(32, 32), (32, 1)])
+def test_conv_input_grad(dev, cin, cout):
+    import torch
+    from paper_1609_03782_amd import surrogate as sg
+    rng = np.random.default_rng(cin + cout)
+    shape = (5, 7, 45)
+    dz, tdz = _bf(rng.standard_normal(shape + (cout,)))
+    W, _ = _bf(rng.standard_normal((27, cin, cout)) * 0.2)
+    got = sg.conv3d_input_grad(tdz.to(dev), cout, torch.from_numpy(W.astype(np.float32)).to(dev), cin)
+    torch.cuda.synchronize()
+    ref = S.conv3d_input_grad(dz, W)
+    scale = float(S.conv3d_input_grad(np.abs(dz), np.abs(W)).max())
+    assert np.abs(got.cpu().numpy()[..., :cin] - ref).max() <= 1e-5 * scale
+    # with the gelu' epilogue of the layer below
+    if cin == 32:
+        z, tz = _bf(rng.standard_normal(shape + (32,)))
+        got2 = sg.conv3d_input_grad(tdz.to(dev), cout, torch.from_numpy(W.astype(np.float32)).to(dev), cin,
+                                    aux=tz.to(dev))
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(got2.float().cpu().numpy(), ref * S.gelu_grad(z), rtol=2 ** -7,
+                                   atol=2e-5 * scale)
+
+
+@pytest.mark.parametrize("cin,cout", [(32, 32), (1, 32), (32, 1)])
+def test_conv_weight_grad(dev, cin, cout):
+    import torch
+    from paper_1609_03782_amd import surrogate as sg
+    rng = np.random.default_rng(100 + cin + cout)
+    shape = (11, 6, 39)          # 11 planes: two z-chunks of the split-K
+    a, ta = _bf(rng.standard_normal(shape + (cin,)))
+    dz, tdz = _bf(rng.standard_normal(shape + (cout,)))
+    dW, db = sg.conv3d_weight_grad(ta.to(dev), cin, tdz.to(dev), cout)
+    torch.cuda.synchronize()
+    rW, rb = S.conv3d_weight_grad(a, dz)
+    sW, _ = S.conv3d_weight_grad(np.abs(a), np.abs(dz))
+    assert np.abs(dW.cpu().numpy() - rW).max() <= 1e-5 * float(sW.max())
+    assert np.abs(db.cpu().numpy() - rb).max() <= 1e-5 * float(np.abs(dz).sum(axis=(0, 1, 2)).max())
+
+
+def _net(depth=4, seed=3):
+    rng = np.random.default_rng(seed)
+    Ws, bs = S.init_params(rng, widths=(1,) + (32,) * (depth - 1) + (1,))
+    Ws[-1] = rng.standard_normal(Ws[-1].shape) * 0.05
+    bs = [rng.standard_normal(b.shape) * 0.05 for b in bs]
+    Ws = [_bf(W)[0] for W in Ws]
+    return Ws, bs
+
+
+def _bf_forward(x, Ws, bs):
+    """Oracle forward with the GPU's rounding points: bf16 input and
+    activations, FP64 arithmetic, FP32 output."""
+    a = _bf(x[..., None])[0]
+    for l in range(len(Ws) - 1):
+        a = _bf(S.gelu(S.conv3d(a, Ws[l], bs[l])))[0]
+    return x.astype(np.float64) + S.conv3d(a, Ws[-1], bs[-1])[..., 0]
+
+
+def test_network_forward_and_tiling(dev):
+    import torch
+    from paper_1609_03782_amd import surrogate as sg
+    depth = 4
+    Ws, bs = _net(depth)
+    net = sg.Surrogate(depth=depth, seed=1)
+    net.set_weights(sg.join_params([W.astype(np.float32) for W in Ws], [b.astype(np.float32) for b in bs]))
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal((19, 21, 40)) * 2).astype(np.float32)
+    tx = torch.from_numpy(x).to(dev)
+    y = net.infer(tx)
+    yt = net.infer(tx, tile=8)
+    torch.cuda.synchronize()
+    assert torch.equal(y, yt)                    # halo of `depth` voxels makes tiles exact
+    ref = _bf_forward(x, Ws, bs)
+    err = np.abs(y.cpu().numpy() - ref)
+    assert np.sqrt((err ** 2).mean()) <= 2e-3 * np.abs(ref - x).max()
+    assert err.max() <= 2e-2 * np.abs(ref - x).max()
+
+
+def test_training_gradient_matches_oracle(dev):
+    import torch
+    from paper_1609_03782_amd import surrogate as sg
+    depth = 3
+    Ws, bs = _net(depth, seed=4)
+    net = sg.Surrogate(depth=depth, seed=2, lr=1e-12)
+    net.set_weights(sg.join_params([W.astype(np.float32) for W in Ws], [b.astype(np.float32) for b in bs]))
+    rng = np.random.default_rng(11)
+    x = _bf(rng.standard_normal((8, 10, 33)))[0].astype(np.float32)
+    t = (x + 0.5 * rng.standard_normal(x.shape)).astype(np.float32)
+    loss = net.train_step([torch.from_numpy(x).to(dev)], [torch.from_numpy(t).to(dev)])
+    g = net.get_grads()
+    rl, rW, rb, _ = S.loss_and_grads(x.astype(np.float64), t.astype(np.float64), Ws, bs)
+    assert loss == pytest.approx(rl, rel=1e-2)
+    gW, gb = sg.split_params(g, depth)
+    for l in range(depth):
+        denom = np.abs(rW[l]).max() + 1e-30
+        assert np.abs(gW[l] - rW[l]).max() <= 3e-2 * denom, l
+        assert np.abs(gb[l] - rb[l]).max() <= 3e-2 * (np.abs(rb[l]).max() + 1e-12), l
+
+
+def test_training_lowers_the_loss(dev):
+    import torch
+    import paper_1609_03782_amd as ig
+    from paper_1609_03782_amd import surrogate as sg
+    import igsynth
+    xs, ts = [], []
+    for k in range(4):
+        c = igsynth.batch_cube(igsynth.BatchItem((24, 24, 24), 2.0, 20, 500 + k))
+        x = torch.from_numpy(c).to(dev)
+        xs.append(x)
+        ts.append(ig.Filter(c.shape, K=2.0, tau=1 / 16, n_iter=20).run(x))
+    torch.cuda.synchronize()
+    net = sg.Surrogate(depth=4, seed=5, lr=2e-3)
+    first = net.train_step(xs, ts)
+    for _ in range(40):
+        last = net.train_step(xs, ts)
+    assert last < 0.5 * first, (first, last)
+
+
+def test_checked_inference_and_fallback(dev):
+    import torch
+    import paper_1609_03782_amd as ig
+    from paper_1609_03782_amd import surrogate as sg
+    import igsynth
+    c = igsynth.random_cube((20, 24, 28), seed=3)
+    x = torch.from_numpy(c).to(dev)
+    params = dict(K=2.0, tau=1 / 16, n_iter=12, cond="pm_exp")
+    net = sg.Surrogate(depth=4, seed=6)          # untrained: y = x
+    y, rep = net.infer_checked(x, params, slope=1.0, threshold=0.0)
+    plain = ig.Filter(c.shape, **params).run(x)
+    torch.cuda.synchronize()
+    assert rep["fell_back"] and torch.equal(y, plain)
+    y2, rep2 = net.infer_checked(x, params, slope=1.0, threshold=1e9)
+    torch.cuda.synchronize()
+    assert not rep2["fell_back"] and torch.equal(y2, x)
+    assert rep2["residual"] > 0
