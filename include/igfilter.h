@@ -156,6 +156,15 @@ ig_status ig_filter_autotune(ig_filter* f, const void* d_in, void* d_work, void*
 ig_status ig_filter_set_timing(ig_filter* f, int enable);
 ig_status ig_filter_get_timing(ig_filter* f, double* total_ms, int64_t* launches, int reset);
 
+/* Host-only: the work split of one pass of depth t_block under schedule s
+ * (BLOCKED) on a GPU with ncu compute units.  geom[8] receives
+ * {ntx, nty, ox, oy, waves, vec_io, V, pieces}; if pieces != NULL, up to cap
+ * pieces as {tile_x, tile_y, z0, z1} (outputs in planes [z0, z1) of tile
+ * (tile_x, tile_y), whose outputs are columns [tile_x*ox, +ox) and rows
+ * [tile_y*oy, +oy), clipped to the cube).  *count receives the number. */
+ig_status ig_schedule_plan(const ig_params* p, const ig_schedule* s, int32_t t_block, int32_t ncu,
+                           int32_t* geom, int32_t* pieces, int64_t cap, int64_t* count);
+
 /* Release the handle and its device memory (NULL is a no-op). */
 void ig_filter_destroy(ig_filter* f);
 

@@ -62,6 +62,9 @@ SIGNATURES = {
     "ig_filter_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "ig_filter_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                             ctypes.c_int]),
+    "ig_schedule_plan": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSchedule), ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "ig_schedule_check": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSchedule)]),
     "ig_filter_batch": (ctypes.c_int, [ctypes.POINTER(IgBatchItem), ctypes.c_int32, ctypes.c_int, _P,
                                        ctypes.POINTER(IgStats), ctypes.POINTER(ctypes.c_double)]),
@@ -133,6 +136,24 @@ def schedule_check(shape, sched: dict, **params) -> str | None:
                    sched.get("zchunk", 0), sched.get("vec", 0), sched.get("rounds", 0))
     rc = lib().ig_schedule_check(ctypes.byref(p), ctypes.byref(s))
     return None if rc == IG_OK else lib().ig_last_error().decode()
+
+
+def schedule_plan(shape, sched: dict, t_block: int, ncu: int = 256, **params):
+    """Host-only work split of one pass: (geometry dict, pieces array (k, 4))."""
+    import numpy as np
+    p = make_params(shape, **params)
+    s = IgSchedule(SCHED[sched.get("kind", "blocked")], sched.get("t_block", 2), sched.get("waves", 16),
+                   sched.get("zchunk", 0), sched.get("vec", 0), sched.get("rounds", 0))
+    geom = (ctypes.c_int32 * 8)()
+    cnt = ctypes.c_int64()
+    _check(lib().ig_schedule_plan(ctypes.byref(p), ctypes.byref(s), t_block, ncu, geom, None, 0,
+                                  ctypes.byref(cnt)), "ig_schedule_plan")
+    arr = np.zeros((cnt.value, 4), np.int32)
+    _check(lib().ig_schedule_plan(ctypes.byref(p), ctypes.byref(s), t_block, ncu, geom,
+                                  arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cnt.value,
+                                  ctypes.byref(cnt)), "ig_schedule_plan")
+    keys = ["ntx", "nty", "ox", "oy", "waves", "vec_io", "V", "pieces"]
+    return dict(zip(keys, list(geom))), arr
 
 
 def _torch_dtype_name(t):

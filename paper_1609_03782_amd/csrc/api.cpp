@@ -357,6 +357,28 @@ extern "C" ig_status ig_schedule_check(const ig_params* p, const ig_schedule* s)
     return check_schedule(p, s, 256);
 }
 
+extern "C" ig_status ig_schedule_plan(const ig_params* p, const ig_schedule* s, int32_t t_block, int32_t ncu,
+                                      int32_t* geom, int32_t* pieces, int64_t cap, int64_t* count) {
+    ig_status st = igk_validate_params(p);
+    if (st != IG_OK) return st;
+    if (!s || !geom || !count || ncu < 1) return fail(IG_ERR_INVALID_ARG, "bad argument");
+    if (s->kind != IG_SCHED_BLOCKED) return fail(IG_ERR_INVALID_ARG, "only BLOCKED schedules have a work split");
+    PassPlan pp;
+    const char* why = plan_pass(*p, *s, t_block, ncu, &pp);
+    if (why) return fail(IG_ERR_INVALID_ARG, "%s", why);
+    const int32_t g[8] = {pp.g.ntx, pp.g.nty, pp.g.ox, pp.g.oy, pp.g.W, pp.g.vec, pp.V, (int32_t)pp.pieces.size()};
+    for (int k = 0; k < 8; ++k) geom[k] = g[k];
+    *count = (int64_t)pp.pieces.size();
+    if (pieces)
+        for (int64_t k = 0; k < std::min<int64_t>(cap, *count); ++k) {
+            pieces[4 * k] = pp.pieces[k].tx;
+            pieces[4 * k + 1] = pp.pieces[k].ty;
+            pieces[4 * k + 2] = pp.pieces[k].z0;
+            pieces[4 * k + 3] = pp.pieces[k].z1;
+        }
+    return IG_OK;
+}
+
 static void drop_plans(ig_filter* f) {
     for (int T = 0; T < 5; ++T) {
         if (f->dpieces[T]) (void)hipFree(f->dpieces[T]);

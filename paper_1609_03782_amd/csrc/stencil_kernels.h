@@ -24,6 +24,8 @@
 // Both kernels use edge_term/combine from stencil_common.h in the same order,
 // so their results are bitwise identical.
 #pragma once
+#include <type_traits>
+
 #include "stencil_common.h"
 
 namespace igk {
@@ -227,11 +229,22 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     const int edge_base = T * W * RX;
     const int lvl = W * RX;
 
-    float cur[T][V], fzm[T][V];
+    // Register rotation (the step loop is unrolled by two, parity p known at
+    // compile time): lv[t][p] is level t's current plane and lv[t][p^1] the
+    // plane above it; level t writes its result straight into lv[t+1][p^1],
+    // and the next step swaps the roles, so no plane is copied between
+    // registers.
+    // one above.  Only the prefetched input plane is copied into lv[0][p^1].
+    // fz[t] is the z edge term below the current plane of level t.
+    float lv[T][2][V], fz[T][V];
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int i = 0; i < V; ++i) { cur[t][i] = 0.0f; fzm[t][i] = 0.0f; }
+        for (int i = 0; i < V; ++i) {
+            lv[t][0][i] = 0.0f;
+            lv[t][1][i] = 0.0f;
+            fz[t][i] = 0.0f;
+        }
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -251,92 +264,116 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     __syncthreads();
 
     const int nsteps = nin + T;
-    for (int s = 0; s < nsteps; ++s) {
-        float nxt[V];
+    // level t (0-based) is exact on this row when y lies in [lo_t, hi_t)
+    bool valid[T];
 #pragma unroll
-        for (int i = 0; i < V; ++i) nxt[i] = pf[i];
+    for (int t = 0; t < T; ++t)
+        valid[t] = row_in && y >= lo_base + (t + 1) * lo_step && y < hi_base - (t + 1) * hi_step;
+
+    // One step.  STEADY: every level computes and has the plane above (the
+    // steps T <= s < nin), so none of the start/end conditions are evaluated.
+    auto step = [&](auto parity, auto steady, int s) {
+        constexpr int p = decltype(parity)::value, q = p ^ 1;
+        constexpr bool STEADY = decltype(steady)::value;
+        if (STEADY || s < nin) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) lv[0][q][i] = pf[i];
+        }
         if (s + 1 < nin) load(zin0 + s + 1);
 
         // phase 1: every level advances one plane
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            const bool has_nxt = (s - t >= 0) && (s - t < nin);
-            const bool compute = (s - t - 1 >= 0) && (s - t - 1 < nin);
-            const int p = zin0 + s - t - 1;
-            if (compute) {
-                const int L = t + 1;
-                const bool valid = row_in && y >= lo_base + L * lo_step && y < hi_base - L * hi_step;
-                float out[V];
-                if (valid) {
-                    const float czp = (p + 1 < nz && has_nxt) ? P.coef[2] : P.closed;
-                    float ex[V];
+            const bool has_nxt = STEADY || ((s - t >= 0) && (s - t < nin));
+            const bool compute = STEADY || ((s - t - 1 >= 0) && (s - t - 1 < nin));
+            const int pz = zin0 + s - t - 1;
+            // halo rows of a level are never used by a valid row: skip them
+            if (!compute || !valid[t]) continue;
+            const float czp = (STEADY || (pz + 1 < nz && has_nxt)) ? P.coef[2] : P.closed;
+            float ex[V];
 #pragma unroll
-                    for (int i = 0; i < V - 1; ++i)
-                        ex[i] = edge_term<COND>(cur[t][i + 1] - cur[t][i], VEC ? P.coef[0] : cx[i], P.kap);
-                    const float right = lane_shl1(cur[t][0]);
-                    ex[V - 1] = edge_term<COND>(right - cur[t][V - 1], cx[VEC ? 0 : V - 1], P.kap);
-                    const float exm0 = lane_shr1(ex[V - 1]);
-                    const int eo = edge_base + t * lvl + row_off;
+            for (int i = 0; i < V - 1; ++i)
+                ex[i] = edge_term<COND>(lv[t][p][i + 1] - lv[t][p][i], VEC ? P.coef[0] : cx[i], P.kap);
+            const float right = lane_shl1(lv[t][p][0]);
+            ex[V - 1] = edge_term<COND>(right - lv[t][p][V - 1], cx[VEC ? 0 : V - 1], P.kap);
+            const float exm0 = lane_shr1(ex[V - 1]);
+            const int eo = edge_base + t * lvl + row_off;
+            float out[V];
 #pragma unroll
-                    for (int i = 0; i < V; ++i) {
-                        const float eyd = w > 0 ? lds[eo - RX + 64 * i] : 0.0f;
-                        const float eyu = lds[eo + 64 * i];
-                        const float up_z = has_nxt ? nxt[i] : cur[t][i];
-                        const float ezp = edge_term<COND>(up_z - cur[t][i], czp, P.kap);
-                        const float o = combine<COND>(cur[t][i], i == 0 ? exm0 : ex[i - 1], ex[i], eyd, eyu,
-                                                      fzm[t][i], ezp, P.kap, P.tau);
-                        out[i] = Store<ST>::quant(o);
-                        fzm[t][i] = ezp;
-                    }
+            for (int i = 0; i < V; ++i) {
+                const float eyd = w > 0 ? lds[eo - RX + 64 * i] : 0.0f;
+                const float eyu = lds[eo + 64 * i];
+                const float c = lv[t][p][i];
+                const float up_z = has_nxt ? lv[t][q][i] : c;
+                const float ezp = edge_term<COND>(up_z - c, czp, P.kap);
+                const float o = combine<COND>(c, i == 0 ? exm0 : ex[i - 1], ex[i], eyd, eyu, fz[t][i], ezp,
+                                              P.kap, P.tau);
+                fz[t][i] = ezp;
+                if (t + 1 < T) lv[t + 1][q][i] = Store<ST>::quant(o);
+                else out[i] = Store<ST>::quant(o);
+            }
+            if (t == T - 1 && row_store && pz >= oz0 && pz < oz1) {
+                ST* r = dst + (long)pz * plane + (long)y * nx;
+                if constexpr (VEC) {
+                    if (xl0 >= ox0 && xl0 + V <= ox1) Vec<ST, V>::store(r + xl0, out);
                 } else {
 #pragma unroll
-                    for (int i = 0; i < V; ++i) out[i] = cur[t][i];
-                }
-                if (t == T - 1 && row_store && p >= oz0 && p < oz1) {
-                    ST* r = dst + (long)p * plane + (long)y * nx;
-                    if constexpr (VEC) {
-                        if (xl0 >= ox0 && xl0 + V <= ox1) Vec<ST, V>::store(r + xl0, out);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < V; ++i) {
-                            const int x = xl0 + i;
-                            if (x >= ox0 && x < ox1) r[x] = Store<ST>::store(out[i]);
-                        }
+                    for (int i = 0; i < V; ++i) {
+                        const int x = xl0 + i;
+                        if (x >= ox0 && x < ox1) r[x] = Store<ST>::store(out[i]);
                     }
                 }
-                if (has_nxt) {
-#pragma unroll
-                    for (int i = 0; i < V; ++i) cur[t][i] = nxt[i];
-                }
-#pragma unroll
-                for (int i = 0; i < V; ++i) nxt[i] = out[i];
-            } else if (has_nxt) {
-#pragma unroll
-                for (int i = 0; i < V; ++i) cur[t][i] = nxt[i];
             }
         }
-        // phase 2: publish each level's new current row
+        // phase 2: publish each level's new current row (lv[t][q])
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            if ((s - t >= 0) && (s - t < nin)) {
+            if (STEADY || ((s - t >= 0) && (s - t < nin))) {
 #pragma unroll
-                for (int i = 0; i < V; ++i) lds[t * lvl + row_off + 64 * i] = cur[t][i];
+                for (int i = 0; i < V; ++i) lds[t * lvl + row_off + 64 * i] = lv[t][q][i];
             }
         }
         __syncthreads();
         // phase 3: y edge term from the new current row to the row above
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            if ((s - t >= 0) && (s - t < nin)) {
+            if (STEADY || ((s - t >= 0) && (s - t < nin))) {
                 const int ro = t * lvl + row_off;
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
-                    const float up = w + 1 < W ? lds[ro + RX + 64 * i] : cur[t][i];
-                    lds[edge_base + ro + 64 * i] = edge_term<COND>(up - cur[t][i], cyu, P.kap);
+                    const float up = w + 1 < W ? lds[ro + RX + 64 * i] : lv[t][q][i];
+                    lds[edge_base + ro + 64 * i] = edge_term<COND>(up - lv[t][q][i], cyu, P.kap);
                 }
             }
         }
         __syncthreads();
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using GEN = std::false_type;
+    using STD = std::true_type;
+    constexpr int PT = T & 1;   // parity of step T
+    using PA = std::integral_constant<int, PT>;
+    using PB = std::integral_constant<int, PT ^ 1>;
+
+    // prologue: steps 0 .. T-1 (parity s & 1)
+#pragma unroll
+    for (int s0 = 0; s0 < T; ++s0) {
+        if (s0 < nsteps) {
+            if ((s0 & 1) == 0) step(I0{}, GEN{}, s0);
+            else step(I1{}, GEN{}, s0);
+        }
+    }
+    // steady state: steps T .. nin-1, two per iteration
+    int s = T;
+    for (; s + 1 < nin; s += 2) {
+        step(PA{}, STD{}, s);
+        step(PB{}, STD{}, s + 1);
+    }
+    // remaining steps: at most one steady one, then the epilogue
+    for (; s < nsteps; ++s) {
+        if (((s - T) & 1) == 0) step(PA{}, GEN{}, s);
+        else step(PB{}, GEN{}, s);
     }
 }
 
