@@ -1,16 +1,15 @@
-// Batched filter: many independent FP32 cubes of uneven sizes and parameters
-// in one persistent launch, captured once per batch signature into a HIP
-// graph.  See ig_filter_batch in include/igfilter.h.
+// Batched filter: many independent FP32 cubes of uneven sizes and parameters,
+// captured once per batch signature into one HIP graph and replayed.  See
+// ig_filter_batch in include/igfilter.h.
 //
-// Work items are (cube, pass, piece) in a host-built order: pass-major over
-// the cubes, so a pass of a cube is dequeued only after every piece of its
-// previous pass was dequeued.  Persistent workgroups take items from one
-// atomic counter; before a piece of pass k of cube c runs, its workgroup waits
-// until all pieces of pass k-1 of c are done (per-cube counter, agent-scope
-// acquire).  Every item a waiter depends on was dequeued earlier by a running
-// workgroup that waits only on still earlier items, so the wait always ends;
-// a spin limit turns a broken dependency into an error flag instead of a hang.
-// Each cube's completion is stamped with the GPU's constant-rate clock.
+// Work items are (cube, pass, piece).  Round r of the graph is one launch of
+// k_batch_round over the pieces of pass r of every cube that has one, largest
+// cubes first; the kernel boundary between rounds orders the passes, so no
+// workgroup ever waits on another.  The graph holds the counter reset (which
+// also stamps the start on the GPU's constant-rate clock), the per-cube FP64
+// noise-level scan, the staging copies and the rounds; the descriptor tables
+// are uploaded once when the plan is built.  The last piece of a cube's last
+// pass stamps the clock, giving each cube's completion latency.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,8 +44,7 @@ struct BatchItem {
     int cube, pass, piece, depth;
 };
 
-constexpr int kCtrHead = 0, kCtrError = 1, kCtrDone = 2;   // + cube
-constexpr long kSpinLimit = 1L << 24;
+constexpr int kCtrDone = 0;   // + cube: pieces of its last pass that are done
 
 // ------------------------------------------------------------ rms pre-pass
 struct SumChunk {
@@ -121,10 +119,12 @@ k_batch_params(const ParamIn* __restrict__ pin, const int* __restrict__ chunk_fi
     out[c] = P;
 }
 
-// Clear the counters and stamps (a kernel, so graph replays start clean).
+// Clear the counters and stamps (a kernel, so graph replays start clean) and
+// stamp the start of the batch.
 __global__ void k_batch_reset(int* __restrict__ ctr, int nctr, unsigned long long* __restrict__ stamps, int nst) {
     for (int i = threadIdx.x; i < nctr; i += blockDim.x) ctr[i] = 0;
-    for (int i = threadIdx.x; i < nst; i += blockDim.x) stamps[i] = i == 0 ? ~0ULL : 0ULL;
+    const unsigned long long t0 = wall_clock64();
+    for (int i = threadIdx.x; i < nst; i += blockDim.x) stamps[i] = i == 0 ? t0 : 0ULL;
 }
 
 // Stage in-place inputs with an odd pass count through scratch (copy), so
@@ -152,66 +152,47 @@ __device__ __forceinline__ void run_piece_v(const BatchCube& cb, const float* sr
     }
 }
 
+// One round: workgroup b runs piece items[b] (one pass of one piece of one cube).
 template <int COND, int T>
 __global__ void __launch_bounds__(1024)
-k_batch(const BatchCube* __restrict__ cubes, const BatchItem* __restrict__ items, int nitems,
-        const Piece* __restrict__ pieces, const DevParams* __restrict__ prm, int* __restrict__ ctr,
-        unsigned long long* __restrict__ stamps) {
+k_batch_round(const BatchCube* __restrict__ cubes, const BatchItem* __restrict__ items,
+              const Piece* __restrict__ pieces, const DevParams* __restrict__ prm, int* __restrict__ ctr,
+              unsigned long long* __restrict__ stamps) {
     extern __shared__ float lds[];
-    __shared__ int s_item;
     const int tid = threadIdx.y * 64 + threadIdx.x;
-    if (tid == 0) atomicMin(&stamps[0], (unsigned long long)wall_clock64());
-    while (true) {
-        if (tid == 0) s_item = atomicAdd(&ctr[kCtrHead], 1);
-        __syncthreads();
-        const int it = s_item;
-        __syncthreads();
-        if (it >= nitems) break;
-        const BatchItem item = items[it];
-        const BatchCube& cb = cubes[item.cube];
-        const DevParams P = prm[item.cube];
-        int* done = &ctr[kCtrDone + item.cube];
-        if (!P.abort) {
-            if (tid == 0 && item.pass > 0) {
-                const int need = item.pass * cb.npieces;
-                long spins = 0;
-                while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > kSpinLimit) { atomicOr(&ctr[kCtrError], 1); break; }
-                }
-            }
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            // buffers: pass k (1-based) writes out if (npass - k) is even, else scratch
-            const int k = item.pass + 1;
-            const float* src = item.pass == 0 ? (cb.stage ? cb.scratch : cb.in)
-                                              : (((cb.npass - (k - 1)) % 2 == 0) ? cb.out : cb.scratch);
-            float* dst = ((cb.npass - k) % 2 == 0) ? cb.out : cb.scratch;
-            const Piece pc = pieces[cb.piece_off + item.piece];
-            if constexpr (T >= 1) if (item.depth == 1) run_piece_v<COND, T, 1>(cb, src, dst, pc, P, lds);
-            if constexpr (T >= 2) if (item.depth == 2) run_piece_v<COND, T, 2>(cb, src, dst, pc, P, lds);
-            if constexpr (T >= 3) if (item.depth == 3) run_piece_v<COND, T, 3>(cb, src, dst, pc, P, lds);
-            if constexpr (T >= 4) if (item.depth == 4) run_piece_v<COND, T, 4>(cb, src, dst, pc, P, lds);
-            __threadfence();   // this wavefront's stores, visible at agent scope
-        }
+    const BatchItem item = items[blockIdx.x];
+    const BatchCube& cb = cubes[item.cube];
+    const DevParams P = prm[item.cube];
+    if (P.abort) return;
+    // pass k (1-based) writes out if (npass - k) is even, else scratch
+    const int k = item.pass + 1;
+    const float* src = item.pass == 0 ? (cb.stage ? cb.scratch : cb.in)
+                                      : (((cb.npass - (k - 1)) % 2 == 0) ? cb.out : cb.scratch);
+    float* dst = ((cb.npass - k) % 2 == 0) ? cb.out : cb.scratch;
+    const Piece pc = pieces[cb.piece_off + item.piece];
+    if constexpr (T >= 1) if (item.depth == 1) run_piece_v<COND, T, 1>(cb, src, dst, pc, P, lds);
+    if constexpr (T >= 2) if (item.depth == 2) run_piece_v<COND, T, 2>(cb, src, dst, pc, P, lds);
+    if constexpr (T >= 3) if (item.depth == 3) run_piece_v<COND, T, 3>(cb, src, dst, pc, P, lds);
+    if constexpr (T >= 4) if (item.depth == 4) run_piece_v<COND, T, 4>(cb, src, dst, pc, P, lds);
+    if (item.pass == cb.npass - 1) {   // completion stamp of the cube
         __syncthreads();
         if (tid == 0) {
-            const int prev = __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev + 1 == cb.npass * cb.npieces) stamps[1 + item.cube] = wall_clock64();
+            const int prev = atomicAdd(&ctr[kCtrDone + item.cube], 1);
+            if (prev + 1 == cb.npieces) stamps[1 + item.cube] = wall_clock64();
         }
     }
 }
 
-using BatchKernel = void (*)(const BatchCube*, const BatchItem*, int, const Piece*, const DevParams*, int*,
+using BatchKernel = void (*)(const BatchCube*, const BatchItem*, const Piece*, const DevParams*, int*,
                              unsigned long long*);
 
 template <int COND>
 static BatchKernel batch_kernel_T(int T) {
     switch (T) {
-        case 1: return k_batch<COND, 1>;
-        case 2: return k_batch<COND, 2>;
-        case 3: return k_batch<COND, 3>;
-        default: return k_batch<COND, 4>;
+        case 1: return k_batch_round<COND, 1>;
+        case 2: return k_batch_round<COND, 2>;
+        case 3: return k_batch_round<COND, 3>;
+        default: return k_batch_round<COND, 4>;
     }
 }
 static BatchKernel batch_kernel(int cond, int T) {
@@ -248,17 +229,6 @@ struct DevBuf {
         return hipMalloc((void**)&p, std::max<size_t>(1, count) * sizeof(T));
     }
 };
-template <typename T>
-struct HostBuf {  // pinned host memory (a graph's copy source must stay alive)
-    T* p = nullptr;
-    size_t n = 0;
-    ~HostBuf() { if (p) (void)hipHostFree(p); }
-    hipError_t alloc(size_t count) {
-        n = count;
-        return hipHostMalloc((void**)&p, std::max<size_t>(1, count) * sizeof(T), hipHostMallocDefault);
-    }
-};
-
 struct BatchPlan {
     int device = 0;
     int cond = 0, T = 1, W = 16;
@@ -277,10 +247,8 @@ struct BatchPlan {
     DevBuf<DevParams> d_outsum;
     DevBuf<int> d_ctr;
     DevBuf<unsigned long long> d_stamps;
-    HostBuf<BatchCube> h_cubes;
-    HostBuf<BatchItem> h_items;
-    HostBuf<Piece> h_pieces;
-    int nitems = 0, nchunks = 0, grid = 0;
+    std::vector<int> round_off;   // items of round r: [round_off[r], round_off[r+1])
+    int nitems = 0, nchunks = 0;
     size_t lds = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -390,19 +358,20 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     bp->passes.resize(count);
     for (int c = 0; c < count; ++c) bp->passes[c] = cubes[c].npass;
 
-    // item order: pass-major; within a pass round, longest cubes first
+    // rounds: round r holds pass r of every cube that has one, largest cubes first
     std::vector<int> order(count);
     for (int c = 0; c < count; ++c) order[c] = c;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return (double)nvox[a] * items[a].p.n_iter > (double)nvox[b] * items[b].p.n_iter;
-    });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nvox[a] > nvox[b]; });
     int maxpass = 0;
     for (int c = 0; c < count; ++c) maxpass = std::max(maxpass, cubes[c].npass);
     std::vector<BatchItem> its;
-    for (int k = 0; k < maxpass; ++k)
+    bp->round_off.assign(1, 0);
+    for (int k = 0; k < maxpass; ++k) {
         for (int c : order)
             if (k < cubes[c].npass)
                 for (int j = 0; j < cubes[c].npieces; ++j) its.push_back(BatchItem{c, k, j, depths[c][k]});
+        bp->round_off.push_back((int)its.size());
+    }
     bp->nitems = (int)its.size();
     bp->nchunks = (int)chunks.size();
 
@@ -420,13 +389,12 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     HIP_TRY(bp->d_outsum.alloc(count));
     HIP_TRY(bp->d_ctr.alloc(kCtrDone + count));
     HIP_TRY(bp->d_stamps.alloc(1 + count));
-    HIP_TRY(bp->h_cubes.alloc(count));
-    HIP_TRY(bp->h_items.alloc(its.size()));
-    HIP_TRY(bp->h_pieces.alloc(pieces.size()));
-    std::memcpy(bp->h_cubes.p, cubes.data(), count * sizeof(BatchCube));
-    std::memcpy(bp->h_items.p, its.data(), its.size() * sizeof(BatchItem));
-    std::memcpy(bp->h_pieces.p, pieces.data(), pieces.size() * sizeof(Piece));
-    // static tables: uploaded once
+    // descriptor tables: fixed for the plan's signature, uploaded once
+    HIP_TRY(hipMemcpy(bp->d_cubes.p, cubes.data(), count * sizeof(BatchCube), hipMemcpyHostToDevice));
+    if (!its.empty())
+        HIP_TRY(hipMemcpy(bp->d_items.p, its.data(), its.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+    if (!pieces.empty())
+        HIP_TRY(hipMemcpy(bp->d_pieces.p, pieces.data(), pieces.size() * sizeof(Piece), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bp->d_chunks.p, chunks.data(), chunks.size() * sizeof(SumChunk), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bp->d_chunk_first.p, chunk_first.data(), (count + 1) * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bp->d_pin.p, pin.data(), count * sizeof(ParamIn), hipMemcpyHostToDevice));
@@ -435,28 +403,36 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     BatchKernel kern = batch_kernel(bp->cond, T);
     if (lds > 65536)
         HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    bp->grid = ncu * resident_per_cu(W, lds);
 
-    // capture: descriptor upload, counter reset, rms pre-pass, staging, persistent kernel
+    // capture: counter reset, noise-level pre-pass, staging, the rounds
     HIP_TRY(hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal));
     hipStream_t s = bp->cap;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-    chk(hipMemcpyAsync(bp->d_cubes.p, bp->h_cubes.p, count * sizeof(BatchCube), hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(bp->d_items.p, bp->h_items.p, its.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(bp->d_pieces.p, bp->h_pieces.p, pieces.size() * sizeof(Piece), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, bp->d_ctr.p, kCtrDone + count, bp->d_stamps.p,
                        1 + count);
-    hipLaunchKernelGGL(k_batch_sum, dim3(bp->nchunks), dim3(256), 0, s, bp->d_cubes.p, bp->d_chunks.p,
-                       bp->d_part.p, 0);
+    chk(hipGetLastError());
+    if (bp->nchunks > 0) {
+        hipLaunchKernelGGL(k_batch_sum, dim3(bp->nchunks), dim3(256), 0, s, bp->d_cubes.p, bp->d_chunks.p,
+                           bp->d_part.p, 0);
+        chk(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_batch_params, dim3(count), dim3(64), 0, s, bp->d_pin.p, bp->d_chunk_first.p,
                        bp->d_part.p, bp->d_nvox.p, bp->d_params.p, 0);
-    hipLaunchKernelGGL(k_batch_stage, dim3(bp->nchunks), dim3(256), 0, s, bp->d_cubes.p, bp->d_chunks.p,
-                       bp->d_params.p);
-    hipLaunchKernelGGL(kern, dim3(bp->grid), dim3(64, W), lds, s, bp->d_cubes.p, bp->d_items.p, bp->nitems,
-                       bp->d_pieces.p, bp->d_params.p, bp->d_ctr.p, bp->d_stamps.p);
     chk(hipGetLastError());
+    if (bp->nchunks > 0) {
+        hipLaunchKernelGGL(k_batch_stage, dim3(bp->nchunks), dim3(256), 0, s, bp->d_cubes.p, bp->d_chunks.p,
+                           bp->d_params.p);
+        chk(hipGetLastError());
+    }
+    for (size_t r = 0; r + 1 < bp->round_off.size(); ++r) {
+        const int n = bp->round_off[r + 1] - bp->round_off[r];
+        if (n <= 0) continue;
+        hipLaunchKernelGGL(kern, dim3(n), dim3(64, W), lds, s, bp->d_cubes.p, bp->d_items.p + bp->round_off[r],
+                           bp->d_pieces.p, bp->d_params.p, bp->d_ctr.p, bp->d_stamps.p);
+        chk(hipGetLastError());
+    }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return fail(IG_ERR_DEVICE, "capture: %s", hipGetErrorString(e)); }
@@ -521,8 +497,6 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
     HIP_TRY(hipGraphLaunch(bp->exec, s));
     if (!per_item && !latency_ms) return IG_OK;
 
-    int ctr_err = 0;
-    HIP_TRY(hipMemcpyAsync(&ctr_err, bp->d_ctr.p + kCtrError, sizeof(int), hipMemcpyDeviceToHost, s));
     std::vector<unsigned long long> stamps(1 + count);
     HIP_TRY(hipMemcpyAsync(stamps.data(), bp->d_stamps.p, stamps.size() * 8, hipMemcpyDeviceToHost, s));
     std::vector<DevParams> prm(count);
@@ -538,7 +512,6 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
     if (per_item)
         HIP_TRY(hipMemcpyAsync(osum.data(), bp->d_outsum.p, count * sizeof(DevParams), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (ctr_err) return fail(IG_ERR_DEVICE, "batch dependency wait exceeded its spin limit");
     int khz = 0;
     (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
     bool bad = false;

@@ -49,7 +49,9 @@ def test_fullsize_sampled_parity(dev, field, oracle_lib, cond, K, tau, n, C):
     torch.cuda.synchronize()
     rho = st.rms_used
     r_or, s_or, _ = oracle_lib.rms(cube)
-    assert rho == pytest.approx(r_or, rel=1e-12)
+    # the oracle sums the 1.3e8 squares one after another: recursive summation
+    # in FP64 is exact to (N-1) u sum|x^2| (u = 2^-53), so rho to half of that
+    assert rho == pytest.approx(r_or, rel=0.5 * cube.size * 2.0 ** -53 + 1e-15)
     rng = np.random.default_rng(n)
     pts = _points(cube, rng)
     ref = oracle_lib.run_points(cube, pts, cond, K=K, tau=tau, n_iter=n, C=(C, C, C), rms=rho)
@@ -64,13 +66,11 @@ def test_fullsize_sampled_parity(dev, field, oracle_lib, cond, K, tau, n, C):
     assert float(y.max()) <= float(x.max()) and float(y.min()) >= float(x.min())
 
 
-def _ulps(a, b, dtype):
+def _ulp_at(mag, dtype):
+    """Spacing of the storage type at magnitude mag (normal range)."""
     import torch
-    # distance in units of the storage type's spacing at the larger magnitude
-    m = np.maximum(np.abs(a), np.abs(b))
-    e = np.floor(np.log2(np.maximum(m, 1e-30)))
     bits = 7 if dtype == torch.bfloat16 else 10
-    return np.abs(a - b) / np.exp2(e - bits)
+    return 2.0 ** (np.floor(np.log2(mag)) - bits)
 
 
 @pytest.mark.parametrize("name", ["bf16", "f16"])
@@ -87,14 +87,17 @@ def test_16bit_storage_vs_rounding_oracle(dev, oracle_lib, name):
     torch.cuda.synchronize()
     g = y.double().cpu().numpy()
     ref, rho = oracle_lib.run(q, "pm_exp", K=2.0, tau=1 / 16, n_iter=n, round_to=name)
-    u = _ulps(g, ref, dt)
     frac_equal = float(np.mean(g == ref))
-    print(f"{name}: bitwise-equal fraction {frac_equal:.5f}, max ulp distance {u.max():.1f}, "
-          f"max-abs {np.abs(g - ref).max():.3e}")
-    # FP32 vs FP64 arithmetic flips a rounding only near ties; the flip moves a
-    # voxel by one storage unit and spreads, damped, to its neighbours
-    assert frac_equal >= 0.97
-    assert u.max() <= 4.0
+    d = np.abs(g - ref)
+    unit = _ulp_at(np.abs(ref).max(), dt)
+    print(f"{name}: bitwise-equal fraction {frac_equal:.5f}, max-abs {d.max():.3e} "
+          f"(= {d.max() / unit:.2f} storage units at the cube's largest value)")
+    # FP32 (GPU) and FP64 (oracle) arithmetic take a different rounding only
+    # near ties; a flip moves a voxel by one storage unit of its magnitude and
+    # reaches its neighbours damped by tau*C*w < 1, so almost every voxel is
+    # bitwise equal and no difference exceeds two units at the largest value
+    assert frac_equal >= 0.99
+    assert d.max() <= 2.0 * unit
     # and the whole run stays close to the exact (unrounded) filter
     exact, _ = oracle_lib.run(q, "pm_exp", K=2.0, tau=1 / 16, n_iter=n)
     assert np.sqrt(np.mean((g - exact) ** 2)) <= (0.02 if name == "bf16" else 0.003) * rho
