@@ -28,18 +28,58 @@ N_ITER = 50
 SHAPE = (512, 512, 512)   # (nz, ny, nx)
 
 
-def cpu_baseline(cube, n_iter, K, tau):
-    """The FP64 oracle on a bounded slab of the same cube (all host threads)."""
+def cpu_baseline(cube, n_iter, K, tau, nz_s=None):
+    """The FP64 oracle on the same cube (all host threads): the whole cube by
+    default (about 15 s on 16 cores), or its first nz_s planes."""
     import oracle
     oracle.build(force=False)
-    nz_s = 48
-    slab = cube[:nz_s]
+    slab = cube if nz_s is None else cube[:nz_s]
     t0 = time.perf_counter()
-    oracle.run(slab, "pm_exp", K=K, tau=tau, n_iter=n_iter, rms=1.0)
+    oracle.run(slab, "pm_exp", K=K, tau=tau, n_iter=n_iter)
     dt = time.perf_counter() - t0
     vi = slab.size * n_iter
+    nz, ny, nx = slab.shape
+    what = "the whole cube" if nz_s is None else "a slab of the same cube"
     return {"value": round(vi / dt / 1e9, 5), "unit": "Gvoxel-iter/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"512x512x{nz_s} slab of the same cube, {n_iter} iterations, FP64 ({dt:.1f} s)"}
+            "sample": f"{what}: {nx}x{ny}x{nz}, {n_iter} iterations, rms estimated, FP64 ({dt:.1f} s)"}
+
+
+# Algorithmic ALU work of one voxel-iteration of the edge-shared exponential
+# update: 3 edges x (difference, square, scaled exponent fma, exp2, flux
+# multiply) + 6 adds for the flux divergence and the update.  Issue slots on
+# gfx950 without packed FP32: 1 per operation, 2 per exp2 -> 24 slots; flops:
+# 1 per operation, 2 per fma -> 24.  Non-packed FP32 issue peak: 256 CUs x
+# 64 lanes x 2.4 GHz = 39.32 T slots/s, so 39.32 TFLOP/s for this mix.
+PM_EXP_FLOP_PER_VOXEL_ITER = 24
+ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def code_only(src):
+    """C++ source without comments and with whitespace collapsed, so that a
+    comment edit does not count as a kernel change."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def counter_traffic():
+    """HBM bytes per k_stream launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken from the kernel sources as they are now."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", "k_stream_pm_exp_512cube.md")
+    srcs = ["stencil_kernels.h", "stencil_common.h", "stencil_inst.hip"]
+    try:
+        m = re.search(r"traffic_bytes_per_launch=(\d+) code_sha256=([0-9a-f]+)", open(prof).read())
+        h = hashlib.sha256()
+        for f in srcs:
+            h.update(code_only(open(os.path.join(ROOT, "paper_1609_03782_amd", "csrc", f)).read()).encode())
+    except OSError:
+        return None
+    if not m or m.group(2) != h.hexdigest():
+        return None
+    return int(m.group(1))
 
 
 def time_runs(f, x, out, steps, warmup, timing=False):
@@ -111,7 +151,7 @@ def bench_paper_defaults(x, steps):
 
 
 def bench_batch(steps):
-    """96 uneven cubes in one persistent, graph-captured launch."""
+    """96 uneven cubes in one graph launch (one kernel per pass round)."""
     import numpy as np
     import torch
     import igsynth
@@ -153,9 +193,13 @@ def bench_surrogate(args):
     params = dict(K=2.0, tau=1 / 16, n_iter=N_ITER, cond="pm_exp")
     t0 = time.perf_counter()
     xs_np = igsynth.train_set(range(100000, 100000 + args.train), n=args.cube, workers=16)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    log(f"generated {len(xs_np)} training cubes in {time.perf_counter() - t0:.1f} s")
     xs = [torch.from_numpy(c).to(dev) for c in xs_np]
     del xs_np
     ts = sg.filter_targets(xs, n_iter=N_ITER)
+    torch.cuda.synchronize()
+    log(f"filtered targets ready at {time.perf_counter() - t0:.1f} s")
     vx_np = igsynth.train_set(range(200000, 200000 + args.val), n=args.cube, workers=16)
     vxs = [torch.from_numpy(c).to(dev) for c in vx_np]
     vts = sg.filter_targets(vxs, n_iter=N_ITER)
@@ -163,11 +207,12 @@ def bench_surrogate(args):
     t_data = time.perf_counter() - t0
     net = sg.Surrogate(depth=8, lr=args.lr, seed=0)
     t0 = time.perf_counter()
-    losses = sg.train(net, xs, ts, epochs=args.epochs, batch=args.batch, log=lambda m: print(m, file=sys.stderr,
-                                                                                            flush=True))
+    losses = sg.train(net, xs, ts, epochs=args.epochs, batch=args.batch, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    log(f"trained {len(losses)} steps in {t_train:.1f} s")
     slope, pairs = sg.calibrate(net, vxs, vts, params)
+    log(f"calibrated slope {slope:.4g} on {len(pairs)} validation cubes")
     val_rmse = float(np.mean([e for _, e in pairs]))
     del xs, ts
     cube = igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])
@@ -262,11 +307,25 @@ def main():
     N = cube.size
     value = N * N_ITER / (ms_step * 1e-3) / 1e9
     eff_gbs = 8.0 * N * N_ITER / (ms_step * 1e-3) / 1e9
-    # dominant kernel: k_stream; algorithmic bytes per launch = 8 B per
-    # voxel-step (4 read + 4 written) x N voxels x steps per launch
+    # dominant kernel: k_stream, T iterations per launch over N voxels.
+    # Algorithmic bytes per launch: 8 B per voxel (one read, one write);
+    # algorithmic flops: 24 per voxel-iteration.
     T = max(1, sched["t_block"]) if sched["kind"] == "blocked" else 1
     avg_ms = k_ms / max(1, k_launches)
-    achieved = 8.0 * N * T / (avg_ms * 1e-3) / 1e9
+    achieved_gbs = 8.0 * N * T / (avg_ms * 1e-3) / 1e9
+    achieved_tf = PM_EXP_FLOP_PER_VOXEL_ITER * N * T / (avg_ms * 1e-3) / 1e12
+    traffic = counter_traffic()
+    # the binding ceiling is the lower of the two voxel-iteration rates
+    alu_cap = ALU_PEAK_TFLOPS * 1e12 / PM_EXP_FLOP_PER_VOXEL_ITER
+    hbm_cap = HBM_PEAK_GBS * 1e9 * T / 8.0
+    hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+    alu = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
+           "frac": round(achieved_tf / ALU_PEAK_TFLOPS, 4), "traffic": traffic}
+    roof = dict(alu if alu_cap <= hbm_cap else hbm)
+    roof["other"] = hbm if alu_cap <= hbm_cap else alu
+    roof.update({"kernel": "k_stream", "avg_launch_ms": round(avg_ms, 5), "launches": k_launches,
+                 "iterations_per_launch": T})
 
     res = {
         "metric": METRIC,
@@ -287,9 +346,7 @@ def main():
                    "voxels": N, "iterations": N_ITER, "schedule": sched,
                    "effective_hbm_GBps": round(eff_gbs, 1),
                    "effective_hbm_frac": round(eff_gbs / HBM_PEAK_GBS, 4)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_stream", "avg_launch_ms": round(avg_ms, 5), "launches": k_launches},
+        "roofline": roof,
     }
     if not args.no_extras:
         extras = {}

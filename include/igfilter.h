@@ -176,11 +176,13 @@ typedef struct {
     void* d_out;
 } ig_batch_item;
 
-/* Filter `count` independent cubes of uneven sizes and parameters in one
- * persistent launch (all items: FP32 storage, same device).  The launch,
- * together with the upload of its work descriptors, is captured once per
- * batch signature into a HIP graph and replayed on later calls with the same
- * signature (item shapes, parameters and buffer addresses).  Scratch cubes
+/* Filter `count` independent cubes of uneven sizes and parameters with one
+ * graph launch (all items: FP32 storage, same device).  The graph holds the
+ * per-cube noise-level scans and one kernel launch per pass round (round r:
+ * pass r of every cube that has one); it is built once per batch signature
+ * (item shapes, parameters and buffer addresses), with its work descriptors
+ * uploaded at that time, and replayed on later calls with the same
+ * signature.  Scratch cubes
  * for the ping-pong are owned by that cached plan (ig_batch_cache_clear frees
  * them).  per_item (nullable, `count` entries) receives each item's stats;
  * latency_ms (nullable, `count` entries) receives each cube's completion time

@@ -269,7 +269,7 @@ class Filter:
 
 
 def batch(items, device=0, want_stats=False, want_latency=False):
-    """items: list of (x, out, params-dict).  One persistent launch (ig_filter_batch)."""
+    """items: list of (x, out, params-dict).  One graph launch (ig_filter_batch)."""
     import torch
     n = len(items)
     arr = _batch_array(items)

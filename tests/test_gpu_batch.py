@@ -1,4 +1,4 @@
-"""GPU checks of the persistent batched launch (ig_filter_batch): every item
+"""GPU checks of the batched graph launch (ig_filter_batch): every item
 matches the FP64 oracle, equals the single-cube run bitwise, graph replays give
 the same bytes, and per-item statistics and latencies are filled."""
 import numpy as np
