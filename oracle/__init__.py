@@ -12,6 +12,8 @@ Contents
   * ``brute``: an independent NumPy pad-and-shift form of the same step, for
     tiny cubes.
   * ``surrogate``: FP64 NumPy forms of the learned surrogate's layers.
+  * ``quality``: the filtering-quality diagnostics of Section 6 (F, sigma_F,
+    F_M) over a region of interest and a sweep of mask thresholds.
 
 Pins (tests/test_oracle_pins.py): constant cube is a fixed point, zero
 conductance is the identity, flux conservation of the per-edge forms under
@@ -19,6 +21,9 @@ reflecting faces, a weighted conservation identity of the intensity form,
 closed-form impulse responses, the linear limit diagonalised by the
 orthonormal DCT-II, the maximum principle, symmetries, composition, the
 brute-force cross-check, and the storage rounding against IEEE casts.
+Quality pins (tests/test_oracle_quality.py): a hand-computed example, the
+identity case in closed form, sigma_F against numerical error propagation,
+region-of-interest consistency, brute-force loops with threshold ties.
 """
 from __future__ import annotations
 
