@@ -60,9 +60,12 @@ ig_status ig_surrogate_get_grads(const ig_surrogate* s, float* host, int64_t cou
 ig_status ig_surrogate_train_step(ig_surrogate* s, const float* const* d_x, const float* const* d_t, int32_t batch,
                                   int64_t nx, int64_t ny, int64_t nz, void* hip_stream, double* loss);
 
-/* Predict y from x.  tile == 0: the whole cube at once.  tile > 0: cubes of
- * tile^3 outputs, each computed with a halo of `depth` voxels (the network's
- * receptive radius), which gives the same result as tile == 0. */
+/* Predict y from x.  tile > 0: cubes of tile^3 outputs, each computed with a
+ * halo of `depth` voxels (the network's receptive radius), which gives the
+ * same result as one piece; (tile + 2 depth)^3 x 32 must stay below 2^31
+ * (32-bit activation offsets).  tile == 0: the whole cube in one piece when
+ * voxels x 32 < 2^31, otherwise the smallest number of equal tiles along the
+ * longest axis that satisfies that bound (e.g. 256 for a 512^3 cube). */
 ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float* d_y, int64_t nx, int64_t ny, int64_t nz,
                              int32_t tile, void* hip_stream);
 

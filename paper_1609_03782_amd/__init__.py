@@ -47,6 +47,23 @@ class IgCompareResult(ctypes.Structure):
                 ("sum_x", ctypes.c_double), ("sum_ref", ctypes.c_double), ("n_over", ctypes.c_int64)]
 
 
+QMAX = 63   # IG_QUALITY_MAX_THR
+
+
+class IgQualityParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("n_thr", ctypes.c_int32), ("roi", ctypes.c_int64 * 6),
+                ("thr_f", ctypes.c_double * QMAX), ("thr_o", ctypes.c_double), ("rms_o", ctypes.c_double),
+                ("rms_f", ctypes.c_double), ("indep", ctypes.c_double)]
+
+
+class IgQualityResult(ctypes.Structure):
+    _fields_ = [("rms_o", ctypes.c_double), ("rms_f", ctypes.c_double), ("S_oo", ctypes.c_double),
+                ("S_m", ctypes.c_double), ("N_o", ctypes.c_int64), ("n_roi", ctypes.c_int64),
+                ("S_of", ctypes.c_double * QMAX), ("S_mf", ctypes.c_double * QMAX), ("N_f", ctypes.c_int64 * QMAX),
+                ("F", ctypes.c_double * QMAX), ("sigma_F", ctypes.c_double * QMAX), ("F_M", ctypes.c_double * QMAX),
+                ("sigma_FM", ctypes.c_double * QMAX)]
+
+
 # name -> (restype, argtypes); the exported C ABI
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -75,6 +92,8 @@ SIGNATURES = {
     "ig_reduce": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int, _P,
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64)]),
+    "ig_quality": (ctypes.c_int, [ctypes.POINTER(IgQualityParams), _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(IgQualityResult)]),
     "ig_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ig_last_error": (ctypes.c_char_p, []),
     "ig_version": (ctypes.c_char_p, []),
@@ -201,9 +220,13 @@ class Filter:
         self._h = h
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().ig_filter_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h:
             self._h = None
+            try:
+                lib().ig_filter_destroy(h)
+            except TypeError:   # interpreter shutdown: module globals are already gone
+                pass
 
     __del__ = close
 
@@ -338,3 +361,34 @@ def reduce(x):
                            x.device.index or 0, _stream_ptr(x), ctypes.byref(s), ctypes.byref(q),
                            ctypes.byref(b)), "ig_reduce")
     return s.value, q.value, b.value
+
+
+def quality(orig, filt, model=None, roi=None, thr_f=(3.0,), thr_o=3.0, rms_o=0.0, rms_f=0.0, indep=1.0):
+    """Section 6 diagnostics (F, sigma_F, F_M, sigma_FM per M_f threshold) of
+    FP32 device cubes (ig_quality).  roi = (x0, x1, y0, y1, z0, z1) or None."""
+    import torch
+    for t in (orig, filt) + ((model,) if model is not None else ()):
+        assert t.dtype == torch.float32 and t.is_contiguous() and t.shape == orig.shape
+    thr_f = list(thr_f)
+    q = IgQualityParams()
+    q.struct_size = ctypes.sizeof(IgQualityParams)
+    q.n_thr = len(thr_f)
+    if len(thr_f) > QMAX:
+        raise ValueError(f"at most {QMAX} thresholds")
+    for j, t in enumerate(thr_f):
+        q.thr_f[j] = float(t)
+    for j, v in enumerate(roi if roi is not None else (0,) * 6):
+        q.roi[j] = int(v)
+    q.thr_o, q.rms_o, q.rms_f, q.indep = float(thr_o), float(rms_o), float(rms_f), float(indep)
+    r = IgQualityResult()
+    nz, ny, nx = orig.shape
+    _check(lib().ig_quality(ctypes.byref(q), ctypes.c_void_p(orig.data_ptr()), ctypes.c_void_p(filt.data_ptr()),
+                            ctypes.c_void_p(model.data_ptr()) if model is not None else None, nx, ny, nz,
+                            orig.device.index or 0, _stream_ptr(orig), ctypes.byref(r)), "ig_quality")
+    k = len(thr_f)
+    return {"rms_o": r.rms_o, "rms_f": r.rms_f, "S_oo": r.S_oo, "N_o": r.N_o,
+            "S_m": r.S_m if model is not None else None, "n_roi": r.n_roi,
+            "S_of": list(r.S_of[:k]), "N_f": list(r.N_f[:k]), "S_mf": list(r.S_mf[:k]) if model is not None else [],
+            "F": list(r.F[:k]), "sigma_F": list(r.sigma_F[:k]),
+            "F_M": list(r.F_M[:k]) if model is not None else [],
+            "sigma_FM": list(r.sigma_FM[:k]) if model is not None else []}

@@ -27,7 +27,8 @@ struct Piece;
 
 // LDS bytes of the streaming kernel: current rows and up-edge terms of every
 // level, for every wavefront.
-inline size_t stream_lds_bytes(int V, int T, int W) { return (size_t)2 * T * W * 64 * V * sizeof(float); }
+// two regions of T levels, each level W + 2 row slots of 64 V floats
+inline size_t stream_lds_bytes(int V, int T, int W) { return (size_t)2 * T * (W + 2) * 64 * V * sizeof(float); }
 constexpr size_t kMaxLds = 160 * 1024;
 
 hipError_t launch_sum_partial(int dtype, const void* x, long n, double* part, int nblk, hipStream_t s);

@@ -1,0 +1,234 @@
+// Filtering-quality diagnostics (Section 6): masked FP64 sums over a region
+// of interest for a sweep of mask thresholds, then F, sigma_F, F_M, sigma_FM.
+// See include/igquality.h.
+//
+// Work split: lane j of every wavefront owns mask threshold j (lanes below
+// n_thr: the M_f thresholds on the filtered cube; lane 63: the M_o threshold
+// on the original, which also accumulates the unmasked model sum).  A
+// wavefront takes 64-voxel chunks of the ROI in a fixed order, parks each
+// chunk's three values (original, filtered, model) in its LDS slice as FP64,
+// and every lane then walks the 64 voxels in order, adding the ones its mask
+// admits.  Each lane's sums are therefore sequential in a fixed order; the
+// per-wavefront partials are folded in wavefront order by one workgroup.  No
+// atomics: bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "igquality.h"
+#include "internal.h"
+
+namespace igk {
+
+struct QGeom {
+    long nx, ny;          // row and plane strides of the cube
+    long x0, y0, z0;      // ROI origin
+    long rx, ry;          // ROI extents in x and y
+    long nroi;            // voxels in the ROI
+    int has_model;
+    int pad;
+    double thr[64];       // absolute threshold per lane (+inf: lane unused)
+};
+
+constexpr int kQWaves = 4;         // wavefronts per workgroup
+constexpr int kQMaxBlocks = 1024;
+
+__global__ void __launch_bounds__(256)
+k_quality_partial(const float* __restrict__ orig, const float* __restrict__ filt, const float* __restrict__ model,
+                  QGeom g, double* __restrict__ part, unsigned* __restrict__ cnt) {
+    __shared__ double vals[kQWaves][64][3];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const long nw = (long)gridDim.x * kQWaves;
+    const long gw = (long)blockIdx.x * kQWaves + wid;
+    const double thr = g.thr[lane];
+    const bool mo = lane == 63;
+    double a1 = 0.0, a2 = 0.0;
+    unsigned c = 0;
+    for (long ch = gw; ch * 64 < g.nroi; ch += nw) {
+        const long r = ch * 64 + lane;
+        double vo = 0.0, vf = 0.0, vm = 0.0;
+        if (r < g.nroi) {
+            const long x = r % g.rx, t = r / g.rx;
+            const long y = t % g.ry, z = t / g.ry;
+            const long idx = (g.x0 + x) + g.nx * ((g.y0 + y) + g.ny * (g.z0 + z));
+            vo = (double)orig[idx];
+            vf = (double)filt[idx];
+            if (g.has_model) vm = (double)model[idx];
+        }
+        vals[wid][lane][0] = vo;
+        vals[wid][lane][1] = vf;
+        vals[wid][lane][2] = vm;
+        __builtin_amdgcn_wave_barrier();
+        const int nv = (int)min(64L, g.nroi - ch * 64);
+        for (int k = 0; k < nv; ++k) {
+            const double so = vals[wid][k][0], sf = vals[wid][k][1], sm = vals[wid][k][2];
+            const bool pass = mo ? (so >= thr) : (sf >= thr);
+            a1 += pass ? so : 0.0;
+            a2 += (pass || mo) ? sm : 0.0;
+            c += pass ? 1u : 0u;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    const long o = gw * 64 + lane;
+    part[2 * o] = a1;
+    part[2 * o + 1] = a2;
+    cnt[o] = c;
+}
+
+// One wavefront: lane j folds the partials of threshold j in wavefront order
+// and derives the diagnostics.
+__global__ void __launch_bounds__(64)
+k_quality_final(const double* __restrict__ part, const unsigned* __restrict__ cnt, long nw, int nthr, int has_model,
+                double rms_o, double rms_f, double indep, long nroi, ig_quality_result* __restrict__ out) {
+    const int j = threadIdx.x;
+    double s1 = 0.0, s2 = 0.0;
+    long long n = 0;
+    for (long w = 0; w < nw; ++w) {
+        s1 += part[2 * (w * 64 + j)];
+        s2 += part[2 * (w * 64 + j) + 1];
+        n += cnt[w * 64 + j];
+    }
+    // lane 63 holds S_oo, S_m, N_o
+    const double S_oo = __shfl(s1, 63, 64);
+    const double S_m = __shfl(s2, 63, 64);
+    const long long N_o = __shfl(n, 63, 64);
+    const double nan = __builtin_nan("");
+    if (j == 63) {
+        out->rms_o = rms_o;
+        out->rms_f = rms_f;
+        out->S_oo = S_oo;
+        out->S_m = has_model ? S_m : 0.0;
+        out->N_o = N_o;
+        out->n_roi = nroi;
+    }
+    if (j < IG_QUALITY_MAX_THR) {
+        const bool on = j < nthr;
+        const double sig_oo = sqrt((double)N_o / indep) * rms_o;
+        const double sig_of = sqrt((double)n / indep) * rms_f;
+        double F = nan, sF = nan, FM = nan, sFM = nan;
+        if (on && S_oo != 0.0) {
+            F = fabs(s1) / fabs(S_oo);
+            sF = sqrt(sig_of * sig_of / (S_oo * S_oo) + s1 * s1 * sig_oo * sig_oo / (S_oo * S_oo * S_oo * S_oo));
+        }
+        if (on && has_model && S_m != 0.0) {
+            FM = fabs(s2) / fabs(S_m);
+            sFM = sig_of / fabs(S_m);
+        }
+        out->S_of[j] = on ? s1 : 0.0;
+        out->S_mf[j] = on && has_model ? s2 : 0.0;
+        out->N_f[j] = on ? n : 0;
+        out->F[j] = F;
+        out->sigma_F[j] = sF;
+        out->F_M[j] = FM;
+        out->sigma_FM[j] = sFM;
+    }
+}
+
+}  // namespace igk
+
+// ====================================================================== host
+using namespace igk;
+#define fail igk_fail
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? IG_ERR_OUT_OF_MEMORY : IG_ERR_DEVICE, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                             \
+    } while (0)
+
+namespace {
+
+struct QScratch {   // per-device partials and result slot, kept for the process
+    double* part = nullptr;
+    unsigned* cnt = nullptr;
+    ig_quality_result* res = nullptr;
+};
+std::mutex g_qmu;
+QScratch g_qs[64];
+
+ig_status noise_level(const float* d, long n, int device, void* stream, double given, double* rms) {
+    if (given > 0.0) {
+        *rms = given;
+        return IG_OK;
+    }
+    double sum = 0.0, sumsq = 0.0;
+    int64_t bad = 0;
+    ig_status st = ig_reduce(d, IG_F32, n, device, stream, &sum, &sumsq, &bad);
+    if (st != IG_OK) return st;
+    if (bad) return fail(IG_ERR_NONFINITE, "a cube whose rms is to be estimated holds %lld non-finite voxels",
+                         (long long)bad);
+    *rms = n > 0 ? std::sqrt(sumsq / (double)n) : 0.0;
+    return IG_OK;
+}
+
+}  // namespace
+
+extern "C" ig_status ig_quality(const ig_quality_params* q, const float* d_orig, const float* d_filt,
+                                const float* d_model, int64_t nx, int64_t ny, int64_t nz, int device,
+                                void* hip_stream, ig_quality_result* out) {
+    if (!q || !out || !d_orig || !d_filt) return fail(IG_ERR_INVALID_ARG, "NULL argument");
+    if (q->struct_size != (int32_t)sizeof(ig_quality_params)) return fail(IG_ERR_INVALID_ARG, "struct_size");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(IG_ERR_INVALID_ARG, "bad cube size");
+    if (q->n_thr < 1 || q->n_thr > IG_QUALITY_MAX_THR) return fail(IG_ERR_INVALID_ARG, "n_thr out of range");
+    for (int j = 0; j < q->n_thr; ++j)
+        if (!std::isfinite(q->thr_f[j])) return fail(IG_ERR_INVALID_ARG, "thr_f[%d] is not finite", j);
+    if (!std::isfinite(q->thr_o)) return fail(IG_ERR_INVALID_ARG, "thr_o is not finite");
+    if (!(q->indep > 0.0) || !std::isfinite(q->indep)) return fail(IG_ERR_INVALID_ARG, "indep must be > 0");
+    if (!std::isfinite(q->rms_o) || !std::isfinite(q->rms_f)) return fail(IG_ERR_INVALID_ARG, "rms not finite");
+    int64_t r[6] = {q->roi[0], q->roi[1], q->roi[2], q->roi[3], q->roi[4], q->roi[5]};
+    if (!(r[0] | r[1] | r[2] | r[3] | r[4] | r[5])) {
+        r[1] = nx; r[3] = ny; r[5] = nz;
+    }
+    if (r[0] < 0 || r[1] > nx || r[0] >= r[1] || r[2] < 0 || r[3] > ny || r[2] >= r[3] || r[4] < 0 || r[5] > nz ||
+        r[4] >= r[5])
+        return fail(IG_ERR_INVALID_ARG, "ROI empty or outside the cube");
+    if (device < 0 || device >= 64) return fail(IG_ERR_INVALID_ARG, "bad device %d", device);
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice(%d)", device);
+    struct Restore { int d; ~Restore() { if (d >= 0) (void)hipSetDevice(d); } } restore{prev};
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    const long n = (long)(nx * ny * nz);
+    double rms_o = 0.0, rms_f = 0.0;
+    ig_status st = noise_level(d_orig, n, device, hip_stream, q->rms_o, &rms_o);
+    if (st != IG_OK) return st;
+    st = noise_level(d_filt, n, device, hip_stream, q->rms_f, &rms_f);
+    if (st != IG_OK) return st;
+
+    QGeom g{};
+    g.nx = nx; g.ny = ny;
+    g.x0 = r[0]; g.y0 = r[2]; g.z0 = r[4];
+    g.rx = r[1] - r[0]; g.ry = r[3] - r[2];
+    g.nroi = g.rx * g.ry * (r[5] - r[4]);
+    g.has_model = d_model != nullptr;
+    for (int j = 0; j < 64; ++j) g.thr[j] = INFINITY;
+    for (int j = 0; j < q->n_thr; ++j) g.thr[j] = q->thr_f[j] * rms_f;
+    g.thr[63] = q->thr_o * rms_o;
+
+    const long chunks = (g.nroi + 63) / 64;
+    const int blocks = (int)std::min<long>(kQMaxBlocks, (chunks + kQWaves - 1) / kQWaves);
+    const long nw = (long)blocks * kQWaves;
+
+    std::lock_guard<std::mutex> lk(g_qmu);
+    QScratch& qs = g_qs[device];
+    if (!qs.part) {
+        HIP_TRY(hipMalloc((void**)&qs.part, (size_t)kQMaxBlocks * kQWaves * 64 * 2 * sizeof(double)));
+        HIP_TRY(hipMalloc((void**)&qs.cnt, (size_t)kQMaxBlocks * kQWaves * 64 * sizeof(unsigned)));
+        HIP_TRY(hipMalloc((void**)&qs.res, sizeof(ig_quality_result)));
+    }
+    hipLaunchKernelGGL(k_quality_partial, dim3(blocks), dim3(64 * kQWaves), 0, s, d_orig, d_filt, d_model, g, qs.part,
+                       qs.cnt);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_quality_final, dim3(1), dim3(64), 0, s, qs.part, qs.cnt, nw, q->n_thr, g.has_model, rms_o,
+                       rms_f, q->indep, g.nroi, qs.res);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, qs.res, sizeof(ig_quality_result), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return IG_OK;
+}

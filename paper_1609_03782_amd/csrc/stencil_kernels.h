@@ -2,19 +2,18 @@
 //
 //  k_naive   one step per launch, one voxel per thread, neighbours straight
 //            from global memory.  The reference schedule.
-//  k_blocked t_block steps per launch.  A workgroup owns an xy tile (halo of
-//            t_block voxels where it borders another tile) and a chunk of
-//            z-planes; it streams the planes in z order, keeping every
-//            intermediate step of the pass on chip:
-//              lane      -> V consecutive x voxels (one 16-byte load for V=8
-//                           in 16-bit storage, two for FP32);
-//              wavefront -> R consecutive rows; x neighbours cross lanes by
-//                           DPP wave shifts, so an x edge term is computed once;
-//              workgroup -> W wavefronts stacked in y; the first and last row
-//                           of each wavefront go through LDS to its neighbours;
-//              z         -> each step level keeps its current plane and the
-//                           edge term to the plane below in registers, so a z
-//                           edge term is computed once.
+//  k_stream  T steps per launch.  A workgroup owns an xy tile (halo of T
+//            voxels where it borders another tile) and a range of z-planes;
+//            it streams the planes in z order, keeping every intermediate
+//            step of the pass on chip:
+//              lane      -> V consecutive x voxels (two 16-byte loads for
+//                           V = 8 in FP32, one in 16-bit storage);
+//              wavefront -> one row; x neighbours cross lanes by DPP wave
+//                           shifts, so an x edge term is computed once;
+//              workgroup -> W wavefronts stacked in y, rows shared in LDS;
+//              z         -> each level keeps its current plane, the plane
+//                           above and the edge term to the plane below in
+//                           registers, so a z edge term is computed once.
 //            Level t of a pass turns plane p of level t-1 into plane p of
 //            level t as soon as plane p+1 of level t-1 exists; the last level
 //            is written to global memory.  Rows, columns and planes that a
@@ -159,28 +158,48 @@ template <int V> struct Vec<__half, V> : Vec16<__half, V> {};
 // One workgroup = W wavefronts = W consecutive rows of a tile; one row per
 // wavefront, V voxels per lane (a row spans 64*V voxels).  Work comes from a
 // host-built piece table: piece b is (x tile, y tile, z0, z1) with outputs in
-// planes [z0, z1).  Per step s the workgroup
-//   phase 1: takes the input plane loaded two steps earlier, issues the load
-//            of plane s+2, and advances every level by one plane: level L
-//            turns plane p of level L-1 into plane p of level L from its own
-//            row (x edges via DPP), the y edge terms to the rows below
-//            (LDS, computed by the wavefront below) and above (own, from the
-//            previous step), and the z edge terms (registers);
-//   phase 2: publishes each level's new current row to LDS;   barrier
-//   phase 3: computes the y edge term to the row above for each level's new
-//            current row and publishes it;                      barrier
-// so every edge term of the pass is evaluated exactly once per level.
+// planes [z0, z1).  Per step s the workgroup takes the input plane loaded one
+// step earlier, issues the load of the next one, and advances every level by
+// one plane: level L turns plane p of level L-1 into plane p of level L from
+// its own row (x edges inside the lane and via DPP across lanes), the rows
+// above and below at level L (y edges, through LDS) and the planes above and
+// below (z edges, registers; the edge to the plane below is the one computed
+// one step earlier).  Two ways to share the y edges:
+//
+//  edge-shared (exponential and rational conductances, where an edge term
+//  costs an exponential or a reciprocal): each level's new row is published
+//  to LDS (barrier), each wavefront computes the edge term to the row above
+//  and publishes it (barrier); every y edge term is evaluated once.
+//
+//  row-shared (intensity conductance, where an edge term is one product):
+//  each level's new row is published to one of two LDS buffers by step
+//  parity (one barrier); each wavefront computes both of its y edge terms
+//  itself from the rows above and below.  An edge term depends only on the
+//  two voxels' values, so both wavefronts obtain the same bits.
+//
+// LDS holds, per level, W+2 row slots of 64*V floats: wavefront w uses slot
+// w+1, slots 0 and W+1 hold zeros so the wavefronts at the tile's edge read
+// without a branch (their edge coefficient is the closed one, or the row is
+// halo).  Element i of a lane's chunk sits at i*64 + lane: consecutive lanes
+// hit consecutive banks.
 struct Piece {
     int tx, ty, z0, z1;
 };
 
+// Which of the two y edge schemes a conductance uses (above).
+template <int COND>
+constexpr bool y_row_shared() {
+    return COND == COND_INTENSITY;
+}
+
 // One piece of one pass: the whole per-workgroup algorithm above.  `lds`
 // must hold stream_lds_bytes(V, T, W) bytes.  Called by k_stream (one cube)
-// and by the persistent batch kernel.
+// and by the batch round kernel.
 template <int COND, typename ST, int V, int T, bool VEC>
 __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __restrict__ dst, const BlockGeom& g,
                                              const Piece pc, const DevParams& P, float* __restrict__ lds) {
     constexpr int RX = 64 * V;
+    constexpr bool RS = y_row_shared<COND>();
     const int lane = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int W = g.W;
@@ -211,6 +230,7 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
         }
     }
     const float cyu = (y >= 0 && y + 1 < ny) ? P.coef[1] : P.closed;   // edge (y, y+1)
+    const float cyd = (y >= 1 && y < ny) ? P.coef[1] : P.closed;       // edge (y-1, y)
     const bool row_in = y >= 0 && y < ny;
     const bool row_store = y >= oy0 && y < oy1;
     const int lo_base = ry0 <= 0 ? 0 : ry0;
@@ -223,18 +243,18 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     const ST* rowp = src + (long)ycl * nx;
     const int xv = min(max(xl0, 0), nx - V);
 
-    // element i of this lane's chunk sits at i*64 + lane: consecutive lanes
-    // hit consecutive banks (no bank conflicts)
-    const int row_off = w * RX + lane;                   // + t * W * RX + i * 64
-    const int edge_base = T * W * RX;
-    const int lvl = W * RX;
+    // LDS regions of T levels each (lvl floats per level): edge-shared uses
+    // region 0 for rows and region 1 for up-edge terms; row-shared uses them
+    // as the two parity buffers of rows.
+    const int lvl = (W + 2) * RX;
+    const int reg1 = T * lvl;
+    const int slot = (w + 1) * RX + lane;            // + t * lvl + i * 64 (+ reg1)
 
     // Register rotation (the step loop is unrolled by two, parity p known at
     // compile time): lv[t][p] is level t's current plane and lv[t][p^1] the
     // plane above it; level t writes its result straight into lv[t+1][p^1],
     // and the next step swaps the roles, so no plane is copied between
-    // registers.
-    // one above.  Only the prefetched input plane is copied into lv[0][p^1].
+    // registers.  Only the prefetched input plane is copied into lv[0][p^1].
     // fz[t] is the z edge term below the current plane of level t.
     float lv[T][2][V], fz[T][V];
 #pragma unroll
@@ -245,10 +265,17 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
             lv[t][1][i] = 0.0f;
             fz[t][i] = 0.0f;
         }
+    // zero this wavefront's slots and, from wavefront 0, the pad slots
 #pragma unroll
-    for (int t = 0; t < T; ++t)
+    for (int r = 0; r < 2 * T; ++r)
 #pragma unroll
-        for (int i = 0; i < V; ++i) lds[edge_base + t * lvl + row_off + 64 * i] = 0.0f;
+        for (int i = 0; i < V; ++i) {
+            lds[r * lvl + slot + 64 * i] = 0.0f;
+            if (w == 0) {
+                lds[r * lvl + lane + 64 * i] = 0.0f;
+                lds[r * lvl + (W + 1) * RX + lane + 64 * i] = 0.0f;
+            }
+        }
 
     float pf[V];
     auto load = [&](int z) {
@@ -281,7 +308,7 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
         }
         if (s + 1 < nin) load(zin0 + s + 1);
 
-        // phase 1: every level advances one plane
+        // every level advances one plane
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const bool has_nxt = STEADY || ((s - t >= 0) && (s - t < nin));
@@ -297,13 +324,20 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
             const float right = lane_shl1(lv[t][p][0]);
             ex[V - 1] = edge_term<COND>(right - lv[t][p][V - 1], cx[VEC ? 0 : V - 1], P.kap);
             const float exm0 = lane_shr1(ex[V - 1]);
-            const int eo = edge_base + t * lvl + row_off;
+            // rows of this level's current plane (published one step earlier)
+            const int ro = (RS ? p * reg1 : reg1) + t * lvl + slot;
             float out[V];
 #pragma unroll
             for (int i = 0; i < V; ++i) {
-                const float eyd = w > 0 ? lds[eo - RX + 64 * i] : 0.0f;
-                const float eyu = lds[eo + 64 * i];
                 const float c = lv[t][p][i];
+                float eyd, eyu;
+                if constexpr (RS) {
+                    eyd = edge_term<COND>(c - lds[ro - RX + 64 * i], cyd, P.kap);
+                    eyu = edge_term<COND>(lds[ro + RX + 64 * i] - c, cyu, P.kap);
+                } else {
+                    eyd = lds[ro - RX + 64 * i];
+                    eyu = lds[ro + 64 * i];
+                }
                 const float up_z = has_nxt ? lv[t][q][i] : c;
                 const float ezp = edge_term<COND>(up_z - c, czp, P.kap);
                 const float o = combine<COND>(c, i == 0 ? exm0 : ex[i - 1], ex[i], eyd, eyu, fz[t][i], ezp,
@@ -325,28 +359,29 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
                 }
             }
         }
-        // phase 2: publish each level's new current row (lv[t][q])
+        // publish each level's new current row (lv[t][q])
+        const int wo = (RS ? q * reg1 : 0) + slot;
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             if (STEADY || ((s - t >= 0) && (s - t < nin))) {
 #pragma unroll
-                for (int i = 0; i < V; ++i) lds[t * lvl + row_off + 64 * i] = lv[t][q][i];
+                for (int i = 0; i < V; ++i) lds[wo + t * lvl + 64 * i] = lv[t][q][i];
             }
         }
         __syncthreads();
-        // phase 3: y edge term from the new current row to the row above
+        if constexpr (!RS) {
+            // y edge term from the new current row to the row above
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            if (STEADY || ((s - t >= 0) && (s - t < nin))) {
-                const int ro = t * lvl + row_off;
+            for (int t = 0; t < T; ++t) {
+                if (STEADY || ((s - t >= 0) && (s - t < nin))) {
+                    const int ro = t * lvl + slot;
 #pragma unroll
-                for (int i = 0; i < V; ++i) {
-                    const float up = w + 1 < W ? lds[ro + RX + 64 * i] : lv[t][q][i];
-                    lds[edge_base + ro + 64 * i] = edge_term<COND>(up - lv[t][q][i], cyu, P.kap);
+                    for (int i = 0; i < V; ++i)
+                        lds[reg1 + ro + 64 * i] = edge_term<COND>(lds[ro + RX + 64 * i] - lv[t][q][i], cyu, P.kap);
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
@@ -381,8 +416,6 @@ template <int COND, typename ST, int V, int T, bool VEC>
 __global__ void __launch_bounds__(1024)
 k_stream(const ST* __restrict__ src, ST* __restrict__ dst, BlockGeom g, const Piece* __restrict__ pieces,
          const DevParams* __restrict__ dp) {
-    // LDS: rows[T][W][64V] (current row of each level) then edges[T][W][64V]
-    // (y edge term from that row to the row above)
     extern __shared__ float lds[];
     const DevParams P = *dp;
     if (P.abort) return;

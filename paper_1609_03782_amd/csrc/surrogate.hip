@@ -396,6 +396,23 @@ extern "C" ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float
     if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
     hipStream_t st = (hipStream_t)hip_stream;
     const long n = nx * ny * nz;
+    const int H = s->L;   // receptive radius
+    // activations are addressed with 32-bit offsets: voxels x 32 channels < 2^31
+    auto fits = [&](long t) {
+        const long d = t + 2 * H;
+        return std::min(nx, d) * std::min(ny, d) * std::min(nz, d) < (1LL << 31) / 32;
+    };
+    if (tile == 0 && n >= (1LL << 31) / 32) {
+        // the smallest number of equal tiles along the longest axis that fits
+        const long big = std::max(nx, std::max(ny, nz));
+        for (long k = 2; k <= big; ++k) {
+            const long t = (big + k - 1) / k;
+            if (fits(t)) { tile = (int)t; break; }
+        }
+        if (tile == 0) return fail(IG_ERR_UNSUPPORTED, "no tile size fits");
+    }
+    if (tile > 0 && !(tile >= nx && tile >= ny && tile >= nz) && !fits(tile))
+        return fail(IG_ERR_INVALID_ARG, "tile %d too large (tile + 2 depth)^3 x 32 must stay below 2^31", tile);
     if (tile == 0 || (tile >= nx && tile >= ny && tile >= nz)) {
         if (n >= (1LL << 31) / 32) return fail(IG_ERR_INVALID_ARG, "cube too large for one piece; use tiles");
         ig_status rc = ensure_acts(s, n);
@@ -404,7 +421,6 @@ extern "C" ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float
         if (rc != IG_OK) return rc;
         return forward(s, d_x, d_y, nx, ny, nz, false, st);
     }
-    const int H = s->L;   // receptive radius
     const long dmax = (long)tile + 2 * H;
     ig_status rc = ensure_acts(s, dmax * dmax * dmax);
     if (rc != IG_OK) return rc;

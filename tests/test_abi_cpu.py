@@ -106,3 +106,46 @@ def test_gpu_test_schedules_are_valid():
         assert ig.schedule_check(g.INPLACE_SHAPE, s, n_iter=5) is None, s
     assert ig.schedule_check((17, 33, 66), dict(kind="blocked", t_block=4, waves=8)) is not None
     assert ig.schedule_check((17, 33, 600), dict(kind="blocked", t_block=4, waves=16, vec=8)) is not None
+
+
+def test_quality_struct_layouts_match_c(tmp_path):
+    src = tmp_path / "q.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "igquality.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(ig_quality_params), '
+                   'sizeof(ig_quality_result), offsetof(ig_quality_params, indep), '
+                   'offsetof(ig_quality_result, N_f), offsetof(ig_quality_result, sigma_FM));return 0;}\n')
+    exe = tmp_path / "q"
+    subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(ig.IgQualityParams), ctypes.sizeof(ig.IgQualityResult), ig.IgQualityParams.indep.offset,
+            ig.IgQualityResult.N_f.offset, ig.IgQualityResult.sigma_FM.offset]
+    assert got == want
+
+
+def _qparams(**kw):
+    q = ig.IgQualityParams()
+    q.struct_size = ctypes.sizeof(ig.IgQualityParams)
+    q.n_thr = 1
+    q.thr_f[0] = 3.0
+    q.thr_o = 3.0
+    q.indep = 1.0
+    for k, v in kw.items():
+        if k == "roi":
+            for j, x in enumerate(v):
+                q.roi[j] = x
+        else:
+            setattr(q, k, v)
+    return q
+
+
+@pytest.mark.parametrize("kw", [dict(n_thr=0), dict(n_thr=64), dict(indep=0.0), dict(thr_o=float("nan")),
+                                dict(struct_size=16), dict(roi=(0, 9, 0, 4, 0, 4)), dict(roi=(3, 3, 0, 4, 0, 4)),
+                                dict(roi=(-1, 2, 0, 4, 0, 4)), dict(rms_f=float("inf"))])
+def test_quality_rejects_invalid_arguments(kw):
+    q = _qparams(**kw)
+    r = ig.IgQualityResult()
+    fake = ctypes.c_void_p(4096)   # never dereferenced: validation fails first
+    rc = ig.lib().ig_quality(ctypes.byref(q), fake, fake, None, 8, 4, 4, 0, None, ctypes.byref(r))
+    assert rc == ig.IG_ERR_INVALID_ARG, kw
+    rc = ig.lib().ig_quality(ctypes.byref(_qparams()), None, fake, None, 8, 4, 4, 0, None, ctypes.byref(r))
+    assert rc == ig.IG_ERR_INVALID_ARG

@@ -79,7 +79,7 @@ SCHEDS = [
     dict(kind="blocked", t_block=1, waves=3, zchunk=3, vec=1),
     dict(kind="blocked", t_block=2, waves=5, zchunk=5, vec=1),
     dict(kind="blocked", t_block=3, waves=8, zchunk=7, vec=2),
-    dict(kind="blocked", t_block=4, waves=9, zchunk=0, vec=0),
+    dict(kind="blocked", t_block=4, waves=9, zchunk=0, vec=4),
     dict(kind="blocked", t_block=2, waves=6, zchunk=4, vec=4),
     dict(kind="blocked", t_block=3, waves=10, zchunk=9, vec=8),
     dict(kind="blocked", t_block=2, waves=16, zchunk=0, vec=0, rounds=3),
@@ -132,7 +132,7 @@ def test_identity_cases_bitwise(dev):
 INPLACE_SHAPE = (17, 33, 66)
 INPLACE_SCHEDS = [dict(kind="naive"), dict(kind="blocked", t_block=1, waves=4, zchunk=8),
                   dict(kind="blocked", t_block=2, waves=8, zchunk=8),
-                  dict(kind="blocked", t_block=4, waves=9, zchunk=0)]
+                  dict(kind="blocked", t_block=4, waves=9, zchunk=0, vec=4)]
 
 
 def test_in_place_and_odd_passes(dev, oracle_lib):

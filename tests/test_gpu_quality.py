@@ -1,0 +1,134 @@
+"""GPU quality diagnostics (ig_quality) against the FP64 oracle of Section 6:
+mask counts bit-exact, FP64 sums within the summation error bound, F and
+F_M to rounding; regions of interest with ragged sizes, threshold ties,
+estimated noise levels, and the full 512^3 cube."""
+import math
+
+import numpy as np
+import pytest
+
+import igsynth
+from oracle import quality as Q
+
+pytestmark = pytest.mark.gpu
+SWEEP = tuple(np.round(np.arange(0.0, 4.5001, 0.1), 10))   # 46 thresholds, 0 to 4.5 rms
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1609_03782_amd as ig
+    ig.lib()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+def _close(a, b, tol):
+    return (math.isnan(a) and math.isnan(b)) or abs(a - b) <= tol
+
+
+def _check(got, ref, orig, model, roi):
+    """Counts bit-exact; each FP64 sum within the recursive-summation bound
+    2 n u sum|x| (any order); F, sigma_F, F_M within what those sum errors
+    allow after first-order propagation."""
+    sub = Q._roi(orig, roi)
+    n = sub.size
+    eps = 2.0 * n * 2.0 ** -53
+    bound_o = eps * float(np.abs(sub).sum()) + 1e-300
+    assert got["N_o"] == ref["N_o"]
+    assert got["N_f"] == ref["N_f"]
+    assert abs(got["S_oo"] - ref["S_oo"]) <= bound_o
+    rel_oo = bound_o / abs(ref["S_oo"]) if ref["S_oo"] else 0.0
+    for k, (a, b) in enumerate(zip(got["S_of"], ref["S_of"])):
+        assert abs(a - b) <= bound_o
+        rel_of = bound_o / abs(b) if b else 0.0
+        F = ref["F"][k]
+        assert _close(got["F"][k], F, F * (rel_of + rel_oo) + 1e-14 if F == F else 0)
+        sF = ref["sigma_F"][k]
+        assert _close(got["sigma_F"][k], sF, sF * 3 * (rel_of + rel_oo) + 1e-14 if sF == sF else 0)
+    if model is not None:
+        msub = Q._roi(model, roi)
+        bound_m = eps * float(np.abs(msub).sum()) + 1e-300
+        assert abs(got["S_m"] - ref["S_m"]) <= bound_m
+        rel_m = bound_m / abs(ref["S_m"]) if ref["S_m"] else 0.0
+        for k, (a, b) in enumerate(zip(got["S_mf"], ref["S_mf"])):
+            assert abs(a - b) <= bound_m
+            rel_mf = bound_m / abs(b) if b else 0.0
+            FM = ref["F_M"][k]
+            assert _close(got["F_M"][k], FM, FM * (rel_mf + rel_m) + 1e-14 if FM == FM else 0)
+            sFM = ref["sigma_FM"][k]
+            assert _close(got["sigma_FM"][k], sFM, sFM * (rel_m + 1e-12) + 1e-14 if sFM == sFM else 0)
+
+
+@pytest.mark.parametrize("roi", [None, (3, 40, 1, 30, 2, 25), (5, 6, 7, 8, 9, 10), (0, 63, 0, 1, 0, 1),
+                                 (1, 66, 2, 3, 0, 1)])
+def test_quality_matches_oracle(dev, roi):
+    import paper_1609_03782_amd as ig
+    rng = np.random.default_rng(17)
+    shape = (27, 33, 70)
+    model = np.zeros(shape)
+    model[8:20, 10:25, 20:50] = 2.0 + rng.random((12, 15, 30))
+    orig = (model + rng.standard_normal(shape)).astype(np.float32)
+    filt = (model * 1.2 + 0.4 * rng.standard_normal(shape)).astype(np.float32)
+    model = model.astype(np.float32)
+    ref = Q.quality(orig, filt, model, roi=roi, thr_f=SWEEP, rms_o=1.05, rms_f=0.7)
+    got = ig.quality(_t(orig, dev), _t(filt, dev), _t(model, dev), roi=roi, thr_f=SWEEP, rms_o=1.05, rms_f=0.7)
+    _check(got, ref, orig, model, roi)
+    assert got["n_roi"] == Q._roi(orig, roi).size
+
+
+def test_quality_ties_and_estimated_rms(dev):
+    import paper_1609_03782_amd as ig
+    rng = np.random.default_rng(5)
+    shape = (9, 10, 11)
+    orig = rng.integers(-4, 9, size=shape).astype(np.float32)
+    filt = rng.integers(-3, 10, size=shape).astype(np.float32)
+    thr = (0.0, 1.0, 2.5, 3.0, 4.5, -2.0)
+    ref = Q.quality(orig, filt, None, thr_f=thr, rms_o=1.0, rms_f=2.0)
+    got = ig.quality(_t(orig, dev), _t(filt, dev), None, thr_f=thr, rms_o=1.0, rms_f=2.0)
+    _check(got, ref, orig, None, None)
+    assert got["F_M"] == [] and got["S_m"] is None
+    # noise levels estimated on the GPU: plain rms of each whole cube
+    orig2 = rng.standard_normal((20, 21, 22)).astype(np.float32) * 1.3
+    filt2 = orig2 * 0.8
+    got = ig.quality(_t(orig2, dev), _t(filt2, dev), None, thr_f=SWEEP)
+    ref = Q.quality(orig2, filt2, None, thr_f=SWEEP)
+    assert got["rms_o"] == pytest.approx(ref["rms_o"], rel=1e-13)
+    assert got["rms_f"] == pytest.approx(ref["rms_f"], rel=1e-13)
+    _check(got, ref, orig2, None, None)
+
+
+def test_quality_of_the_filter_on_a_galaxy_cube(dev):
+    """F of the exponential filter's output on the small synthetic cube, with the
+    noiseless model known: the library's filter, then the diagnostics."""
+    import torch
+    import paper_1609_03782_amd as ig
+    cube = igsynth.cube_small(seed=1)
+    x = _t(cube, dev)
+    f = ig.Filter(cube.shape, K=2.0, tau=1 / 16, n_iter=10)
+    y = f.run(x)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    model = np.clip(cube, 0, None).astype(np.float32)          # a positive stand-in for the model cube
+    got = ig.quality(x, y, _t(model, dev), thr_f=SWEEP)
+    ref = Q.quality(cube, yh, model, thr_f=SWEEP)
+    _check(got, ref, cube, model, None)
+
+
+def test_quality_fullsize(dev):
+    import paper_1609_03782_amd as ig
+    cube = igsynth.cube_field(512, seed=2)
+    rng = np.random.default_rng(1)
+    filt = (cube * 0.9 + 0.1 * rng.standard_normal(cube.shape, dtype=np.float32)).astype(np.float32)
+    thr = (0.0, 1.5, 3.0, 4.5)
+    roi = (100, 400, 50, 450, 10, 500)
+    got = ig.quality(_t(cube, dev), _t(filt, dev), None, roi=roi, thr_f=thr)
+    ref = Q.quality(cube, filt, None, roi=roi, thr_f=thr, rms_o=got["rms_o"], rms_f=got["rms_f"])
+    assert got["rms_o"] == pytest.approx(Q.plain_rms(cube), rel=1e-11)
+    _check(got, ref, cube, None, roi)

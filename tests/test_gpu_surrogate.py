@@ -158,6 +158,23 @@ def test_network_forward_and_tiling(dev):
     assert err.max() <= 2e-2 * np.abs(ref - x).max()
 
 
+def test_large_cube_auto_tiles(dev):
+    """A cube whose activations exceed 32-bit offsets (voxels x 32 >= 2^31)
+    is tiled by the library when tile == 0; tiling is exact, so the result
+    equals an explicit tiling bit for bit."""
+    import torch
+    from paper_1609_03782_amd import surrogate as sg
+    net = sg.Surrogate(depth=8, seed=5)
+    x = torch.randn(257, 512, 512, device=dev)       # 6.74e7 voxels: 32 x voxels > 2^31
+    y0 = net.infer(x)                                # library-picked tiles (256)
+    y1 = net.infer(x, tile=200)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    assert bool(torch.isfinite(y0).all())
+    with pytest.raises(Exception):
+        net.infer(x, tile=500)                       # (500 + 16)^2 x 257 x 32 >= 2^31
+
+
 def test_training_gradient_matches_oracle(dev):
     import torch
     from paper_1609_03782_amd import surrogate as sg
