@@ -165,6 +165,14 @@ ig_status ig_filter_get_timing(ig_filter* f, double* total_ms, int64_t* launches
 ig_status ig_schedule_plan(const ig_params* p, const ig_schedule* s, int32_t t_block, int32_t ncu,
                            int32_t* geom, int32_t* pieces, int64_t cap, int64_t* count);
 
+/* Replace the filter parameters of f (conductance, K, tau, n_iter, C, rms) in
+ * place.  The shape and storage type must stay those f was created with
+ * (else IG_ERR_INVALID_ARG); the scratch cube, the schedule and its piece
+ * tables are kept, so a series of runs with different parameters on one cube
+ * (a parameter sweep) allocates nothing.  Host only; not to be called while
+ * a run of f is being enqueued from another thread. */
+ig_status ig_filter_set_params(ig_filter* f, const ig_params* p);
+
 /* Release the handle and its device memory (NULL is a no-op). */
 void ig_filter_destroy(ig_filter* f);
 

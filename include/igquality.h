@@ -64,6 +64,28 @@ typedef struct {
 ig_status ig_quality(const ig_quality_params* q, const float* d_orig, const float* d_filt, const float* d_model,
                      int64_t nx, int64_t ny, int64_t nz, int device, void* hip_stream, ig_quality_result* out);
 
+/* One point of a parameter sweep. */
+typedef struct {
+    float K, tau;          /* K in units of the noise level rho */
+    int32_t n_iter;
+    float C[3];            /* per axis x, y, z */
+} ig_sweep_point;
+
+/* Parameter sweep, the tuning procedure of Section 6: filter d_in once per
+ * point, with base's conductance and shape and the point's K, tau, n_iter and
+ * C, and score each output with ig_quality(q, d_in, output, d_model).  The
+ * input's noise level rho (base->rms > 0: as given; else the plain rms of
+ * d_in, computed once) is used by every run and, unless q->rms_o > 0, as
+ * rms_o.  results[i] receives point i's diagnostics; *best the index of the
+ * largest F[0] (the lowest index among equal values; -1 if every F[0] is
+ * NaN); d_best (nullable, nx*ny*nz FP32 device memory) the output of that
+ * point.  FP32 storage only; d_in and d_model are only read.  Device memory:
+ * one filter scratch cube and one work cube for the whole sweep.  Every point
+ * is validated before any work starts.  Waits for the stream. */
+ig_status ig_filter_sweep(const ig_params* base, const ig_sweep_point* points, int32_t count, const float* d_in,
+                          const float* d_model, const ig_quality_params* q, int device, void* hip_stream,
+                          ig_quality_result* results, int32_t* best, float* d_best);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,10 @@ class IgQualityResult(ctypes.Structure):
                 ("sigma_FM", ctypes.c_double * QMAX)]
 
 
+class IgSweepPoint(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_float), ("tau", ctypes.c_float), ("n_iter", ctypes.c_int32), ("C", ctypes.c_float * 3)]
+
+
 # name -> (restype, argtypes); the exported C ABI
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -94,6 +98,10 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_int64)]),
     "ig_quality": (ctypes.c_int, [ctypes.POINTER(IgQualityParams), _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
                                   ctypes.c_int64, ctypes.c_int, _P, ctypes.POINTER(IgQualityResult)]),
+    "ig_filter_set_params": (ctypes.c_int, [_P, ctypes.POINTER(IgParams)]),
+    "ig_filter_sweep": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSweepPoint), ctypes.c_int32, _P, _P,
+                                       ctypes.POINTER(IgQualityParams), ctypes.c_int, _P,
+                                       ctypes.POINTER(IgQualityResult), ctypes.POINTER(ctypes.c_int32), _P]),
     "ig_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ig_last_error": (ctypes.c_char_p, []),
     "ig_version": (ctypes.c_char_p, []),
@@ -218,6 +226,26 @@ class Filter:
         _check(lib().ig_filter_create(ctypes.byref(self.params), self.device, ctypes.byref(h)),
                "ig_filter_create")
         self._h = h
+
+    def set_params(self, K=None, tau=None, n_iter=None, C=None, rms=None, cond=None):
+        """Change the filter parameters in place (ig_filter_set_params); shape
+        and storage type stay.  Arguments left None keep their value."""
+        p = IgParams.from_buffer_copy(self.params)
+        if K is not None:
+            p.K = float(K)
+        if tau is not None:
+            p.tau = float(tau)
+        if n_iter is not None:
+            p.n_iter = int(n_iter)
+        if C is not None:
+            for a in range(3):
+                p.C[a] = float(C[a])
+        if rms is not None:
+            p.rms = float(rms)
+        if cond is not None:
+            p.cond = CONDS[cond]
+        _check(lib().ig_filter_set_params(self._h, ctypes.byref(p)), "ig_filter_set_params")
+        self.params = p
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -363,32 +391,66 @@ def reduce(x):
     return s.value, q.value, b.value
 
 
+def _quality_params(roi, thr_f, thr_o, rms_o, rms_f, indep):
+    thr_f = list(thr_f)
+    if not 1 <= len(thr_f) <= QMAX:
+        raise ValueError(f"1 to {QMAX} thresholds")
+    q = IgQualityParams()
+    q.struct_size = ctypes.sizeof(IgQualityParams)
+    q.n_thr = len(thr_f)
+    for j, t in enumerate(thr_f):
+        q.thr_f[j] = float(t)
+    for j, v in enumerate(roi if roi is not None else (0,) * 6):
+        q.roi[j] = int(v)
+    q.thr_o, q.rms_o, q.rms_f, q.indep = float(thr_o), float(rms_o), float(rms_f), float(indep)
+    return q
+
+
+def _quality_dict(r, k, has_model):
+    return {"rms_o": r.rms_o, "rms_f": r.rms_f, "S_oo": r.S_oo, "N_o": r.N_o,
+            "S_m": r.S_m if has_model else None, "n_roi": r.n_roi,
+            "S_of": list(r.S_of[:k]), "N_f": list(r.N_f[:k]), "S_mf": list(r.S_mf[:k]) if has_model else [],
+            "F": list(r.F[:k]), "sigma_F": list(r.sigma_F[:k]),
+            "F_M": list(r.F_M[:k]) if has_model else [],
+            "sigma_FM": list(r.sigma_FM[:k]) if has_model else []}
+
+
 def quality(orig, filt, model=None, roi=None, thr_f=(3.0,), thr_o=3.0, rms_o=0.0, rms_f=0.0, indep=1.0):
     """Section 6 diagnostics (F, sigma_F, F_M, sigma_FM per M_f threshold) of
     FP32 device cubes (ig_quality).  roi = (x0, x1, y0, y1, z0, z1) or None."""
     import torch
     for t in (orig, filt) + ((model,) if model is not None else ()):
         assert t.dtype == torch.float32 and t.is_contiguous() and t.shape == orig.shape
-    thr_f = list(thr_f)
-    q = IgQualityParams()
-    q.struct_size = ctypes.sizeof(IgQualityParams)
-    q.n_thr = len(thr_f)
-    if len(thr_f) > QMAX:
-        raise ValueError(f"at most {QMAX} thresholds")
-    for j, t in enumerate(thr_f):
-        q.thr_f[j] = float(t)
-    for j, v in enumerate(roi if roi is not None else (0,) * 6):
-        q.roi[j] = int(v)
-    q.thr_o, q.rms_o, q.rms_f, q.indep = float(thr_o), float(rms_o), float(rms_f), float(indep)
+    q = _quality_params(roi, thr_f, thr_o, rms_o, rms_f, indep)
     r = IgQualityResult()
     nz, ny, nx = orig.shape
     _check(lib().ig_quality(ctypes.byref(q), ctypes.c_void_p(orig.data_ptr()), ctypes.c_void_p(filt.data_ptr()),
                             ctypes.c_void_p(model.data_ptr()) if model is not None else None, nx, ny, nz,
                             orig.device.index or 0, _stream_ptr(orig), ctypes.byref(r)), "ig_quality")
-    k = len(thr_f)
-    return {"rms_o": r.rms_o, "rms_f": r.rms_f, "S_oo": r.S_oo, "N_o": r.N_o,
-            "S_m": r.S_m if model is not None else None, "n_roi": r.n_roi,
-            "S_of": list(r.S_of[:k]), "N_f": list(r.N_f[:k]), "S_mf": list(r.S_mf[:k]) if model is not None else [],
-            "F": list(r.F[:k]), "sigma_F": list(r.sigma_F[:k]),
-            "F_M": list(r.F_M[:k]) if model is not None else [],
-            "sigma_FM": list(r.sigma_FM[:k]) if model is not None else []}
+    return _quality_dict(r, q.n_thr, model is not None)
+
+
+def sweep(x, points, cond="intensity", model=None, roi=None, thr_f=(3.0,), thr_o=3.0, rms=0.0, rms_f=0.0,
+          indep=1.0, want_best=False):
+    """Parameter sweep scored by F (ig_filter_sweep).  points: dicts with K,
+    tau, n_iter, C.  Returns (list of quality dicts, best index, best output
+    or None)."""
+    import torch
+    assert x.dtype == torch.float32 and x.is_contiguous()
+    if model is not None:
+        assert model.dtype == torch.float32 and model.is_contiguous() and model.shape == x.shape
+    base = make_params(tuple(x.shape), cond=cond, rms=rms if rms > 0 else None)
+    pts = (IgSweepPoint * len(points))()
+    for i, p in enumerate(points):
+        pts[i].K, pts[i].tau, pts[i].n_iter = float(p["K"]), float(p["tau"]), int(p["n_iter"])
+        for a in range(3):
+            pts[i].C[a] = float(p["C"][a])
+    q = _quality_params(roi, thr_f, thr_o, 0.0, rms_f, indep)
+    res = (IgQualityResult * len(points))()
+    best = ctypes.c_int32(-1)
+    out = torch.empty_like(x) if want_best else None
+    _check(lib().ig_filter_sweep(ctypes.byref(base), pts, len(points), ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(model.data_ptr()) if model is not None else None, ctypes.byref(q),
+                                 x.device.index or 0, _stream_ptr(x), res, ctypes.byref(best),
+                                 ctypes.c_void_p(out.data_ptr()) if out is not None else None), "ig_filter_sweep")
+    return [_quality_dict(r, q.n_thr, model is not None) for r in res], best.value, out
