@@ -14,6 +14,8 @@ Contents
   * ``surrogate``: FP64 NumPy forms of the learned surrogate's layers.
   * ``quality``: the filtering-quality diagnostics of Section 6 (F, sigma_F,
     F_M) over a region of interest and a sweep of mask thresholds.
+  * ``sweep``: the parameter sweep scored by F, and the paper's tuning grid.
+  * ``smooth``: the box and (rotated) Gaussian smoothing filters of Section 3.
 
 Pins (tests/test_oracle_pins.py): constant cube is a fixed point, zero
 conductance is the identity, flux conservation of the per-edge forms under
