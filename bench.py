@@ -222,6 +222,35 @@ def bench_sweep(x):
             "Gvoxel_iter_s_incl_scoring": round(vi / s / 1e9, 1), "best": pts[best], "F_best": res[best]["F"][0]}
 
 
+def bench_smooth(x):
+    """The paper's comparison filters with its performance-test parameters
+    (Section 5) on the 512^3 cube, plus one rotated Gaussian."""
+    import torch
+    import paper_1609_03782_amd as ig
+    out, work = torch.empty_like(x), torch.empty_like(x)
+    cases = {"box_iso_3": ("box", (3, 3, 3), (0, 0, 0)), "box_aniso_3x5x5": ("box", (3, 5, 5), (0, 0, 0)),
+             "gauss_iso_fwhm3": ("gauss", (3.0, 3.0, 3.0), (0, 0, 0)),
+             "gauss_aniso_fwhm2x3x3": ("gauss", (2.0, 3.0, 3.0), (0, 0, 0)),
+             "gauss_rotated_fwhm2x3x3_10_20_30deg": ("gauss", (2.0, 3.0, 3.0), (10.0, 20.0, 30.0))}
+    res = {}
+    for name, (kind, size, theta) in cases.items():
+        ig.smooth(x, kind, size, theta, out=out, work=work)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream(x.device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(5):
+            ig.smooth(x, kind, size, theta, out=out, work=work)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        r, sep = ig.smooth_geometry(kind, size, theta)
+        res[name] = {"ms": round(ms, 3), "Gvoxel_s": round(x.numel() / ms / 1e6, 1), "half_widths": r,
+                     "separable": sep}
+    res["paper_gpu_s_for_1.4e8_voxels"] = {"gauss_iso": 1.8, "gauss_aniso": 3.5}
+    return res
+
+
 def bench_surrogate(args):
     """Learned surrogate: train on filter-generated pairs, calibrate the
     residual check, then time checked inference on the 512^3 cube against
@@ -397,6 +426,7 @@ def main():
         extras["batch_96"] = bench_batch(max(3, args.steps // 4))
         extras["quality_512"] = bench_quality(x, out)
         extras["sweep_paper_grid_512"] = bench_sweep(x)
+        extras["smoothing_512"] = bench_smooth(x)
         res["extras"] = extras
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(cube, N_ITER, K, tau)

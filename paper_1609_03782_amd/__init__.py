@@ -68,6 +68,14 @@ class IgSweepPoint(ctypes.Structure):
     _fields_ = [("K", ctypes.c_float), ("tau", ctypes.c_float), ("n_iter", ctypes.c_int32), ("C", ctypes.c_float * 3)]
 
 
+class IgSmoothParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("kind", ctypes.c_int32), ("size", ctypes.c_float * 3),
+                ("theta", ctypes.c_float * 3), ("truncate", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+SMOOTH_KINDS = {"box": 0, "gauss": 1}
+
+
 # name -> (restype, argtypes); the exported C ABI
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -102,6 +110,10 @@ SIGNATURES = {
     "ig_filter_sweep": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSweepPoint), ctypes.c_int32, _P, _P,
                                        ctypes.POINTER(IgQualityParams), ctypes.c_int, _P,
                                        ctypes.POINTER(IgQualityResult), ctypes.POINTER(ctypes.c_int32), _P]),
+    "ig_smooth_geometry": (ctypes.c_int, [ctypes.POINTER(IgSmoothParams), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32)]),
+    "ig_smooth": (ctypes.c_int, [ctypes.POINTER(IgSmoothParams), _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_int64, _P]),
     "ig_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ig_last_error": (ctypes.c_char_p, []),
     "ig_version": (ctypes.c_char_p, []),
@@ -454,3 +466,41 @@ def sweep(x, points, cond="intensity", model=None, roi=None, thr_f=(3.0,), thr_o
                                  x.device.index or 0, _stream_ptr(x), res, ctypes.byref(best),
                                  ctypes.c_void_p(out.data_ptr()) if out is not None else None), "ig_filter_sweep")
     return [_quality_dict(r, q.n_thr, model is not None) for r in res], best.value, out
+
+
+def smooth_params(kind="gauss", size=(3.0, 3.0, 3.0), theta=(0.0, 0.0, 0.0), truncate=0.0):
+    p = IgSmoothParams()
+    p.struct_size = ctypes.sizeof(IgSmoothParams)
+    p.kind = SMOOTH_KINDS[kind]
+    for a in range(3):
+        p.size[a] = float(size[a])
+        p.theta[a] = float(theta[a])
+    p.truncate = float(truncate)
+    p.reserved = 0
+    return p
+
+
+def smooth_geometry(kind="gauss", size=(3.0, 3.0, 3.0), theta=(0.0, 0.0, 0.0), truncate=0.0):
+    """((r_x, r_y, r_z), separable) of a box / Gaussian kernel (host only)."""
+    p = smooth_params(kind, size, theta, truncate)
+    r = (ctypes.c_int32 * 3)()
+    sep = ctypes.c_int32()
+    _check(lib().ig_smooth_geometry(ctypes.byref(p), r, ctypes.byref(sep)), "ig_smooth_geometry")
+    return tuple(r), bool(sep.value)
+
+
+def smooth(x, kind="gauss", size=(3.0, 3.0, 3.0), theta=(0.0, 0.0, 0.0), truncate=0.0, out=None, work=None):
+    """Box (size = odd N_x, N_y, N_z) or Gaussian (size = FWHM_x, y, z; Euler
+    angles theta in degrees) smoothing of an FP32 device cube (ig_smooth)."""
+    import torch
+    assert x.dtype == torch.float32 and x.is_contiguous()
+    p = smooth_params(kind, size, theta, truncate)
+    out = torch.empty_like(x) if out is None else out
+    _, sep = smooth_geometry(kind, size, theta, truncate)
+    if sep and work is None:
+        work = torch.empty_like(x)
+    nz, ny, nx = x.shape
+    _check(lib().ig_smooth(ctypes.byref(p), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                           ctypes.c_void_p(work.data_ptr()) if work is not None else None, nx, ny, nz,
+                           _stream_ptr(x)), "ig_smooth")
+    return out

@@ -149,3 +149,23 @@ def test_quality_rejects_invalid_arguments(kw):
     assert rc == ig.IG_ERR_INVALID_ARG, kw
     rc = ig.lib().ig_quality(ctypes.byref(_qparams()), None, fake, None, 8, 4, 4, 0, None, ctypes.byref(r))
     assert rc == ig.IG_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kind,size,theta", [("box", (3, 5, 7), (0, 0, 0)), ("gauss", (3.0, 3.0, 3.0), (0, 0, 0)),
+                                             ("gauss", (1.5, 4.0, 2.5), (0, 0, 0)),
+                                             ("gauss", (2.0, 3.0, 3.0), (10.0, 20.0, 30.0)),
+                                             ("gauss", (2.0, 5.0, 3.0), (0.0, 0.0, 30.0))])
+def test_smooth_geometry_matches_oracle_kernel(kind, size, theta):
+    from oracle import smooth as Sm
+    r, sep = ig.smooth_geometry(kind, size, theta)
+    k = Sm.box_kernel(size) if kind == "box" else Sm.gauss_kernel(size, theta)
+    assert (2 * r[2] + 1, 2 * r[1] + 1, 2 * r[0] + 1) == k.shape
+    assert sep == (kind == "box" or not any(theta))
+
+
+@pytest.mark.parametrize("kind,size,theta", [("box", (2, 3, 3), (0, 0, 0)), ("box", (3, 3, 3), (0, 0, 5)),
+                                             ("box", (3.5, 3, 3), (0, 0, 0)), ("gauss", (0.0, 3, 3), (0, 0, 0)),
+                                             ("gauss", (3, float("nan"), 3), (0, 0, 0))])
+def test_smooth_rejects_invalid(kind, size, theta):
+    p = ig.smooth_params(kind, size, theta)
+    assert ig.lib().ig_smooth_geometry(ctypes.byref(p), None, None) == ig.IG_ERR_INVALID_ARG
