@@ -16,6 +16,8 @@ Contents
     F_M) over a region of interest and a sweep of mask thresholds.
   * ``sweep``: the parameter sweep scored by F, and the paper's tuning grid.
   * ``smooth``: the box and (rotated) Gaussian smoothing filters of Section 3.
+  * ``wavelet``: Haar / Le Gall 5/3 lifting and the thresholding denoiser of
+    Section 3.4, in FP64 or in FP32 in the GPU's operation order.
 
 Pins (tests/test_oracle_pins.py): constant cube is a fixed point, zero
 conductance is the identity, flux conservation of the per-edge forms under
