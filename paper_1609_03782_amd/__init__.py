@@ -74,6 +74,13 @@ class IgSmoothParams(ctypes.Structure):
 
 
 SMOOTH_KINDS = {"box": 0, "gauss": 1}
+WAVELETS = {"haar": 0, "legall53": 1}
+WMAX = 8   # IG_WAVELET_MAX_LEVELS
+
+
+class IgWaveletParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("kind", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("t", ctypes.c_double * WMAX), ("rms", ctypes.c_double)]
 
 
 # name -> (restype, argtypes); the exported C ABI
@@ -114,6 +121,12 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_int32)]),
     "ig_smooth": (ctypes.c_int, [ctypes.POINTER(IgSmoothParams), _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_int64, _P]),
+    "ig_wavelet_forward": (ctypes.c_int, [ctypes.POINTER(IgWaveletParams), _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_int64, _P]),
+    "ig_wavelet_inverse": (ctypes.c_int, [ctypes.POINTER(IgWaveletParams), _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_int64, _P]),
+    "ig_wavelet_denoise": (ctypes.c_int, [ctypes.POINTER(IgWaveletParams), _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_double)]),
     "ig_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ig_last_error": (ctypes.c_char_p, []),
     "ig_version": (ctypes.c_char_p, []),
@@ -504,3 +517,48 @@ def smooth(x, kind="gauss", size=(3.0, 3.0, 3.0), theta=(0.0, 0.0, 0.0), truncat
                            ctypes.c_void_p(work.data_ptr()) if work is not None else None, nx, ny, nz,
                            _stream_ptr(x)), "ig_smooth")
     return out
+
+
+def wavelet_params(kind="haar", levels=3, t=(0.5, 0.8, 1.1), rms=0.0):
+    p = IgWaveletParams()
+    p.struct_size = ctypes.sizeof(IgWaveletParams)
+    p.kind = WAVELETS[kind]
+    p.levels = int(levels)
+    p.reserved = 0
+    for l, v in enumerate(t):
+        p.t[l] = float(v)
+    p.rms = float(rms)
+    return p
+
+
+def _wcall(fn, p, x, out):
+    nz, ny, nx = x.shape
+    _check(getattr(lib(), fn)(ctypes.byref(p), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), nx, ny,
+                              nz, _stream_ptr(x)), fn)
+    return out
+
+
+def wavelet_forward(x, kind="haar", levels=3, out=None):
+    """Multi-level lifting transform of an FP32 device cube (ig_wavelet_forward)."""
+    import torch
+    assert x.dtype == torch.float32 and x.is_contiguous()
+    return _wcall("ig_wavelet_forward", wavelet_params(kind, levels), x, torch.empty_like(x) if out is None else out)
+
+
+def wavelet_inverse(c, kind="haar", levels=3, out=None):
+    import torch
+    assert c.dtype == torch.float32 and c.is_contiguous()
+    return _wcall("ig_wavelet_inverse", wavelet_params(kind, levels), c, torch.empty_like(c) if out is None else out)
+
+
+def wavelet_denoise(x, kind="haar", levels=3, t=(0.5, 0.8, 1.1), rms=0.0, out=None):
+    """Threshold denoiser (ig_wavelet_denoise); returns (output, rms used)."""
+    import torch
+    assert x.dtype == torch.float32 and x.is_contiguous()
+    out = torch.empty_like(x) if out is None else out
+    p = wavelet_params(kind, levels, t, rms)
+    used = ctypes.c_double()
+    nz, ny, nx = x.shape
+    _check(lib().ig_wavelet_denoise(ctypes.byref(p), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    nx, ny, nz, _stream_ptr(x), ctypes.byref(used)), "ig_wavelet_denoise")
+    return out, used.value

@@ -169,3 +169,18 @@ def test_smooth_geometry_matches_oracle_kernel(kind, size, theta):
 def test_smooth_rejects_invalid(kind, size, theta):
     p = ig.smooth_params(kind, size, theta)
     assert ig.lib().ig_smooth_geometry(ctypes.byref(p), None, None) == ig.IG_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kw,shape", [(dict(levels=0), (8, 8, 8)), (dict(levels=9), (8, 8, 8)), (dict(kind=2), (8, 8, 8)),
+                                      (dict(reserved=1), (8, 8, 8)), ({}, (0, 8, 8)), ({}, (8, 8, 10241)),
+                                      ({}, (2561, 8, 8))])
+def test_wavelet_rejects_invalid(kw, shape):
+    p = ig.wavelet_params()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    fake = ctypes.c_void_p(4096)   # never dereferenced: validation fails first
+    nz, ny, nx = shape
+    rc = ig.lib().ig_wavelet_forward(ctypes.byref(p), fake, fake, nx, ny, nz, None)
+    assert rc in (ig.IG_ERR_INVALID_ARG, ig.IG_ERR_UNSUPPORTED), (kw, shape)
+    if shape[2] > 10240 or shape[0] > 2560:
+        assert rc == ig.IG_ERR_UNSUPPORTED
