@@ -217,7 +217,7 @@ static BatchKernel batch_kernel(int cond, int T) {
 
 namespace {
 
-constexpr long kChunk = 1L << 18;   // voxels per rms partial
+constexpr long kChunk = 1L << 16;   // voxels per rms partial (many workgroups even for small batches)
 
 template <typename T>
 struct DevBuf {

@@ -2,15 +2,25 @@
 // of interest for a sweep of mask thresholds, then F, sigma_F, F_M, sigma_FM.
 // See include/igquality.h.
 //
-// Work split: lane j of every wavefront owns mask threshold j (lanes below
-// n_thr: the M_f thresholds on the filtered cube; lane 63: the M_o threshold
-// on the original, which also accumulates the unmasked model sum).  A
-// wavefront takes 64-voxel chunks of the ROI in a fixed order, parks each
-// chunk's three values (original, filtered, model) in its LDS slice as FP64,
-// and every lane then walks the 64 voxels in order, adding the ones its mask
-// admits.  Each lane's sums are therefore sequential in a fixed order; the
-// per-wavefront partials are folded in wavefront order by one workgroup.  No
-// atomics: bitwise reproducible.
+// Partial sums live in 192 FP64 slots per partial: slot 3j + {0, 1, 2} holds
+// (sum of original values, sum of model values, voxel count) under mask j,
+// j < n_thr for the M_f thresholds and j = 63 for M_o (whose model slot is the
+// unmasked model sum).  Two ways to produce the partials, both with a fixed
+// work split and fixed-order sums, so results are bitwise reproducible run to
+// run (no atomics):
+//
+//  * up to 8 thresholds (the sweep's case): voxel-parallel.  Each thread keeps
+//    every mask's sums in registers and walks its voxels in a fixed order
+//    (row segments of the ROI, grid-stride); a fixed shuffle tree and the
+//    wavefronts in order make one partial per workgroup.  Bound by HBM.
+//  * more thresholds: lane j of every wavefront owns mask j.  A wavefront
+//    takes 64-voxel chunks in a fixed order, parks each chunk's three values
+//    as FP64 in its LDS slice, and every lane walks the 64 voxels in order
+//    (a uniform-address LDS read is a broadcast).  One partial per wavefront.
+//
+// k_quality_fold folds each slot over the partials (block b folds slot b:
+// strided per-thread sums, then a fixed tree); k_quality_derive turns the 192
+// sums into the diagnostics.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -28,17 +38,78 @@ struct QGeom {
     long x0, y0, z0;      // ROI origin
     long rx, ry;          // ROI extents in x and y
     long nroi;            // voxels in the ROI
+    long nrows;           // ROI rows (ry * rz)
     int has_model;
     int pad;
-    double thr[64];       // absolute threshold per lane (+inf: lane unused)
+    double thr[64];       // absolute threshold per mask (+inf: unused)
 };
 
-constexpr int kQWaves = 4;         // wavefronts per workgroup
+constexpr int kQWaves = 4;          // wavefronts per workgroup
 constexpr int kQMaxBlocks = 1024;
+constexpr int kQSlots = 192;        // 64 masks x (orig sum, model sum, count)
+constexpr int kQSeg = 256;          // row-segment length of the voxel-parallel kernel
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_quality_vox(const float* __restrict__ orig, const float* __restrict__ filt, const float* __restrict__ model,
+              QGeom g, double* __restrict__ part) {
+    constexpr int NA = 3 * (K + 1);
+    double acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = 0.0;
+    double thr[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) thr[k] = g.thr[k];
+    const double thr_o = g.thr[63];
+    const long segs = (g.rx + kQSeg - 1) / kQSeg;
+    for (long t = blockIdx.x; t < g.nrows * segs; t += gridDim.x) {
+        const long row = t / segs, seg = t - row * segs;
+        const long x = seg * kQSeg + threadIdx.x;
+        if (x >= g.rx) continue;
+        const long y = row % g.ry, z = row / g.ry;
+        const long idx = (g.x0 + x) + g.nx * ((g.y0 + y) + g.ny * (g.z0 + z));
+        const double o = (double)orig[idx], f = (double)filt[idx];
+        const double m = g.has_model ? (double)model[idx] : 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bool p = f >= thr[k];
+            acc[3 * k] += p ? o : 0.0;
+            acc[3 * k + 1] += p ? m : 0.0;
+            acc[3 * k + 2] += p ? 1.0 : 0.0;
+        }
+        const bool po = o >= thr_o;
+        acc[3 * K] += po ? o : 0.0;
+        acc[3 * K + 1] += m;
+        acc[3 * K + 2] += po ? 1.0 : 0.0;
+    }
+    __shared__ double red[kQWaves][NA];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        const double v = wsum(acc[a]);
+        if (lane == 0) red[wid][a] = v;
+    }
+    __syncthreads();
+    double* out = part + (long)blockIdx.x * kQSlots;
+    for (int sl = threadIdx.x; sl < kQSlots; sl += 256) {
+        const int j = sl / 3, c = sl % 3;
+        const int a = j < K ? 3 * j + c : (j == 63 ? 3 * K + c : -1);
+        double v = 0.0;
+        if (a >= 0)
+            for (int w = 0; w < kQWaves; ++w) v += red[w][a];
+        out[sl] = v;
+    }
+}
 
 __global__ void __launch_bounds__(256)
-k_quality_partial(const float* __restrict__ orig, const float* __restrict__ filt, const float* __restrict__ model,
-                  QGeom g, double* __restrict__ part, unsigned* __restrict__ cnt) {
+k_quality_lanes(const float* __restrict__ orig, const float* __restrict__ filt, const float* __restrict__ model,
+                QGeom g, double* __restrict__ part) {
     __shared__ double vals[kQWaves][64][3];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
@@ -46,8 +117,7 @@ k_quality_partial(const float* __restrict__ orig, const float* __restrict__ filt
     const long gw = (long)blockIdx.x * kQWaves + wid;
     const double thr = g.thr[lane];
     const bool mo = lane == 63;
-    double a1 = 0.0, a2 = 0.0;
-    unsigned c = 0;
+    double a1 = 0.0, a2 = 0.0, c = 0.0;
     for (long ch = gw; ch * 64 < g.nroi; ch += nw) {
         const long r = ch * 64 + lane;
         double vo = 0.0, vf = 0.0, vm = 0.0;
@@ -69,33 +139,39 @@ k_quality_partial(const float* __restrict__ orig, const float* __restrict__ filt
             const bool pass = mo ? (so >= thr) : (sf >= thr);
             a1 += pass ? so : 0.0;
             a2 += (pass || mo) ? sm : 0.0;
-            c += pass ? 1u : 0u;
+            c += pass ? 1.0 : 0.0;
         }
         __builtin_amdgcn_wave_barrier();
     }
-    const long o = gw * 64 + lane;
-    part[2 * o] = a1;
-    part[2 * o + 1] = a2;
-    cnt[o] = c;
+    double* out = part + gw * kQSlots;
+    out[3 * lane] = a1;
+    out[3 * lane + 1] = a2;
+    out[3 * lane + 2] = c;
 }
 
-// One wavefront: lane j folds the partials of threshold j in wavefront order
-// and derives the diagnostics.
+// Block b folds slot b over `count` partials: thread t sums partials t,
+// t + 256, ... in order, then a fixed tree over the threads.
+__global__ void __launch_bounds__(256)
+k_quality_fold(const double* __restrict__ part, long count, double* __restrict__ sums) {
+    const int sl = blockIdx.x;
+    double v = 0.0;
+    for (long i = threadIdx.x; i < count; i += 256) v += part[i * kQSlots + sl];
+    v = wsum(v);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[sl] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// One wavefront: lane j derives the diagnostics of mask j.
 __global__ void __launch_bounds__(64)
-k_quality_final(const double* __restrict__ part, const unsigned* __restrict__ cnt, long nw, int nthr, int has_model,
-                double rms_o, double rms_f, double indep, long nroi, ig_quality_result* __restrict__ out) {
+k_quality_derive(const double* __restrict__ sums, int nthr, int has_model, double rms_o, double rms_f, double indep,
+                 long nroi, ig_quality_result* __restrict__ out) {
     const int j = threadIdx.x;
-    double s1 = 0.0, s2 = 0.0;
-    long long n = 0;
-    for (long w = 0; w < nw; ++w) {
-        s1 += part[2 * (w * 64 + j)];
-        s2 += part[2 * (w * 64 + j) + 1];
-        n += cnt[w * 64 + j];
-    }
-    // lane 63 holds S_oo, S_m, N_o
-    const double S_oo = __shfl(s1, 63, 64);
-    const double S_m = __shfl(s2, 63, 64);
-    const long long N_o = __shfl(n, 63, 64);
+    const double s1 = sums[3 * j], s2 = sums[3 * j + 1];
+    const long long n = (long long)sums[3 * j + 2];
+    const double S_oo = sums[3 * 63], S_m = sums[3 * 63 + 1];
+    const long long N_o = (long long)sums[3 * 63 + 2];
     const double nan = __builtin_nan("");
     if (j == 63) {
         out->rms_o = rms_o;
@@ -143,9 +219,9 @@ using namespace igk;
 
 namespace {
 
-struct QScratch {   // per-device partials and result slot, kept for the process
+struct QScratch {   // per-device partials, folded sums and result slot, kept for the process
     double* part = nullptr;
-    unsigned* cnt = nullptr;
+    double* sums = nullptr;
     ig_quality_result* res = nullptr;
 };
 std::mutex g_qmu;
@@ -211,22 +287,34 @@ extern "C" ig_status ig_quality(const ig_quality_params* q, const float* d_orig,
     for (int j = 0; j < q->n_thr; ++j) g.thr[j] = q->thr_f[j] * rms_f;
     g.thr[63] = q->thr_o * rms_o;
 
-    const long chunks = (g.nroi + 63) / 64;
-    const int blocks = (int)std::min<long>(kQMaxBlocks, (chunks + kQWaves - 1) / kQWaves);
-    const long nw = (long)blocks * kQWaves;
-
+    g.nrows = g.ry * (r[5] - r[4]);
     std::lock_guard<std::mutex> lk(g_qmu);
     QScratch& qs = g_qs[device];
     if (!qs.part) {
-        HIP_TRY(hipMalloc((void**)&qs.part, (size_t)kQMaxBlocks * kQWaves * 64 * 2 * sizeof(double)));
-        HIP_TRY(hipMalloc((void**)&qs.cnt, (size_t)kQMaxBlocks * kQWaves * 64 * sizeof(unsigned)));
+        HIP_TRY(hipMalloc((void**)&qs.part, (size_t)kQMaxBlocks * kQWaves * kQSlots * sizeof(double)));
+        HIP_TRY(hipMalloc((void**)&qs.sums, (size_t)kQSlots * sizeof(double)));
         HIP_TRY(hipMalloc((void**)&qs.res, sizeof(ig_quality_result)));
     }
-    hipLaunchKernelGGL(k_quality_partial, dim3(blocks), dim3(64 * kQWaves), 0, s, d_orig, d_filt, d_model, g, qs.part,
-                       qs.cnt);
+    long count;
+    if (q->n_thr <= 8) {
+        const int K = q->n_thr <= 1 ? 1 : q->n_thr <= 2 ? 2 : q->n_thr <= 4 ? 4 : 8;
+        const long segs = g.nrows * ((g.rx + kQSeg - 1) / kQSeg);
+        const int blocks = (int)std::min<long>(kQMaxBlocks * 2, segs);
+        auto k = K == 1 ? k_quality_vox<1> : K == 2 ? k_quality_vox<2> : K == 4 ? k_quality_vox<4> : k_quality_vox<8>;
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, s, d_orig, d_filt, d_model, g, qs.part);
+        count = blocks;
+    } else {
+        const long chunks = (g.nroi + 63) / 64;
+        const int blocks = (int)std::min<long>(kQMaxBlocks, (chunks + kQWaves - 1) / kQWaves);
+        hipLaunchKernelGGL(k_quality_lanes, dim3(blocks), dim3(64 * kQWaves), 0, s, d_orig, d_filt, d_model, g,
+                           qs.part);
+        count = (long)blocks * kQWaves;
+    }
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_quality_final, dim3(1), dim3(64), 0, s, qs.part, qs.cnt, nw, q->n_thr, g.has_model, rms_o,
-                       rms_f, q->indep, g.nroi, qs.res);
+    hipLaunchKernelGGL(k_quality_fold, dim3(kQSlots), dim3(256), 0, s, qs.part, count, qs.sums);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_quality_derive, dim3(1), dim3(64), 0, s, qs.sums, q->n_thr, g.has_model, rms_o, rms_f,
+                       q->indep, g.nroi, qs.res);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(out, qs.res, sizeof(ig_quality_result), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

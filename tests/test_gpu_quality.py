@@ -132,3 +132,22 @@ def test_quality_fullsize(dev):
     ref = Q.quality(cube, filt, None, roi=roi, thr_f=thr, rms_o=got["rms_o"], rms_f=got["rms_f"])
     assert got["rms_o"] == pytest.approx(Q.plain_rms(cube), rel=1e-11)
     _check(got, ref, cube, None, roi)
+
+
+def test_voxel_parallel_and_lane_paths_agree(dev):
+    """Up to 8 thresholds run voxel-parallel, more run one mask per lane: the
+    same masks give the same counts and sums (to summation order)."""
+    import paper_1609_03782_amd as ig
+    rng = np.random.default_rng(12)
+    orig = rng.standard_normal((30, 41, 77)).astype(np.float32) * 2
+    filt = (orig * 0.6 + rng.standard_normal(orig.shape).astype(np.float32) * 0.3).astype(np.float32)
+    model = np.abs(orig).astype(np.float32)
+    thr8 = (0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5)
+    roi = (2, 70, 3, 40, 1, 29)
+    a = ig.quality(_t(orig, dev), _t(filt, dev), _t(model, dev), roi=roi, thr_f=thr8, rms_o=1.0, rms_f=1.0)
+    b = ig.quality(_t(orig, dev), _t(filt, dev), _t(model, dev), roi=roi, thr_f=thr8 + (4.0,), rms_o=1.0, rms_f=1.0)
+    assert a["N_f"] == b["N_f"][:8] and a["N_o"] == b["N_o"]
+    ref = Q.quality(orig, filt, model, roi=roi, thr_f=thr8, rms_o=1.0, rms_f=1.0)
+    _check(a, ref, orig, model, roi)
+    for x, y in zip(a["S_of"] + a["S_mf"], b["S_of"][:8] + b["S_mf"][:8]):
+        assert x == pytest.approx(y, rel=1e-12, abs=1e-9)
