@@ -162,7 +162,7 @@ def bench_batch(steps):
         x = torch.from_numpy(igsynth.batch_cube(it)).cuda()
         items.append((x, torch.empty_like(x), dict(K=it.K, tau=1 / 16, n_iter=it.n_iter, cond="pm_exp")))
         work += x.numel() * it.n_iter
-    T, W, _ = ig.batch_autotune(items)
+    T, W, Z, _ = ig.batch_autotune(items)
     ig.batch(items)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -177,7 +177,7 @@ def bench_batch(steps):
             "ms_per_batch": round(ms, 4), "Gvoxel_iter_s": round(work / ms / 1e6, 2),
             "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
             "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
-            "policy": "pass-major rounds, longest cubes first", "t_block": T, "waves": W}
+            "policy": "pass-major rounds, longest cubes first", "t_block": T, "waves": W, "zchunk": Z}
 
 
 def paper_tuning_grid():

@@ -90,12 +90,16 @@ typedef enum {
 typedef struct {
     int32_t kind;      /* ig_sched_kind */
     int32_t t_block;   /* steps per pass, 1..4 (BLOCKED) */
-    int32_t waves;     /* wavefronts per workgroup = rows of a tile, 1..16 (BLOCKED) */
+    int32_t waves;     /* wavefronts per workgroup, 1..16 (BLOCKED) */
     int32_t zchunk;    /* 0: split the cube into pieces of equal work, a whole number of
                           rounds of the workgroups the GPU holds at once; > 0: pieces
                           of zchunk output planes (BLOCKED) */
-    int32_t vec;       /* x voxels per lane: 1, 2, 4 or 8; 0 = smallest covering nx */
+    int32_t vec;       /* x voxels per lane: 1, 2, 4 or 8; 0 = automatic (8 above nx = 256,
+                          else 4 with `rows` chosen to cover nx) */
     int32_t rounds;    /* zchunk == 0: rounds of resident workgroups; 0 = as few as possible */
+    int32_t rows;      /* rows per wavefront: 1, 2 or 4 (a tile has waves * rows rows); more
+                          than 1 needs vec 4 and nx <= 256 / rows (one x tile); 0 = automatic
+                          with vec 0, else 1 */
 } ig_schedule;
 
 typedef struct {
@@ -157,8 +161,9 @@ ig_status ig_filter_set_timing(ig_filter* f, int enable);
 ig_status ig_filter_get_timing(ig_filter* f, double* total_ms, int64_t* launches, int reset);
 
 /* Host-only: the work split of one pass of depth t_block under schedule s
- * (BLOCKED) on a GPU with ncu compute units.  geom[8] receives
- * {ntx, nty, ox, oy, waves, vec_io, V, pieces}; if pieces != NULL, up to cap
+ * (BLOCKED) on a GPU with ncu compute units.  geom[9] receives
+ * {ntx, nty, ox, oy, waves, vec_io, V, pieces, rows per wavefront}; if
+ * pieces != NULL, up to cap
  * pieces as {tile_x, tile_y, z0, z1} (outputs in planes [z0, z1) of tile
  * (tile_x, tile_y), whose outputs are columns [tile_x*ox, +ox) and rows
  * [tile_y*oy, +oy), clipped to the cube).  *count receives the number. */
@@ -203,16 +208,18 @@ ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, int device,
 void ig_batch_cache_clear(void);
 
 /* Schedule of later ig_filter_batch plans: steps per pass t_block (1..4; 0 =
- * library default) and wavefronts per workgroup (1..16, > 2 t_block).  All
- * items of a batch must have nx <= 256 and share one conductance. */
-ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves);
+ * library default), wavefronts per workgroup (1..16, > 2 t_block) and planes
+ * per z-chunk of a piece (1..4096; default 32).  All items of a batch must
+ * have nx <= 256 and share one conductance. */
+ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves, int32_t zchunk);
 
-/* Batch autotuner: runs the batch with t_block 1..4 and waves 8 and 16,
- * keeps the fastest (sets it as by ig_batch_set_schedule) and returns it.
+/* Batch autotuner: runs the batch with t_block 1..4, waves 8, 12 and 16 and
+ * z-chunks of 32 and 64 planes, keeps the fastest (sets it as by
+ * ig_batch_set_schedule, and keeps only that plan cached) and returns it.
  * Every item must have d_in != d_out (outputs are overwritten; inputs are
  * read only).  Waits for the stream. */
 ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
-                            int32_t* best_t_block, int32_t* best_waves, double* best_ms);
+                            int32_t* best_t_block, int32_t* best_waves, int32_t* best_zchunk, double* best_ms);
 
 /* Comparison of a device cube with an FP64 device reference (both n
  * elements): maximum |x - ref|, root mean square of x - ref, count of

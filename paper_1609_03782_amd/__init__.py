@@ -29,7 +29,8 @@ class IgParams(ctypes.Structure):
 
 class IgSchedule(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("t_block", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("zchunk", ctypes.c_int32), ("vec", ctypes.c_int32), ("rounds", ctypes.c_int32)]
+                ("zchunk", ctypes.c_int32), ("vec", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("rows", ctypes.c_int32)]
 
 
 class IgStats(ctypes.Structure):
@@ -94,7 +95,7 @@ SIGNATURES = {
     "ig_filter_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(IgSchedule), ctypes.POINTER(ctypes.c_double)]),
     "ig_batch_autotune": (ctypes.c_int, [ctypes.POINTER(IgBatchItem), ctypes.c_int32, ctypes.c_int, _P,
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                         ctypes.POINTER(ctypes.c_double)]),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "ig_filter_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "ig_filter_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                             ctypes.c_int]),
@@ -105,7 +106,7 @@ SIGNATURES = {
     "ig_filter_batch": (ctypes.c_int, [ctypes.POINTER(IgBatchItem), ctypes.c_int32, ctypes.c_int, _P,
                                        ctypes.POINTER(IgStats), ctypes.POINTER(ctypes.c_double)]),
     "ig_batch_cache_clear": (None, []),
-    "ig_batch_set_schedule": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "ig_batch_set_schedule": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "ig_compare": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_int, _P,
                                   ctypes.POINTER(IgCompareResult)]),
     "ig_reduce": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int, _P,
@@ -185,7 +186,7 @@ def schedule_check(shape, sched: dict, **params) -> str | None:
     """None if `sched` can serve cubes of `shape`, else the reason (host only)."""
     p = make_params(shape, **params)
     s = IgSchedule(SCHED[sched.get("kind", "blocked")], sched.get("t_block", 2), sched.get("waves", 16),
-                   sched.get("zchunk", 0), sched.get("vec", 0), sched.get("rounds", 0))
+                   sched.get("zchunk", 0), sched.get("vec", 0), sched.get("rounds", 0), sched.get("rows", 0))
     rc = lib().ig_schedule_check(ctypes.byref(p), ctypes.byref(s))
     return None if rc == IG_OK else lib().ig_last_error().decode()
 
@@ -195,8 +196,8 @@ def schedule_plan(shape, sched: dict, t_block: int, ncu: int = 256, **params):
     import numpy as np
     p = make_params(shape, **params)
     s = IgSchedule(SCHED[sched.get("kind", "blocked")], sched.get("t_block", 2), sched.get("waves", 16),
-                   sched.get("zchunk", 0), sched.get("vec", 0), sched.get("rounds", 0))
-    geom = (ctypes.c_int32 * 8)()
+                   sched.get("zchunk", 0), sched.get("vec", 0), sched.get("rounds", 0), sched.get("rows", 0))
+    geom = (ctypes.c_int32 * 9)()
     cnt = ctypes.c_int64()
     _check(lib().ig_schedule_plan(ctypes.byref(p), ctypes.byref(s), t_block, ncu, geom, None, 0,
                                   ctypes.byref(cnt)), "ig_schedule_plan")
@@ -204,7 +205,7 @@ def schedule_plan(shape, sched: dict, t_block: int, ncu: int = 256, **params):
     _check(lib().ig_schedule_plan(ctypes.byref(p), ctypes.byref(s), t_block, ncu, geom,
                                   arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cnt.value,
                                   ctypes.byref(cnt)), "ig_schedule_plan")
-    keys = ["ntx", "nty", "ox", "oy", "waves", "vec_io", "V", "pieces"]
+    keys = ["ntx", "nty", "ox", "oy", "waves", "vec_io", "V", "pieces", "rows"]
     return dict(zip(keys, list(geom))), arr
 
 
@@ -231,7 +232,7 @@ class Stats:
 
 def _sched_dict(s: IgSchedule):
     return {"kind": {v: k for k, v in SCHED.items()}[s.kind], "t_block": s.t_block, "waves": s.waves,
-            "zchunk": s.zchunk, "vec": s.vec, "rounds": s.rounds}
+            "zchunk": s.zchunk, "vec": s.vec, "rounds": s.rounds, "rows": s.rows}
 
 
 class Filter:
@@ -283,11 +284,11 @@ class Filter:
 
     __del__ = close
 
-    def set_schedule(self, kind="blocked", t_block=2, waves=16, zchunk=0, vec=0, rounds=0):
+    def set_schedule(self, kind="blocked", t_block=2, waves=16, zchunk=0, vec=0, rounds=0, rows=0):
         if kind == "auto":
             _check(lib().ig_filter_set_schedule(self._h, None), "ig_filter_set_schedule")
             return
-        s = IgSchedule(SCHED[kind], t_block, waves, zchunk, vec, rounds)
+        s = IgSchedule(SCHED[kind], t_block, waves, zchunk, vec, rounds, rows)
         _check(lib().ig_filter_set_schedule(self._h, ctypes.byref(s)), "ig_filter_set_schedule")
 
     def autotune(self, x, work=None):
@@ -376,22 +377,23 @@ def _batch_array(items):
 
 
 def batch_autotune(items, device=0):
-    """Time the batch under candidate schedules; keep the fastest.  Returns (t_block, waves, ms)."""
+    """Time the batch under candidate schedules; keep the fastest.  Returns
+    (t_block, waves, zchunk, ms)."""
     import torch
     arr = _batch_array(items)
-    T, W, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    T, W, Z, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
     _check(lib().ig_batch_autotune(arr, len(items), device, stream, ctypes.byref(T), ctypes.byref(W),
-                                   ctypes.byref(ms)), "ig_batch_autotune")
-    return T.value, W.value, ms.value
+                                   ctypes.byref(Z), ctypes.byref(ms)), "ig_batch_autotune")
+    return T.value, W.value, Z.value, ms.value
 
 
 def batch_cache_clear():
     lib().ig_batch_cache_clear()
 
 
-def batch_set_schedule(t_block=0, waves=16):
-    _check(lib().ig_batch_set_schedule(int(t_block), int(waves)), "ig_batch_set_schedule")
+def batch_set_schedule(t_block=0, waves=16, zchunk=32):
+    _check(lib().ig_batch_set_schedule(int(t_block), int(waves), int(zchunk)), "ig_batch_set_schedule")
 
 
 def compare(x, ref, tol=0.0):

@@ -121,10 +121,13 @@ ig_status igk_validate_params(const ig_params* p) {
 }
 
 // ------------------------------------------------------------------ schedule
-int pick_vec(int64_t nx) {
-    for (int v : {1, 2, 4, 8})
-        if (64 * v >= nx) return v;
-    return 8;
+// Automatic x layout: 8 voxels per lane above nx = 256 (x tiles beyond 512);
+// else 4 voxels per lane and as many rows per wavefront as keep one row's
+// lanes covering nx, so narrow cubes still give every lane 4 voxels.
+void auto_vec_rows(int64_t nx, int* V, int* R) {
+    if (nx > 256) { *V = 8; *R = 1; return; }
+    *V = 4;
+    *R = nx <= 64 ? 4 : nx <= 128 ? 2 : 1;
 }
 
 // Workgroups of the streaming kernel one CU holds at once: 16 wavefronts of
@@ -139,15 +142,25 @@ int resident_per_cu(int W, size_t lds) {
 // cannot serve the shape.
 const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp) {
     const int nx = (int)p.nx, ny = (int)p.ny, nz = (int)p.nz;
-    const int V = s.vec ? s.vec : pick_vec(p.nx), W = s.waves;
+    int V = s.vec, R = s.rows;
+    if (V == 0) {
+        int av, ar;
+        auto_vec_rows(p.nx, &av, &ar);
+        V = av;
+        if (R == 0) R = ar;
+    }
+    if (R == 0) R = 1;
+    const int W = s.waves;
     if (!(V == 1 || V == 2 || V == 4 || V == 8)) return "vec must be 1, 2, 4 or 8";
+    if (!(R == 1 || R == 2 || R == 4)) return "rows must be 1, 2 or 4";
+    if (R > 1 && (V != 4 || (64 / R) * V < nx)) return "rows > 1 needs vec 4 and nx <= 256 / rows";
     if (W < 1 || W > 16) return "waves must be in 1..16";
     if (T < 1 || T > 4) return "t_block must be in 1..4";
     if (s.zchunk < 0 || s.rounds < 0) return "zchunk and rounds must be >= 0";
     const size_t lds = stream_lds_bytes(V, T, W);
     if (lds > kMaxLds) return "tile needs more LDS than a CU has (reduce waves, vec or t_block)";
     BlockGeom& g = pp->g;
-    g.nx = nx; g.ny = ny; g.nz = nz; g.W = W;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.W = W; g.R = R;
     const int RX = 64 * V;
     if (nx <= RX) { g.ntx = 1; g.ox = nx; }
     else {
@@ -155,10 +168,10 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
         if (g.ox < 1) return "x tile too narrow for t_block";
         g.ntx = (nx + g.ox - 1) / g.ox;
     }
-    if (ny <= W) { g.nty = 1; g.oy = ny; }
+    if (ny <= W * R) { g.nty = 1; g.oy = ny; }
     else {
-        g.oy = W - 2 * T;
-        if (g.oy < 1) return "too few waves for t_block (need waves > 2 * t_block)";
+        g.oy = W * R - 2 * T;
+        if (g.oy < 1) return "too few rows for t_block (need waves * rows > 2 * t_block)";
         g.nty = (ny + g.oy - 1) / g.oy;
     }
     g.vec = (g.ntx == 1 && nx % V == 0) ? 1 : 0;
@@ -240,7 +253,7 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
 static ig_schedule auto_schedule(const ig_params* p) {
     ig_schedule s{};
     s.kind = IG_SCHED_BLOCKED;
-    s.vec = pick_vec(p->nx);
+    auto_vec_rows(p->nx, &s.vec, &s.rows);
     s.t_block = std::max(1, std::min(2, p->n_iter));
     // 12 wavefronts and one round of pieces: the fastest on gfx950 for the
     // 512^3 cube in every conductance and storage type (measured over
@@ -344,7 +357,15 @@ extern "C" void ig_filter_destroy(ig_filter* f) {
 static ig_schedule resolve_schedule(const ig_filter* f) {
     if (f->sched.kind == IG_SCHED_AUTO) return auto_schedule(&f->p);
     ig_schedule s = f->sched;
-    if (s.kind == IG_SCHED_BLOCKED && s.vec == 0) s.vec = pick_vec(f->p.nx);
+    if (s.kind == IG_SCHED_BLOCKED) {
+        if (s.vec == 0) {
+            int V, R;
+            auto_vec_rows(f->p.nx, &V, &R);
+            s.vec = V;
+            if (s.rows == 0) s.rows = R;
+        }
+        if (s.rows == 0) s.rows = 1;
+    }
     return s;
 }
 
@@ -357,8 +378,9 @@ static ig_status check_schedule(const ig_params* p, const ig_schedule* s, int nc
     for (int T = 1; T <= s->t_block; ++T) {
         const char* why = plan_pass(*p, *s, T, ncu, &pp);
         if (why)
-            return fail(IG_ERR_INVALID_ARG, "schedule (t_block=%d waves=%d zchunk=%d vec=%d) cannot serve %lldx%lldx%lld: %s",
-                        s->t_block, s->waves, s->zchunk, s->vec, (long long)p->nx, (long long)p->ny,
+            return fail(IG_ERR_INVALID_ARG,
+                        "schedule (t_block=%d waves=%d zchunk=%d vec=%d rows=%d) cannot serve %lldx%lldx%lld: %s",
+                        s->t_block, s->waves, s->zchunk, s->vec, s->rows, (long long)p->nx, (long long)p->ny,
                         (long long)p->nz, why);
     }
     return IG_OK;
@@ -380,8 +402,9 @@ extern "C" ig_status ig_schedule_plan(const ig_params* p, const ig_schedule* s, 
     PassPlan pp;
     const char* why = plan_pass(*p, *s, t_block, ncu, &pp);
     if (why) return fail(IG_ERR_INVALID_ARG, "%s", why);
-    const int32_t g[8] = {pp.g.ntx, pp.g.nty, pp.g.ox, pp.g.oy, pp.g.W, pp.g.vec, pp.V, (int32_t)pp.pieces.size()};
-    for (int k = 0; k < 8; ++k) geom[k] = g[k];
+    const int32_t g[9] = {pp.g.ntx, pp.g.nty, pp.g.ox, pp.g.oy, pp.g.W, pp.g.vec, pp.V, (int32_t)pp.pieces.size(),
+                          pp.g.R};
+    for (int k = 0; k < 9; ++k) geom[k] = g[k];
     *count = (int64_t)pp.pieces.size();
     if (pieces)
         for (int64_t k = 0; k < std::min<int64_t>(cap, *count); ++k) {

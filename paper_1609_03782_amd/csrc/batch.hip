@@ -138,17 +138,19 @@ k_batch_stage(const BatchCube* __restrict__ cubes, const SumChunk* __restrict__ 
     for (long i = threadIdx.x; i < ch.len; i += 256) to[ch.off + i] = cb.in[ch.off + i];
 }
 
+// Batch cubes have nx <= 256, so the automatic layout is 4 voxels per lane
+// with 1, 2 or 4 rows per wavefront.
 template <int COND, int T, int D>
 __device__ __forceinline__ void run_piece_v(const BatchCube& cb, const float* src, float* dst, const Piece pc,
                                             const DevParams& P, float* lds) {
     const bool vec = cb.g.vec;
-    switch (cb.V) {
-        case 1: vec ? stream_piece<COND, float, 1, D, true>(src, dst, cb.g, pc, P, lds)
-                    : stream_piece<COND, float, 1, D, false>(src, dst, cb.g, pc, P, lds); break;
-        case 2: vec ? stream_piece<COND, float, 2, D, true>(src, dst, cb.g, pc, P, lds)
-                    : stream_piece<COND, float, 2, D, false>(src, dst, cb.g, pc, P, lds); break;
-        default: vec ? stream_piece<COND, float, 4, D, true>(src, dst, cb.g, pc, P, lds)
-                     : stream_piece<COND, float, 4, D, false>(src, dst, cb.g, pc, P, lds); break;
+    switch (cb.g.R) {
+        case 4: vec ? stream_piece<COND, float, 4, D, true, 4>(src, dst, cb.g, pc, P, lds)
+                    : stream_piece<COND, float, 4, D, false, 4>(src, dst, cb.g, pc, P, lds); break;
+        case 2: vec ? stream_piece<COND, float, 4, D, true, 2>(src, dst, cb.g, pc, P, lds)
+                    : stream_piece<COND, float, 4, D, false, 2>(src, dst, cb.g, pc, P, lds); break;
+        default: vec ? stream_piece<COND, float, 4, D, true, 1>(src, dst, cb.g, pc, P, lds)
+                     : stream_piece<COND, float, 4, D, false, 1>(src, dst, cb.g, pc, P, lds); break;
     }
 }
 
@@ -231,7 +233,7 @@ struct DevBuf {
 };
 struct BatchPlan {
     int device = 0;
-    int cond = 0, T = 1, W = 16;
+    int cond = 0, T = 1, W = 16, Z = 32;
     int count = 0;
     std::vector<int> passes;
     DevBuf<float> scratch;
@@ -264,12 +266,14 @@ std::mutex g_mu;
 std::map<std::vector<uint64_t>, std::unique_ptr<BatchPlan>> g_cache;
 int g_batch_T = 0;    // 0: default choice
 int g_batch_W = 16;
+int g_batch_Z = 32;   // planes per z-chunk of a piece
 
 std::vector<uint64_t> signature(const ig_batch_item* items, int count, int device) {
     std::vector<uint64_t> key;
     key.push_back((uint64_t)device);
     key.push_back((uint64_t)g_batch_T);
     key.push_back((uint64_t)g_batch_W);
+    key.push_back((uint64_t)g_batch_Z);
     for (int i = 0; i < count; ++i) {
         uint64_t w[(sizeof(ig_params) + 7) / 8] = {};
         std::memcpy(w, &items[i].p, sizeof(ig_params));
@@ -291,6 +295,7 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         maxnx = std::max<long>(maxnx, items[i].p.nx);
     }
     bp->W = g_batch_W;
+    bp->Z = g_batch_Z;
     bp->T = g_batch_T > 0 ? g_batch_T : std::max(1, std::min(2, maxn));
     const int T = bp->T, W = bp->W;
     if (maxnx > 256) return fail(IG_ERR_UNSUPPORTED, "batch items need nx <= 256");
@@ -318,11 +323,12 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         s.kind = IG_SCHED_BLOCKED;
         s.t_block = T;
         s.waves = W;
-        s.zchunk = 32;
+        s.zchunk = g_batch_Z;
         s.vec = 0;
         PassPlan pp;
         const char* why = plan_pass(p, s, T, ncu, &pp);
         if (why) return fail(IG_ERR_INVALID_ARG, "batch item %d: %s", c, why);
+        if (pp.V != 4) return fail(IG_ERR_UNSUPPORTED, "batch item %d: layout with %d voxels per lane", c, pp.V);
         lds = std::max(lds, stream_lds_bytes(pp.V, T, W));
         BatchCube& cb = cubes[c];
         cb.in = (const float*)items[c].d_in;
@@ -527,7 +533,7 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
             st.sum_out = osum[c].sum;
             st.nonfinite = prm[c].nonfinite;
             st.monotone = (2.0 * (double)p.tau * ((double)p.C[0] + p.C[1] + p.C[2]) <= 1.0) ? 1 : 0;
-            st.schedule = ig_schedule{IG_SCHED_BLOCKED, bp->T, bp->W, 32, 0, 0};
+            st.schedule = ig_schedule{IG_SCHED_BLOCKED, bp->T, bp->W, bp->Z, 4, 0, 0};
         }
         if (prm[c].abort) bad = true;
     }
@@ -541,7 +547,8 @@ extern "C" void ig_batch_cache_clear(void) {
 }
 
 extern "C" ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
-                                       int32_t* best_t_block, int32_t* best_waves, double* best_ms) {
+                                       int32_t* best_t_block, int32_t* best_waves, int32_t* best_zchunk,
+                                       double* best_ms) {
     if (!items || count < 1) return fail(IG_ERR_INVALID_ARG, "empty batch");
     for (int i = 0; i < count; ++i)
         if (items[i].d_in == items[i].d_out) return fail(IG_ERR_INVALID_ARG, "autotuning needs d_in != d_out");
@@ -551,36 +558,57 @@ extern "C" ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count
     HIP_TRY(hipEventCreate(&e1));
     int maxn = 0;
     for (int i = 0; i < count; ++i) maxn = std::max(maxn, items[i].p.n_iter);
+    // drop the plan of a candidate that is not kept (each plan holds scratch
+    // cubes for the whole batch)
+    auto drop = [&](int T, int W, int Z) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        const int t0 = g_batch_T, w0 = g_batch_W, z0 = g_batch_Z;
+        g_batch_T = T; g_batch_W = W; g_batch_Z = Z;
+        g_cache.erase(signature(items, count, device));
+        g_batch_T = t0; g_batch_W = w0; g_batch_Z = z0;
+    };
     double best = 1e300;
-    int bT = 0, bW = 16;
+    int bT = 0, bW = 16, bZ = 32;
     for (int T = 1; T <= std::max(1, std::min(4, maxn)); ++T)
-        for (int W : {8, 16}) {
-            if (W <= 2 * T) continue;
-            if (ig_batch_set_schedule(T, W) != IG_OK) continue;
-            if (ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) != IG_OK) continue;   // build + warm
-            float ms = 0.0f;
-            if (hipEventRecord(e0, s) != hipSuccess) continue;
-            bool ok = true;
-            for (int k = 0; k < 2 && ok; ++k) ok = ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) == IG_OK;
-            if (!ok || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) continue;
-            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
-            if (ms / 2 < best) { best = ms / 2; bT = T; bW = W; }
-        }
+        for (int W : {8, 12, 16})
+            for (int Z : {32, 64}) {
+                if (W <= 2 * T) continue;
+                if (ig_batch_set_schedule(T, W, Z) != IG_OK) continue;
+                if (ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) != IG_OK) {   // build + warm
+                    drop(T, W, Z);
+                    continue;
+                }
+                float ms = 0.0f;
+                bool ok = hipEventRecord(e0, s) == hipSuccess;
+                for (int k = 0; k < 2 && ok; ++k)
+                    ok = ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) == IG_OK;
+                ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                if (ok && ms / 2 < best) {
+                    if (best < 1e300) drop(bT, bW, bZ);
+                    best = ms / 2; bT = T; bW = W; bZ = Z;
+                } else {
+                    drop(T, W, Z);
+                }
+            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (best >= 1e300) return fail(IG_ERR_UNSUPPORTED, "no batch schedule ran");
-    ig_status st = ig_batch_set_schedule(bT, bW);
+    ig_status st = ig_batch_set_schedule(bT, bW, bZ);
     if (st != IG_OK) return st;
     if (best_t_block) *best_t_block = bT;
     if (best_waves) *best_waves = bW;
+    if (best_zchunk) *best_zchunk = bZ;
     if (best_ms) *best_ms = best;
     return IG_OK;
 }
 
-extern "C" ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves) {
-    if (t_block < 0 || t_block > 4 || waves < 1 || waves > 16) return fail(IG_ERR_INVALID_ARG, "bad batch schedule");
+extern "C" ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves, int32_t zchunk) {
+    if (t_block < 0 || t_block > 4 || waves < 1 || waves > 16 || zchunk < 1 || zchunk > 4096)
+        return fail(IG_ERR_INVALID_ARG, "bad batch schedule");
     std::lock_guard<std::mutex> lk(g_mu);
     g_batch_T = t_block;
     g_batch_W = waves;
+    g_batch_Z = zchunk;
     return IG_OK;
 }

@@ -58,7 +58,7 @@ struct PassPlan {
     std::vector<igk::Piece> pieces;
     int V = 0, T = 0;
 };
-int pick_vec(int64_t nx);
+void auto_vec_rows(int64_t nx, int* V, int* R);
 int resident_per_cu(int W, size_t lds);
 // nullptr on success, else the reason schedule s cannot serve p at depth T
 const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp);

@@ -34,10 +34,10 @@ static hipError_t naive_launch(const void* src, void* dst, int nx, int ny, int n
     return hipGetLastError();
 }
 
-template <int V, int T, bool VEC>
+template <int V, int T, bool VEC, int R>
 static hipError_t stream_one(const void* src, void* dst, const BlockGeom& g, const Piece* pieces, int npieces,
                              const DevParams* dp, hipStream_t s) {
-    auto kern = k_stream<IG_COND, ST, V, T, VEC>;
+    auto kern = k_stream<IG_COND, ST, V, T, VEC, R>;
     const size_t lds = stream_lds_bytes(V, T, g.W);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -47,31 +47,40 @@ static hipError_t stream_one(const void* src, void* dst, const BlockGeom& g, con
     return hipGetLastError();
 }
 
-template <int V, bool VEC>
+template <int V, bool VEC, int R>
 static hipError_t stream_T(const void* src, void* dst, const BlockGeom& g, int T, const Piece* pc, int np,
                            const DevParams* dp, hipStream_t s) {
     switch (T) {
-        case 1: return stream_one<V, 1, VEC>(src, dst, g, pc, np, dp, s);
-        case 2: return stream_one<V, 2, VEC>(src, dst, g, pc, np, dp, s);
-        case 3: return stream_one<V, 3, VEC>(src, dst, g, pc, np, dp, s);
-        case 4: return stream_one<V, 4, VEC>(src, dst, g, pc, np, dp, s);
+        case 1: return stream_one<V, 1, VEC, R>(src, dst, g, pc, np, dp, s);
+        case 2: return stream_one<V, 2, VEC, R>(src, dst, g, pc, np, dp, s);
+        case 3: return stream_one<V, 3, VEC, R>(src, dst, g, pc, np, dp, s);
+        case 4: return stream_one<V, 4, VEC, R>(src, dst, g, pc, np, dp, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int V>
+template <int V, int R>
 static hipError_t stream_V(const void* src, void* dst, const BlockGeom& g, int T, const Piece* pc, int np,
                            const DevParams* dp, hipStream_t s) {
-    return g.vec ? stream_T<V, true>(src, dst, g, T, pc, np, dp, s) : stream_T<V, false>(src, dst, g, T, pc, np, dp, s);
+    return g.vec ? stream_T<V, true, R>(src, dst, g, T, pc, np, dp, s)
+                 : stream_T<V, false, R>(src, dst, g, T, pc, np, dp, s);
 }
 
+// Rows per wavefront above 1 exist for V = 4 only (narrow cubes).
 static hipError_t blocked_launch(const void* src, void* dst, const BlockGeom& g, int V, int T, const Piece* pc,
                                  int np, const DevParams* dp, hipStream_t s) {
+    if (g.R != 1 && V != 4) return hipErrorInvalidValue;
     switch (V) {
-        case 1: return stream_V<1>(src, dst, g, T, pc, np, dp, s);
-        case 2: return stream_V<2>(src, dst, g, T, pc, np, dp, s);
-        case 4: return stream_V<4>(src, dst, g, T, pc, np, dp, s);
-        case 8: return stream_V<8>(src, dst, g, T, pc, np, dp, s);
+        case 1: return stream_V<1, 1>(src, dst, g, T, pc, np, dp, s);
+        case 2: return stream_V<2, 1>(src, dst, g, T, pc, np, dp, s);
+        case 4:
+            switch (g.R) {
+                case 1: return stream_V<4, 1>(src, dst, g, T, pc, np, dp, s);
+                case 2: return stream_V<4, 2>(src, dst, g, T, pc, np, dp, s);
+                case 4: return stream_V<4, 4>(src, dst, g, T, pc, np, dp, s);
+                default: return hipErrorInvalidValue;
+            }
+        case 8: return stream_V<8, 1>(src, dst, g, T, pc, np, dp, s);
         default: return hipErrorInvalidValue;
     }
 }

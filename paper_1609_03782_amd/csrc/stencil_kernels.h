@@ -37,8 +37,9 @@ struct BlockGeom {
     int nx, ny, nz;
     int ntx, nty;         // tile counts in x, y
     int ox, oy;           // output extent of a tile in x, y
-    int W;                // wavefronts (= rows) per workgroup (== blockDim.y)
+    int W;                // wavefronts per workgroup (== blockDim.y)
     int vec;              // 1: lane chunks are whole and aligned (vector I/O)
+    int R;                // rows per wavefront (1, 2 or 4); a tile has W * R rows
 };
 
 __device__ __forceinline__ float lane_shr1(float v) {  // lane i <- lane i-1, lane 0 <- 0
@@ -155,8 +156,9 @@ template <int V> struct Vec<__hip_bfloat16, V> : Vec16<__hip_bfloat16, V> {};
 template <int V> struct Vec<__half, V> : Vec16<__half, V> {};
 
 // ---------------------------------------------------------------- streaming
-// One workgroup = W wavefronts = W consecutive rows of a tile; one row per
-// wavefront, V voxels per lane (a row spans 64*V voxels).  Work comes from a
+// One workgroup = W wavefronts = W*R consecutive rows of a tile; R rows per
+// wavefront (64/R lanes per row, used for narrow cubes: R > 1 needs one x
+// tile), V voxels per lane (a row spans 64/R*V voxels).  Work comes from a
 // host-built piece table: piece b is (x tile, y tile, z0, z1) with outputs in
 // planes [z0, z1).  Per step s the workgroup takes the input plane loaded one
 // step earlier, issues the load of the next one, and advances every level by
@@ -177,11 +179,14 @@ template <int V> struct Vec<__half, V> : Vec16<__half, V> {};
 //  itself from the rows above and below.  An edge term depends only on the
 //  two voxels' values, so both wavefronts obtain the same bits.
 //
-// LDS holds, per level, W+2 row slots of 64*V floats: wavefront w uses slot
-// w+1, slots 0 and W+1 hold zeros so the wavefronts at the tile's edge read
-// without a branch (their edge coefficient is the closed one, or the row is
-// halo).  Element i of a lane's chunk sits at i*64 + lane: consecutive lanes
-// hit consecutive banks.
+// LDS holds, per level, W+2 slots of 64*V floats: wavefront w uses slot w+1
+// (its R rows side by side, lane groups of 64/R), slots 0 and W+1 hold zeros so
+// the rows at the tile's edge read without a branch (their edge coefficient is
+// the closed one, or the row is halo).  Element i of a lane's chunk sits at
+// i*64 + lane: consecutive lanes hit consecutive banks.  With R > 1 the x edge
+// between the last lane of one row and the first lane of the next (adjacent
+// lanes, exchanged by the same DPP shifts) has the closed coefficient, since
+// a row's lanes cover the whole row, so no value crosses rows.
 struct Piece {
     int tx, ty, z0, z1;
 };
@@ -195,14 +200,18 @@ constexpr bool y_row_shared() {
 // One piece of one pass: the whole per-workgroup algorithm above.  `lds`
 // must hold stream_lds_bytes(V, T, W) bytes.  Called by k_stream (one cube)
 // and by the batch round kernel.
-template <int COND, typename ST, int V, int T, bool VEC>
+template <int COND, typename ST, int V, int T, bool VEC, int R>
 __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __restrict__ dst, const BlockGeom& g,
                                              const Piece pc, const DevParams& P, float* __restrict__ lds) {
     constexpr int RX = 64 * V;
+    constexpr int LR = 64 / R;                    // lanes per row
     constexpr bool RS = y_row_shared<COND>();
     const int lane = threadIdx.x;
+    const int sr = R == 1 ? 0 : lane / LR;        // this lane's row within the wavefront
+    const int lr = R == 1 ? lane : lane % LR;     // this lane's place in its row
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int W = g.W;
+    const int rows = W * R;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
 
     const int ox0 = pc.tx * g.ox, oy0 = pc.ty * g.oy;
@@ -212,8 +221,8 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     const int ry0 = g.nty > 1 ? oy0 - T : 0;
     const int zin0 = max(oz0 - T, 0), zin1 = min(oz1 + T, nz);
     const int nin = zin1 - zin0;
-    const int y = ry0 + w;                        // this wavefront's row
-    const int xl0 = rx0 + lane * V;
+    const int y = ry0 + w * R + sr;               // this lane's row
+    const int xl0 = rx0 + lr * V;
 
     // x edge coefficients.  Vector path (one x tile, nx a multiple of V): the
     // edges inside a lane's chunk are open (or belong to a lane past the end
@@ -234,9 +243,9 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     const bool row_in = y >= 0 && y < ny;
     const bool row_store = y >= oy0 && y < oy1;
     const int lo_base = ry0 <= 0 ? 0 : ry0;
-    const int hi_base = ry0 + W >= ny ? ny : ry0 + W;
+    const int hi_base = ry0 + rows >= ny ? ny : ry0 + rows;
     const int lo_step = ry0 <= 0 ? 0 : 1;
-    const int hi_step = ry0 + W >= ny ? 0 : 1;
+    const int hi_step = ry0 + rows >= ny ? 0 : 1;
 
     const int ycl = min(max(y, 0), ny - 1);
     const long plane = (long)nx * ny;
@@ -249,6 +258,9 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     const int lvl = (W + 2) * RX;
     const int reg1 = T * lvl;
     const int slot = (w + 1) * RX + lane;            // + t * lvl + i * 64 (+ reg1)
+    // offsets to the same lane place in the rows above and below
+    const int up_off = (R == 1 || sr == R - 1) ? RX - (R - 1) * LR : LR;
+    const int dn_off = (R == 1 || sr == 0) ? -(RX - (R - 1) * LR) : -LR;
 
     // Register rotation (the step loop is unrolled by two, parity p known at
     // compile time): lv[t][p] is level t's current plane and lv[t][p^1] the
@@ -315,7 +327,13 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
             const bool compute = STEADY || ((s - t - 1 >= 0) && (s - t - 1 < nin));
             const int pz = zin0 + s - t - 1;
             // halo rows of a level are never used by a valid row: skip them
-            if (!compute || !valid[t]) continue;
+            // (with R > 1, when no row of the wavefront is valid)
+            if (!compute) continue;
+            if constexpr (R == 1) {
+                if (!valid[t]) continue;
+            } else {
+                if (!__any(valid[t])) continue;
+            }
             const float czp = (STEADY || (pz + 1 < nz && has_nxt)) ? P.coef[2] : P.closed;
             float ex[V];
 #pragma unroll
@@ -332,10 +350,10 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
                 const float c = lv[t][p][i];
                 float eyd, eyu;
                 if constexpr (RS) {
-                    eyd = edge_term<COND>(c - lds[ro - RX + 64 * i], cyd, P.kap);
-                    eyu = edge_term<COND>(lds[ro + RX + 64 * i] - c, cyu, P.kap);
+                    eyd = edge_term<COND>(c - lds[ro + dn_off + 64 * i], cyd, P.kap);
+                    eyu = edge_term<COND>(lds[ro + up_off + 64 * i] - c, cyu, P.kap);
                 } else {
-                    eyd = lds[ro - RX + 64 * i];
+                    eyd = lds[ro + dn_off + 64 * i];
                     eyu = lds[ro + 64 * i];
                 }
                 const float up_z = has_nxt ? lv[t][q][i] : c;
@@ -377,7 +395,8 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
                     const int ro = t * lvl + slot;
 #pragma unroll
                     for (int i = 0; i < V; ++i)
-                        lds[reg1 + ro + 64 * i] = edge_term<COND>(lds[ro + RX + 64 * i] - lv[t][q][i], cyu, P.kap);
+                        lds[reg1 + ro + 64 * i] =
+                            edge_term<COND>(lds[ro + up_off + 64 * i] - lv[t][q][i], cyu, P.kap);
                 }
             }
             __syncthreads();
@@ -412,14 +431,14 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     }
 }
 
-template <int COND, typename ST, int V, int T, bool VEC>
+template <int COND, typename ST, int V, int T, bool VEC, int R>
 __global__ void __launch_bounds__(1024)
 k_stream(const ST* __restrict__ src, ST* __restrict__ dst, BlockGeom g, const Piece* __restrict__ pieces,
          const DevParams* __restrict__ dp) {
     extern __shared__ float lds[];
     const DevParams P = *dp;
     if (P.abort) return;
-    stream_piece<COND, ST, V, T, VEC>(src, dst, g, pieces[blockIdx.x], P, lds);
+    stream_piece<COND, ST, V, T, VEC, R>(src, dst, g, pieces[blockIdx.x], P, lds);
 }
 
 }  // namespace igk

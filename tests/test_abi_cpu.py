@@ -104,7 +104,17 @@ def test_gpu_test_schedules_are_valid():
             assert ig.schedule_check(shape, s, n_iter=7) is None, (shape, s)
     for s in g.INPLACE_SCHEDS:
         assert ig.schedule_check(g.INPLACE_SHAPE, s, n_iter=5) is None, s
-    assert ig.schedule_check((17, 33, 66), dict(kind="blocked", t_block=4, waves=8)) is not None
+    for shape in g.ROWS_SHAPES:
+        for s in g.ROWS_SCHEDS:
+            if 64 // s["rows"] * 4 >= shape[2]:
+                assert ig.schedule_check(shape, s, n_iter=7) is None, (shape, s)
+    assert ig.schedule_check((17, 33, 66), dict(kind="blocked", t_block=4, waves=8, vec=2)) is not None
+    # automatic layout for nx = 66: 4 voxels per lane, 2 rows per wavefront -> 16 rows, enough for t_block 4
+    assert ig.schedule_check((17, 33, 66), dict(kind="blocked", t_block=4, waves=8)) is None
+    assert ig.schedule_check((17, 33, 66), dict(kind="blocked", t_block=2, waves=8, vec=8, rows=2)) is not None
+    assert ig.schedule_check((17, 33, 100), dict(kind="blocked", t_block=2, waves=8, vec=4, rows=4)) is not None
+    assert ig.schedule_check((17, 33, 64), dict(kind="blocked", t_block=2, waves=8, vec=4, rows=4)) is None
+    assert ig.schedule_check((17, 33, 64), dict(kind="blocked", t_block=2, waves=8, vec=4, rows=3)) is not None
     assert ig.schedule_check((17, 33, 600), dict(kind="blocked", t_block=4, waves=16, vec=8)) is not None
 
 

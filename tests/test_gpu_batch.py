@@ -41,11 +41,12 @@ def _items(dev, seed=0):
     return cubes, items
 
 
-@pytest.mark.parametrize("t_block,waves", [(0, 16), (1, 8), (2, 16), (3, 8), (4, 16)])
-def test_batch_matches_oracle_and_single_runs(dev, oracle_lib, t_block, waves):
+@pytest.mark.parametrize("t_block,waves,zchunk", [(0, 16, 32), (1, 8, 7), (2, 16, 64), (3, 8, 13), (4, 16, 32),
+                                                  (2, 12, 5)])
+def test_batch_matches_oracle_and_single_runs(dev, oracle_lib, t_block, waves, zchunk):
     import torch
     import paper_1609_03782_amd as ig
-    ig.batch_set_schedule(t_block, waves)
+    ig.batch_set_schedule(t_block, waves, zchunk)
     try:
         cubes, items = _items(dev)
         res = ig.batch(items, want_stats=True, want_latency=True)
@@ -64,7 +65,7 @@ def test_batch_matches_oracle_and_single_runs(dev, oracle_lib, t_block, waves):
             torch.cuda.synchronize()
             assert np.array_equal(ys.cpu().numpy(), y), (c.shape, n_iter)
     finally:
-        ig.batch_set_schedule(0, 16)
+        ig.batch_set_schedule(0, 16, 32)
         ig.batch_cache_clear()
 
 

@@ -129,6 +129,29 @@ def test_identity_cases_bitwise(dev):
     assert np.array_equal(_run(zero, dev, n_iter=3), zero)
 
 
+# several rows per wavefront (narrow cubes): explicit layouts against the naive schedule
+ROWS_SHAPES = [(11, 29, 40), (6, 50, 64), (9, 23, 100), (4, 70, 17)]
+ROWS_SCHEDS = [dict(kind="blocked", t_block=1, waves=2, vec=4, rows=4),
+               dict(kind="blocked", t_block=3, waves=4, vec=4, rows=2, zchunk=3),
+               dict(kind="blocked", t_block=2, waves=3, vec=4, rows=2, rounds=2),
+               dict(kind="blocked", t_block=4, waves=16, vec=4, rows=2)]
+
+
+@pytest.mark.parametrize("cond", CONDS)
+@pytest.mark.parametrize("shape", ROWS_SHAPES)
+def test_rows_per_wavefront_bitwise(dev, oracle_lib, cond, shape):
+    cube = igsynth.random_cube(shape, seed=3 * sum(shape), scale=2.0)
+    kw = dict(K=1.3, tau=0.05, n_iter=7, C=(1.0, 0.7, 1.3), cond=cond)
+    ref, rho = oracle_lib.run(cube, cond, K=1.3, tau=0.05, n_iter=7, C=(1.0, 0.7, 1.3))
+    y0 = _run(cube, dev, sched=dict(kind="naive"), **kw)
+    assert _err(y0, ref) <= TOL * rho
+    for sc in ROWS_SCHEDS:
+        if 64 // sc["rows"] * 4 < shape[2]:
+            continue
+        y = _run(cube, dev, sched=sc, **kw)
+        assert np.array_equal(y, y0), (shape, sc)
+
+
 INPLACE_SHAPE = (17, 33, 66)
 INPLACE_SCHEDS = [dict(kind="naive"), dict(kind="blocked", t_block=1, waves=4, zchunk=8),
                   dict(kind="blocked", t_block=2, waves=8, zchunk=8),

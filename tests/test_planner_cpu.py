@@ -32,9 +32,9 @@ def test_pieces_cover_every_output_once(shape, sched):
             cover[z0:z1, y0:y0 + g["oy"], x0:x0 + g["ox"]] += 1
         assert cover.min() == 1 and cover.max() == 1, (shape, sched, T)
         if g["ntx"] == 1:
-            assert 64 * g["V"] >= nx
+            assert 64 // g["rows"] * g["V"] >= nx
         if g["nty"] == 1:
-            assert g["waves"] >= ny
+            assert g["waves"] * g["rows"] >= ny
 
 
 def test_balanced_split_whole_rounds():
