@@ -41,60 +41,72 @@ __device__ __forceinline__ void sep_weights(const SepGeom& g, float* w) {
     }
 }
 
-// x pass: one row segment of kSepRow outputs per workgroup of kSepRow threads.
+// x pass: row segments of kSepRow outputs, kSepRowsX rows per workgroup of
+// kSepRow threads (the weights are computed once per workgroup).
+constexpr int kSepRowsX = 8;
 __global__ void __launch_bounds__(kSepRow)
 k_sep_x(const float* __restrict__ src, float* __restrict__ dst, SepGeom g) {
     __shared__ float w[2 * kSepMaxR + 1];
-    __shared__ float row[kSepRow + 2 * kSepMaxR];
+    __shared__ float row[kSepRowsX][kSepRow + 2 * kSepMaxR];
     const int r = g.r;
     const long x0 = (long)blockIdx.x * kSepRow;
-    const long base = g.nx * ((long)blockIdx.y + g.ny * (long)blockIdx.z);
+    const long nrows = g.ny * g.nz;
+    const long row0 = (long)blockIdx.y * kSepRowsX;
     sep_weights(g, w);
-    for (int i = threadIdx.x; i < kSepRow + 2 * r; i += kSepRow) {
-        const long x = x0 - r + i;
-        row[i] = (x >= 0 && x < g.nx) ? src[base + x] : 0.0f;
+    for (int k = 0; k < kSepRowsX; ++k) {
+        const long rw = row0 + k;
+        if (rw >= nrows) break;
+        for (int i = threadIdx.x; i < kSepRow + 2 * r; i += kSepRow) {
+            const long x = x0 - r + i;
+            row[k][i] = (x >= 0 && x < g.nx) ? src[rw * g.nx + x] : 0.0f;
+        }
     }
     __syncthreads();
     const long x = x0 + threadIdx.x;
     if (x >= g.nx) return;
     const int lo = (int)max(-(long)r, -x), hi = (int)min((long)r, g.nx - 1 - x);
-    float acc = 0.0f, ws = 0.0f;
-    for (int k = lo; k <= hi; ++k) {
-        acc = __builtin_fmaf(w[k + r], row[threadIdx.x + r + k], acc);
-        ws += w[k + r];
+    float ws = 0.0f;
+    for (int k = lo; k <= hi; ++k) ws += w[k + r];
+    for (int j = 0; j < kSepRowsX; ++j) {
+        const long rw = row0 + j;
+        if (rw >= nrows) break;
+        float acc = 0.0f;
+        for (int k = lo; k <= hi; ++k) acc = __builtin_fmaf(w[k + r], row[j][threadIdx.x + r + k], acc);
+        dst[rw * g.nx + x] = acc / ws;
     }
-    dst[base + x] = acc / ws;
 }
 
-// y (AXIS 1) or z (AXIS 2) pass: 64 columns in x, kSepSeg outputs along the
-// axis per workgroup of 64 x 4 threads.
+// y (AXIS 1) or z (AXIS 2) pass: kSepCols columns in x (512-byte row pieces),
+// kSepSeg outputs along the axis per workgroup of kSepCols x 2 threads; the
+// tile with its halo sits in dynamic LDS.
+constexpr int kSepCols = 128;
 template <int AXIS>
 __global__ void __launch_bounds__(256)
 k_sep_yz(const float* __restrict__ src, float* __restrict__ dst, SepGeom g) {
     __shared__ float w[2 * kSepMaxR + 1];
-    __shared__ float tile[kSepSeg + 2 * kSepMaxR][64];
+    extern __shared__ float tile[];   // [kSepSeg + 2r][kSepCols]
     const int r = g.r;
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const long x = (long)blockIdx.x * 64 + tx;
+    const long x = (long)blockIdx.x * kSepCols + tx;
     const long a0 = (long)blockIdx.y * kSepSeg;          // first output along the axis
     const long other = blockIdx.z;                        // z for the y pass, y for the z pass
     const long na = AXIS == 1 ? g.ny : g.nz;
     const long sa = AXIS == 1 ? g.nx : g.nx * g.ny;       // stride along the axis
     const long base = x + (AXIS == 1 ? other * g.nx * g.ny : other * g.nx);
     sep_weights(g, w);
-    for (int i = ty; i < kSepSeg + 2 * r; i += 4) {
+    for (int i = ty; i < kSepSeg + 2 * r; i += 2) {
         const long a = a0 - r + i;
-        tile[i][tx] = (x < g.nx && a >= 0 && a < na) ? src[base + a * sa] : 0.0f;
+        tile[i * kSepCols + tx] = (x < g.nx && a >= 0 && a < na) ? src[base + a * sa] : 0.0f;
     }
     __syncthreads();
     if (x >= g.nx) return;
-    for (int j = ty; j < kSepSeg; j += 4) {
+    for (int j = ty; j < kSepSeg; j += 2) {
         const long a = a0 + j;
         if (a >= na) break;
         const int lo = (int)max(-(long)r, -a), hi = (int)min((long)r, na - 1 - a);
         float acc = 0.0f, ws = 0.0f;
         for (int k = lo; k <= hi; ++k) {
-            acc = __builtin_fmaf(w[k + r], tile[j + r + k][tx], acc);
+            acc = __builtin_fmaf(w[k + r], tile[(j + r + k) * kSepCols + tx], acc);
             ws += w[k + r];
         }
         dst[base + a * sa] = acc / ws;
@@ -323,21 +335,30 @@ extern "C" ig_status ig_smooth(const ig_smooth_params* s, const float* d_in, flo
         SepGeom g{nx, ny, nz, 0, s->kind, 0.0};
         g.r = p.r[0];
         g.sigma = p.sigma[0];
-        hipLaunchKernelGGL(k_sep_x, dim3((unsigned)((nx + kSepRow - 1) / kSepRow), (unsigned)ny, (unsigned)nz),
-                           dim3(kSepRow), 0, st_, d_in, d_out, g);
+        const long xrows = (ny * nz + kSepRowsX - 1) / kSepRowsX;
+        if (xrows > 2147483647L) return fail(IG_ERR_UNSUPPORTED, "cube too large");
+        hipLaunchKernelGGL(k_sep_x, dim3((unsigned)((nx + kSepRow - 1) / kSepRow), (unsigned)xrows), dim3(kSepRow), 0,
+                           st_, d_in, d_out, g);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(IG_ERR_DEVICE, "x pass: %s", hipGetErrorString(e));
         g.r = p.r[1];
         g.sigma = p.sigma[1];
-        hipLaunchKernelGGL(k_sep_yz<1>, dim3((unsigned)((nx + 63) / 64), (unsigned)((ny + kSepSeg - 1) / kSepSeg),
-                                             (unsigned)nz),
-                           dim3(64, 4), 0, st_, (const float*)d_out, d_work, g);
+        const unsigned gx = (unsigned)((nx + kSepCols - 1) / kSepCols);
+        size_t lds = (size_t)(kSepSeg + 2 * g.r) * kSepCols * sizeof(float);
+        if (lds > 65536 && (e = hipFuncSetAttribute((const void*)k_sep_yz<1>,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+            return fail(IG_ERR_DEVICE, "y pass: %s", hipGetErrorString(e));
+        hipLaunchKernelGGL(k_sep_yz<1>, dim3(gx, (unsigned)((ny + kSepSeg - 1) / kSepSeg), (unsigned)nz),
+                           dim3(kSepCols, 2), lds, st_, (const float*)d_out, d_work, g);
         if ((e = hipGetLastError()) != hipSuccess) return fail(IG_ERR_DEVICE, "y pass: %s", hipGetErrorString(e));
         g.r = p.r[2];
         g.sigma = p.sigma[2];
-        hipLaunchKernelGGL(k_sep_yz<2>, dim3((unsigned)((nx + 63) / 64), (unsigned)((nz + kSepSeg - 1) / kSepSeg),
-                                             (unsigned)ny),
-                           dim3(64, 4), 0, st_, (const float*)d_work, d_out, g);
+        lds = (size_t)(kSepSeg + 2 * g.r) * kSepCols * sizeof(float);
+        if (lds > 65536 && (e = hipFuncSetAttribute((const void*)k_sep_yz<2>,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+            return fail(IG_ERR_DEVICE, "z pass: %s", hipGetErrorString(e));
+        hipLaunchKernelGGL(k_sep_yz<2>, dim3(gx, (unsigned)((nz + kSepSeg - 1) / kSepSeg), (unsigned)ny),
+                           dim3(kSepCols, 2), lds, st_, (const float*)d_work, d_out, g);
         if ((e = hipGetLastError()) != hipSuccess) return fail(IG_ERR_DEVICE, "z pass: %s", hipGetErrorString(e));
         return IG_OK;
     }

@@ -181,7 +181,12 @@ ig_status check(const ig_wavelet_params* p, const void* a, const void* b, int64_
     return IG_OK;
 }
 
+// Lines per workgroup along y or z: the widest whose LDS tile stays within
+// 64 KiB (two or more workgroups per CU hide the loads of one another), else
+// the widest that fits at all.
 int lines_per_block(long n) {
+    for (int W : {64, 32, 16})
+        if ((size_t)n * W * sizeof(float) <= 65536) return W;
     for (int W : {64, 32, 16})
         if ((size_t)n * W * sizeof(float) <= kMaxLds) return W;
     return 0;
