@@ -11,8 +11,9 @@
 //
 //  * up to 8 thresholds (the sweep's case): voxel-parallel.  Each thread keeps
 //    every mask's sums in registers and walks its voxels in a fixed order
-//    (row segments of the ROI, grid-stride); a fixed shuffle tree and the
-//    wavefronts in order make one partial per workgroup.  Bound by HBM.
+//    (a contiguous range of ROI rows per workgroup, four loads in flight per
+//    thread); a fixed shuffle tree and the wavefronts in order make one
+//    partial per workgroup.  Bound by HBM.
 //  * more thresholds: lane j of every wavefront owns mask j.  A wavefront
 //    takes 64-voxel chunks in a fixed order, parks each chunk's three values
 //    as FP64 in its LDS slice, and every lane walks the 64 voxels in order
@@ -67,26 +68,47 @@ k_quality_vox(const float* __restrict__ orig, const float* __restrict__ filt, co
 #pragma unroll
     for (int k = 0; k < K; ++k) thr[k] = g.thr[k];
     const double thr_o = g.thr[63];
-    const long segs = (g.rx + kQSeg - 1) / kQSeg;
-    for (long t = blockIdx.x; t < g.nrows * segs; t += gridDim.x) {
-        const long row = t / segs, seg = t - row * segs;
-        const long x = seg * kQSeg + threadIdx.x;
-        if (x >= g.rx) continue;
-        const long y = row % g.ry, z = row / g.ry;
-        const long idx = (g.x0 + x) + g.nx * ((g.y0 + y) + g.ny * (g.z0 + z));
-        const double o = (double)orig[idx], f = (double)filt[idx];
-        const double m = g.has_model ? (double)model[idx] : 0.0;
+    // workgroup b takes a contiguous range of ROI rows (sequential memory),
+    // (y, z) carried from row to row; within a row, thread t takes voxels
+    // t, t + kQSeg, ... (kQUnroll loads in flight)
+    constexpr int kQUnroll = 4;
+    const long per = (g.nrows + gridDim.x - 1) / gridDim.x;
+    const long r0 = (long)blockIdx.x * per, r1 = min(g.nrows, r0 + per);
+    long y = r0 % g.ry, z = r0 / g.ry;
+    for (long row = r0; row < r1; ++row) {
+        const long base = g.x0 + g.nx * ((g.y0 + y) + g.ny * (g.z0 + z));
+        for (long x0 = 0; x0 < g.rx; x0 += (long)kQSeg * kQUnroll) {
+            float fo[kQUnroll], ff[kQUnroll], fm[kQUnroll];
+            bool in[kQUnroll];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const bool p = f >= thr[k];
-            acc[3 * k] += p ? o : 0.0;
-            acc[3 * k + 1] += p ? m : 0.0;
-            acc[3 * k + 2] += p ? 1.0 : 0.0;
+            for (int u = 0; u < kQUnroll; ++u) {
+                const long x = x0 + u * kQSeg + threadIdx.x;
+                in[u] = x < g.rx;
+                fo[u] = in[u] ? orig[base + x] : 0.0f;
+                ff[u] = in[u] ? filt[base + x] : 0.0f;
+                fm[u] = (in[u] && g.has_model) ? model[base + x] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kQUnroll; ++u) {
+                if (!in[u]) continue;
+                const double o = (double)fo[u], f = (double)ff[u], m = (double)fm[u];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const bool p = f >= thr[k];
+                    acc[3 * k] += p ? o : 0.0;
+                    acc[3 * k + 1] += p ? m : 0.0;
+                    acc[3 * k + 2] += p ? 1.0 : 0.0;
+                }
+                const bool po = o >= thr_o;
+                acc[3 * K] += po ? o : 0.0;
+                acc[3 * K + 1] += m;
+                acc[3 * K + 2] += po ? 1.0 : 0.0;
+            }
         }
-        const bool po = o >= thr_o;
-        acc[3 * K] += po ? o : 0.0;
-        acc[3 * K + 1] += m;
-        acc[3 * K + 2] += po ? 1.0 : 0.0;
+        if (++y == g.ry) {
+            y = 0;
+            ++z;
+        }
     }
     __shared__ double red[kQWaves][NA];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -298,8 +320,7 @@ extern "C" ig_status ig_quality(const ig_quality_params* q, const float* d_orig,
     long count;
     if (q->n_thr <= 8) {
         const int K = q->n_thr <= 1 ? 1 : q->n_thr <= 2 ? 2 : q->n_thr <= 4 ? 4 : 8;
-        const long segs = g.nrows * ((g.rx + kQSeg - 1) / kQSeg);
-        const int blocks = (int)std::min<long>(kQMaxBlocks * 2, segs);
+        const int blocks = (int)std::min<long>(kQMaxBlocks * 2, g.nrows);
         auto k = K == 1 ? k_quality_vox<1> : K == 2 ? k_quality_vox<2> : K == 4 ? k_quality_vox<4> : k_quality_vox<8>;
         hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, s, d_orig, d_filt, d_model, g, qs.part);
         count = blocks;
