@@ -47,7 +47,8 @@ typedef struct {
  * three separable passes (1) or one dense pass (0).  Host only. */
 ig_status ig_smooth_geometry(const ig_smooth_params* s, int32_t* radius, int32_t* separable);
 
-/* Smooth d_in (FP32, nx*ny*nz voxels, x fastest) into d_out on hip_stream.
+/* Smooth d_in (FP32, nx*ny*nz voxels, x fastest) into d_out on hip_stream;
+ * the buffers and the stream belong to the calling thread's current device.
  * d_work: nx*ny*nz FP32 device scratch, required by the separable path (it
  * holds the middle pass), ignored (may be NULL) by the dense one.  d_in is only
  * read; d_in, d_out and d_work must not overlap.  Asynchronous.  Errors:

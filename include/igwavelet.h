@@ -46,7 +46,8 @@ typedef struct {
 
 /* Forward transform of the FP32 cube d_in (nx*ny*nz, x fastest) into d_coef
  * (d_coef == d_in allowed; otherwise they must not overlap).  Asynchronous on
- * hip_stream.  Errors: IG_ERR_INVALID_ARG (NULL, partial overlap, bad sizes,
+ * hip_stream; buffers and stream belong to the calling thread's current device
+ * (as for every entry point of this header).  Errors: IG_ERR_INVALID_ARG (NULL, partial overlap, bad sizes,
  * kind, levels or reserved), IG_ERR_UNSUPPORTED (a line along y or z longer
  * than 2560, or along x longer than 10240: it must fit one compute unit's
  * LDS), IG_ERR_DEVICE. */
