@@ -55,8 +55,10 @@ ig_status ig_smooth_geometry(const ig_smooth_params* s, int32_t* radius, int32_t
  * IG_ERR_INVALID_ARG (NULL or overlapping buffers, bad sizes, even or
  * non-integer box sizes, FWHM <= 0, non-finite values, non-zero reserved or box
  * angles), IG_ERR_UNSUPPORTED (a half-width above 31 for the separable path,
- * or a dense kernel whose input tile exceeds the LDS of one compute unit:
- * (64 + 2 r_x)(4 + 2 r_y)(4 + 2 r_z) x 4 B > 160 KiB), IG_ERR_DEVICE. */
+ * or a dense kernel too large for one compute unit's LDS: its
+ * (2 r_x + 1)(2 r_y + 1)(2 r_z + 1) weights plus an input tile of at least
+ * (64 + 2 r_x)(4 + 2 r_y)(1 + 2 r_z) voxels, x 4 B, above 160 KiB),
+ * IG_ERR_DEVICE. */
 ig_status ig_smooth(const ig_smooth_params* s, const float* d_in, float* d_out, float* d_work, int64_t nx,
                     int64_t ny, int64_t nz, void* hip_stream);
 
