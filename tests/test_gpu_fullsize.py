@@ -101,3 +101,23 @@ def test_16bit_storage_vs_rounding_oracle(dev, oracle_lib, name):
     # and the whole run stays close to the exact (unrounded) filter
     exact, _ = oracle_lib.run(q, "pm_exp", K=2.0, tau=1 / 16, n_iter=n)
     assert np.sqrt(np.mean((g - exact) ** 2)) <= (0.02 if name == "bf16" else 0.003) * rho
+
+
+def test_intensity_weighted_conservation_fullsize(dev, field):
+    """One step of the intensity form conserves sum (I1 - I0)(1 + I0^2/(K rho)^2)
+    (the weight is 1/S at the centre and each edge term is antisymmetric), so
+    on the whole 512^3 cube the weighted change cancels to rounding."""
+    import torch
+    import paper_1609_03782_amd as ig
+    cube, x = field
+    K = 1.5
+    f = ig.Filter(cube.shape, K=K, tau=0.0325, n_iter=1, C=(5.0, 5.0, 5.0), cond="intensity")
+    y, st = f.run(x, stats=True)
+    torch.cuda.synchronize()
+    kap = 1.0 / (K * st.rms_used) ** 2
+    x64 = x.double()
+    wchg = (y.double() - x64) * (1.0 + x64 * x64 * kap)
+    total = float(wchg.sum())
+    scale = float(wchg.abs().sum())
+    print(f"weighted change: sum {total:.3e} against sum of magnitudes {scale:.3e}")
+    assert scale > 0 and abs(total) <= 1e-6 * scale
