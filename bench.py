@@ -30,18 +30,20 @@ SHAPE = (512, 512, 512)   # (nz, ny, nx)
 
 def cpu_baseline(cube, n_iter, K, tau, nz_s=None):
     """The FP64 oracle on the same cube (all host threads): the whole cube by
-    default (about 15 s on 16 cores), or its first nz_s planes."""
+    default (about 15 s on 16 cores), or its first nz_s planes.  Returns the
+    baseline record, the oracle's output and the rms it used."""
     import oracle
     oracle.build(force=False)
     slab = cube if nz_s is None else cube[:nz_s]
     t0 = time.perf_counter()
-    oracle.run(slab, "pm_exp", K=K, tau=tau, n_iter=n_iter)
+    out, rho = oracle.run(slab, "pm_exp", K=K, tau=tau, n_iter=n_iter)
     dt = time.perf_counter() - t0
     vi = slab.size * n_iter
     nz, ny, nx = slab.shape
     what = "the whole cube" if nz_s is None else "a slab of the same cube"
-    return {"value": round(vi / dt / 1e9, 5), "unit": "Gvoxel-iter/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{what}: {nx}x{ny}x{nz}, {n_iter} iterations, rms estimated, FP64 ({dt:.1f} s)"}
+    rec = {"value": round(vi / dt / 1e9, 5), "unit": "Gvoxel-iter/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"{what}: {nx}x{ny}x{nz}, {n_iter} iterations, rms estimated, FP64 ({dt:.1f} s)"}
+    return rec, out, rho
 
 
 # Algorithmic ALU work of one voxel-iteration of the edge-shared exponential
@@ -107,12 +109,15 @@ def time_runs(f, x, out, steps, warmup, timing=False):
     return ms, kt
 
 
-def bench_precision(cube_t, steps, ref_out):
-    """16-bit storage of the same cube: throughput and deviation from the FP32 run."""
+def bench_precision(cube_t, steps, ref_out, keep=None):
+    """16-bit storage of the same cube: throughput and deviation from the FP32
+    run in units of the cube's rms; `keep` (a dict) receives host copies of
+    the outputs for the comparison with the FP64 oracle."""
     import torch
     import paper_1609_03782_amd as ig
     res = {}
     ref = ref_out.double()
+    rho = float(torch.sqrt((cube_t.double() ** 2).mean()))
     for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
         x = cube_t.to(dt)
         out = torch.empty_like(x)
@@ -121,9 +126,42 @@ def bench_precision(cube_t, steps, ref_out):
         d = out.double() - ref
         res[name] = {"ms_per_run": round(ms, 4), "Gvoxel_iter_s": round(x.numel() * N_ITER / ms / 1e6, 2),
                      "effective_hbm_GBps": round(4.0 * x.numel() * N_ITER / ms / 1e6, 1),
-                     "max_abs_vs_f32_rms": float(d.abs().max()), "rms_vs_f32_rms": float(d.pow(2).mean().sqrt()),
+                     "max_abs_vs_f32_in_rms": float(d.abs().max()) / rho,
+                     "rmse_vs_f32_in_rms": float(d.pow(2).mean().sqrt()) / rho,
                      "schedule": f.schedule()}
+        if keep is not None:
+            keep[name] = (out.float().cpu().numpy(), ms)
     return res
+
+
+def errors_vs_oracle(outs, ref, rho, ms_f32):
+    """Max-abs and RMS error of each GPU output against the FP64 oracle's
+    output for the whole cube, in units of rho, with each 16-bit form's
+    speed-up over the FP32 GPU run."""
+    import numpy as np
+    res = {}
+    for name, (y, ms) in outs.items():
+        d = y.astype(np.float64) - ref
+        res[name] = {"max_abs_in_rms": float(np.abs(d).max()) / rho,
+                     "rmse_in_rms": float(np.sqrt(np.mean(d * d))) / rho,
+                     "voxels_over_1e-5_rms": int((np.abs(d) > 1e-5 * rho).sum()),
+                     "speedup_vs_f32_gpu": round(ms_f32 / ms, 4)}
+    return res
+
+
+def storage_floor(cube, ref, rho, n_iter, K, tau):
+    """Error that storing the state in binary32 after every step causes by
+    itself: the FP64 oracle with that rounding against the plain FP64 oracle.
+    Where the exponential conductance falls faster than the difference grows
+    (|difference| above K rho / sqrt 2) the equation amplifies perturbations,
+    so no filter that keeps its state in FP32 gets closer to the FP64 result
+    than this."""
+    import numpy as np
+    import oracle
+    r32, _ = oracle.run(cube, "pm_exp", K=K, tau=tau, n_iter=n_iter, rms=rho, round_to="f32")
+    d = np.abs(r32 - ref)
+    return {"max_abs_in_rms": float(d.max()) / rho, "rmse_in_rms": float(np.sqrt(np.mean(d * d))) / rho,
+            "voxels_over_1e-5_rms": int((d > 1e-5 * rho).sum())}
 
 
 def bench_paper_defaults(x, steps):
@@ -445,9 +483,10 @@ def main():
                    "effective_hbm_frac": round(eff_gbs / HBM_PEAK_GBS, 4)},
         "roofline": roof,
     }
+    outs16 = {}
     if not args.no_extras:
         extras = {}
-        extras["precision_16bit"] = bench_precision(x, max(3, args.steps // 4), out)
+        extras["precision_16bit"] = bench_precision(x, max(3, args.steps // 4), out, keep=outs16)
         extras["paper_defaults_intensity"] = bench_paper_defaults(x, max(3, args.steps // 4))
         extras["batch_96"] = bench_batch(max(3, args.steps // 4))
         extras["quality_512"] = bench_quality(x, out)
@@ -456,7 +495,12 @@ def main():
         extras["wavelet_512"] = bench_wavelet(x)
         res["extras"] = extras
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(cube, N_ITER, K, tau)
+        y32 = out.cpu().numpy()
+        res["cpu_baseline"], ref, rho = cpu_baseline(cube, N_ITER, K, tau)
+        outs16["f32"] = (y32, ms_step)
+        res["errors_vs_fp64_oracle"] = errors_vs_oracle(outs16, ref, rho, ms_step)
+        res["errors_vs_fp64_oracle"]["f32_storage_floor"] = storage_floor(cube, ref, rho, N_ITER, K, tau)
+        del ref
     print(json.dumps(res), flush=True)
 
 
