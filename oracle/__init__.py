@@ -42,7 +42,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 COND = {"intensity": 0, "pm_exp": 1, "pm_rational": 2}
-ROUND = {None: 0, "f32": 0, "bf16": 1, "f16": 2}
+ROUND = {None: 0, "bf16": 1, "f16": 2, "f32": 3}
 
 
 def build(force: bool = True) -> str:

@@ -26,9 +26,9 @@
  * through the cube faces).  Every step reads only I_i (two buffers, the
  * result-plus-temporary memory model of Section 5).
  *
- * Optional storage rounding: round_mode 1 (bfloat16) or 2 (binary16) rounds
- * every voxel to the nearest representable value, ties to even, after each
- * step; the arithmetic of the step itself stays FP64.
+ * Optional storage rounding: round_mode 1 (bfloat16), 2 (binary16) or 3
+ * (binary32) rounds every voxel to the nearest representable value, ties to
+ * even, after each step; the arithmetic of the step itself stays FP64.
  */
 #include <math.h>
 #include <stdint.h>
@@ -49,7 +49,7 @@ int oracle_threads(void)
 }
 
 enum { COND_INTENSITY = 0, COND_PM_EXP = 1, COND_PM_RATIONAL = 2 };
-enum { ROUND_NONE = 0, ROUND_BF16 = 1, ROUND_F16 = 2 };
+enum { ROUND_NONE = 0, ROUND_BF16 = 1, ROUND_F16 = 2, ROUND_F32 = 3 };
 
 /* Round x to the nearest bfloat16 (8 significant bits), ties to even. */
 double oracle_round_bf16(double x)
@@ -83,6 +83,7 @@ static double round_store(double x, int mode)
 {
     if (mode == ROUND_BF16) return oracle_round_bf16(x);
     if (mode == ROUND_F16) return oracle_round_f16(x);
+    if (mode == ROUND_F32) return (double)(float)x; /* IEEE conversion: nearest, ties to even */
     return x;
 }
 
@@ -158,7 +159,7 @@ int oracle_run(const double* in, double* out, int64_t nx, int64_t ny, int64_t nz
                double rms, int round_mode, double* rms_used)
 {
     if (nx < 1 || ny < 1 || nz < 1 || n_iter < 0 || !(K > 0.0) || !(tau >= 0.0)) return -1;
-    if (cond < 0 || cond > 2 || round_mode < 0 || round_mode > 2) return -1;
+    if (cond < 0 || cond > 2 || round_mode < 0 || round_mode > 3) return -1;
     const int64_t n = nx * ny * nz;
     double s1;
     int64_t bad;

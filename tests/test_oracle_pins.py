@@ -285,6 +285,21 @@ def test_rounded_run_stays_on_grid(oracle_lib):
         assert np.abs(out - ref).max() < 0.05
 
 
+def test_f32_storage_is_stepwise_ieee_cast(oracle_lib):
+    """round_to="f32" equals single FP64 steps with numpy's binary32 cast
+    between them (nearest, ties to even)."""
+    c = igsynth.random_cube((9, 10, 11), seed=18).astype(np.float64) * 3
+    for cond in ("pm_exp", "intensity", "pm_rational"):
+        out, rho = oracle_lib.run(c, cond, n_iter=4, C=(2.0, 2.0, 2.0), tau=0.05, round_to="f32")
+        a = c.copy()
+        for _ in range(4):
+            a, _ = oracle_lib.run(a, cond, n_iter=1, C=(2.0, 2.0, 2.0), tau=0.05, rms=rho)
+            a = a.astype(np.float32).astype(np.float64)
+        assert np.array_equal(out, a)
+        ref, _ = oracle_lib.run(c, cond, n_iter=4, C=(2.0, 2.0, 2.0), tau=0.05)
+        assert 0 < np.abs(out - ref).max() < 1e-5 * rho
+
+
 # --- sampled values on large cubes --------------------------------------------
 def test_run_points_matches_full_run(oracle_lib):
     c = igsynth.random_cube((20, 23, 26), seed=17).astype(np.float64)
