@@ -201,12 +201,13 @@ def bench_batch(steps):
         items.append((x, torch.empty_like(x), dict(K=it.K, tau=1 / 16, n_iter=it.n_iter, cond="pm_exp")))
         work += x.numel() * it.n_iter
     T, W, Z, _ = ig.batch_autotune(items)
-    ig.batch(items)
+    prep = ig.batch_prepare(items)
+    ig.batch(prep)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        ig.batch(items)
+        ig.batch(prep)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -216,6 +217,67 @@ def bench_batch(steps):
             "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
             "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
             "policy": "pass-major rounds, longest cubes first", "t_block": T, "waves": W, "zchunk": Z}
+
+
+def bench_batch_tiny(steps, count=512, side=32):
+    """Many small cubes (side^3, 128 KiB each at side 32): LDS-resident (one
+    workgroup per cube runs all steps in LDS) against the same batch streamed
+    through pass rounds (best of t_block 1-3, 8 or 16 waves)."""
+    import numpy as np
+    import torch
+    import igsynth
+    import paper_1609_03782_amd as ig
+    n_iter = 50
+    items = []
+    for k in range(count):
+        x = torch.from_numpy(igsynth.batch_cube(igsynth.BatchItem((side, side, side), 2.0, n_iter, 9000 + k))).cuda()
+        items.append((x, torch.empty_like(x), dict(K=2.0, tau=1 / 16, n_iter=n_iter, cond="pm_exp")))
+    work = count * side ** 3 * n_iter
+
+    prep = ig.batch_prepare(items)   # marshal the item table once
+
+    def timed():
+        ig.batch(prep)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ig.batch(prep)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    res = {"cubes": count, "shape": [side] * 3, "n_iter": n_iter, "voxel_iters": work}
+    try:
+        ig.batch_set_resident(32768)
+        ms_res = timed()
+        lat_res = np.array(ig.batch(prep, want_latency=True)["latency_ms"])
+        ref = [o.clone() for _, o, _ in items]
+        ig.batch_cache_clear()
+        ig.batch_set_resident(0)
+        best = None
+        for T in (1, 2, 3):
+            for W in (8, 16):
+                ig.batch_set_schedule(T, W, 32)
+                ms = timed()
+                ig.batch_cache_clear()
+                if best is None or ms < best[0]:
+                    best = (ms, T, W)
+                    ig.batch_set_schedule(T, W, 32)
+                    lat_str = np.array(ig.batch(prep, want_latency=True)["latency_ms"])
+                    ig.batch_cache_clear()
+        same = all(torch.equal(a, o) for a, (_, o, _) in zip(ref, items))
+    finally:
+        ig.batch_set_resident(32768)
+        ig.batch_set_schedule(0, 16, 32)
+        ig.batch_cache_clear()
+    res.update({"resident_ms": round(ms_res, 4), "resident_Gvoxel_iter_s": round(work / ms_res / 1e6, 2),
+                "streamed_ms": round(best[0], 4), "streamed_Gvoxel_iter_s": round(work / best[0] / 1e6, 2),
+                "streamed_schedule": {"t_block": best[1], "waves": best[2], "zchunk": 32},
+                "speedup": round(best[0] / ms_res, 3), "bitwise_same": same,
+                "latency_ms_p50_resident": round(float(np.percentile(lat_res, 50)), 4),
+                "latency_ms_p50_streamed": round(float(np.percentile(lat_str, 50)), 4)})
+    return res
 
 
 def paper_tuning_grid():
@@ -368,6 +430,18 @@ def bench_surrogate(args):
     e1.record()
     torch.cuda.synchronize()
     ms_infer = e0.elapsed_time(e1)
+    # break-even iteration count: the plain filter costs about a + b n; the
+    # surrogate path one forward pass plus the two-step residual check
+    tmp = torch.empty_like(x)
+    f10 = ig.Filter(cube.shape, **dict(params, n_iter=10))
+    ms10, _ = time_runs(f10, x, tmp, 5, 2)
+    f2 = ig.Filter(cube.shape, **dict(params, n_iter=2))
+    ms2, _ = time_runs(f2, x, tmp, 5, 2)
+    del tmp
+    slope_ms = (ms_plain - ms10) / (params["n_iter"] - 10)
+    icpt_ms = ms10 - 10 * slope_ms
+    ms_sur_path = ms_infer + ms2
+    n_break = (ms_sur_path - icpt_ms) / slope_ms
     rmse_sur = float(torch.sqrt(torch.mean((ysur.double() - plain.double()) ** 2)).item()) / rep["rho"]
     rmse_out = float(torch.sqrt(torch.mean((y.double() - plain.double()) ** 2)).item()) / rep["rho"]
     flops = 335232.0 * cube.size
@@ -385,7 +459,11 @@ def bench_surrogate(args):
            "threshold": args.threshold, "val_rmse_mean_sigma": val_rmse,
            "loss_first": losses[0] if losses else None, "loss_last": float(np.mean(losses[-20:])) if losses else None,
            "s_data": round(t_data, 1), "s_train": round(t_train, 1),
-           "breakeven_note": "plain filter time grows ~linearly with n; surrogate time does not"}
+           "plain_ms_per_iteration": round(slope_ms, 4), "plain_ms_fixed": round(icpt_ms, 4),
+           "ms_surrogate_path": round(ms_sur_path, 3),
+           "breakeven_n": round(n_break, 1),
+           "breakeven_note": "iterations at which the plain filter (fixed + per-iteration cost, fitted from 10 and "
+                             "the configured n) costs as much as one forward pass plus the 2-step residual check"}
     print(json.dumps(res), flush=True)
 
 
@@ -497,6 +575,8 @@ def main():
         extras["precision_16bit"] = bench_precision(x, max(3, args.steps // 4), out, keep=outs16)
         extras["paper_defaults_intensity"] = bench_paper_defaults(x, max(3, args.steps // 4))
         extras["batch_96"] = bench_batch(max(3, args.steps // 4))
+        extras["batch_tiny_512x32cube"] = bench_batch_tiny(max(3, args.steps // 4), 512, 32)
+        extras["batch_tiny_4096x16cube"] = bench_batch_tiny(max(3, args.steps // 4), 4096, 16)
         extras["quality_512"] = bench_quality(x, out)
         extras["sweep_paper_grid_512"] = bench_sweep(x)
         extras["smoothing_512"] = bench_smooth(x)

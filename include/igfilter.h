@@ -191,16 +191,22 @@ typedef struct {
 
 /* Filter `count` independent cubes of uneven sizes and parameters with one
  * graph launch (all items: FP32 storage, same device).  The graph holds the
- * per-cube noise-level scans and one kernel launch per pass round (round r:
- * pass r of every cube that has one); it is built once per batch signature
- * (item shapes, parameters and buffer addresses), with its work descriptors
- * uploaded at that time, and replayed on later calls with the same
- * signature.  Scratch cubes
- * for the ping-pong are owned by that cached plan (ig_batch_cache_clear frees
- * them).  per_item (nullable, `count` entries) receives each item's stats;
- * latency_ms (nullable, `count` entries) receives each cube's completion time
- * measured on the GPU clock from the start of the launch.  Either makes the
- * call wait for the stream. */
+ * per-cube noise-level scans, one launch for the LDS-resident cubes (below)
+ * and one kernel launch per pass round (round r: pass r of every other cube
+ * that has one); it is built once per batch signature (item shapes,
+ * parameters, buffer addresses and the batch settings), with its work
+ * descriptors uploaded at that time, and replayed on later calls with the
+ * same signature.  Scratch cubes for the ping-pong are owned by that cached
+ * plan (ig_batch_cache_clear frees them).  A cube of at most the resident
+ * limit of voxels (ig_batch_set_resident; default 32768, 128 KiB) with
+ * n_iter > 0 runs LDS-resident: one workgroup loads it into LDS, runs all
+ * n_iter steps there and writes the result, bitwise what the passes give;
+ * its stats report passes = 1, schedule.t_block = n_iter and schedule.waves
+ * = the wavefronts of its workgroup (sized to the cube: 1 to 16).  per_item
+ * (nullable, `count` entries) receives each item's stats; latency_ms
+ * (nullable, `count` entries) receives each cube's completion time measured
+ * on the GPU clock from the start of the launch.  Either makes the call wait
+ * for the stream. */
 ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
                           ig_stats* per_item, double* latency_ms);
 
@@ -210,14 +216,24 @@ void ig_batch_cache_clear(void);
 /* Schedule of later ig_filter_batch plans: steps per pass t_block (1..4; 0 =
  * library default), wavefronts per workgroup (1..16, > 2 t_block) and planes
  * per z-chunk of a piece (1..4096; default 32).  All items of a batch must
- * have nx <= 256 and share one conductance. */
+ * share one conductance, and those not run LDS-resident need nx <= 256. */
 ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves, int32_t zchunk);
 
+/* Resident limit of later ig_filter_batch plans: cubes of at most max_voxels
+ * voxels (0..32768; 0 = none) run LDS-resident.  Host only.  Errors:
+ * IG_ERR_INVALID_ARG outside that range. */
+ig_status ig_batch_set_resident(int32_t max_voxels);
+
+/* The current resident limit (IG_ERR_INVALID_ARG for NULL). */
+ig_status ig_batch_get_resident(int32_t* max_voxels);
+
 /* Batch autotuner: runs the batch with t_block 1..4, waves 8, 12 and 16 and
- * z-chunks of 32 and 64 planes, keeps the fastest (sets it as by
- * ig_batch_set_schedule, and keeps only that plan cached) and returns it.
- * Every item must have d_in != d_out (outputs are overwritten; inputs are
- * read only).  Waits for the stream. */
+ * z-chunks of 32 and 64 planes, and, when some cube is small enough, with the
+ * resident limit at 32768 and at 0; keeps the fastest (sets it as by
+ * ig_batch_set_schedule and ig_batch_set_resident, and keeps only that plan
+ * cached) and returns the schedule (the resident limit through
+ * ig_batch_get_resident).  Every item must have d_in != d_out (outputs are
+ * overwritten; inputs are read only).  Waits for the stream. */
 ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
                             int32_t* best_t_block, int32_t* best_waves, int32_t* best_zchunk, double* best_ms);
 

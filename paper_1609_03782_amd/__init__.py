@@ -107,6 +107,8 @@ SIGNATURES = {
                                        ctypes.POINTER(IgStats), ctypes.POINTER(ctypes.c_double)]),
     "ig_batch_cache_clear": (None, []),
     "ig_batch_set_schedule": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ig_batch_set_resident": (ctypes.c_int, [ctypes.c_int32]),
+    "ig_batch_get_resident": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32)]),
     "ig_compare": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_int, _P,
                                   ctypes.POINTER(IgCompareResult)]),
     "ig_reduce": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int, _P,
@@ -345,11 +347,29 @@ class Filter:
         return out
 
 
+class PreparedBatch:
+    """The marshalled item array of a batch, for repeated ig_filter_batch calls
+    on the same tensors without rebuilding it (thousands of items take
+    milliseconds to marshal).  Keeps the tensors alive."""
+
+    def __init__(self, items):
+        self.items = list(items)
+        self.arr = _batch_array(self.items)
+
+    def __len__(self):
+        return len(self.items)
+
+
+def batch_prepare(items):
+    return PreparedBatch(items)
+
+
 def batch(items, device=0, want_stats=False, want_latency=False):
-    """items: list of (x, out, params-dict).  One graph launch (ig_filter_batch)."""
+    """items: list of (x, out, params-dict), or a PreparedBatch of one.  One
+    graph launch (ig_filter_batch)."""
     import torch
     n = len(items)
-    arr = _batch_array(items)
+    arr = items.arr if isinstance(items, PreparedBatch) else _batch_array(items)
     st = (IgStats * n)() if want_stats else None
     if st is not None:
         for k in range(n):
@@ -394,6 +414,17 @@ def batch_cache_clear():
 
 def batch_set_schedule(t_block=0, waves=16, zchunk=32):
     _check(lib().ig_batch_set_schedule(int(t_block), int(waves), int(zchunk)), "ig_batch_set_schedule")
+
+
+def batch_set_resident(max_voxels=32768):
+    """Cubes of at most max_voxels voxels run LDS-resident in later batches (0: none)."""
+    _check(lib().ig_batch_set_resident(int(max_voxels)), "ig_batch_set_resident")
+
+
+def batch_get_resident():
+    v = ctypes.c_int32()
+    _check(lib().ig_batch_get_resident(ctypes.byref(v)), "ig_batch_get_resident")
+    return v.value
 
 
 def compare(x, ref, tol=0.0):

@@ -5,11 +5,15 @@
 // Work items are (cube, pass, piece).  Round r of the graph is one launch of
 // k_batch_round over the pieces of pass r of every cube that has one, largest
 // cubes first; the kernel boundary between rounds orders the passes, so no
-// workgroup ever waits on another.  The graph holds the counter reset (which
-// also stamps the start on the GPU's constant-rate clock), the per-cube FP64
-// noise-level scan, the staging copies and the rounds; the descriptor tables
-// are uploaded once when the plan is built.  The last piece of a cube's last
-// pass stamps the clock, giving each cube's completion latency.
+// workgroup ever waits on another.  Cubes small enough to live in one compute
+// unit's LDS (at most kResidentMax voxels, when enabled) skip the passes: one
+// workgroup of k_batch_resident loads the cube, runs all n steps in LDS and
+// writes the result.  The graph holds the counter reset (which also stamps
+// the start on the GPU's constant-rate clock), the per-cube FP64 noise-level
+// scan, the staging copies, the resident launch and the rounds; the
+// descriptor tables are uploaded once when the plan is built.  The last piece
+// of a cube's last pass (or its resident workgroup) stamps the clock, giving
+// each cube's completion latency.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +40,7 @@ struct BatchCube {
     int piece_off;     // first piece in the shared table
     int npass;         // passes
     int stage;         // 1: input copied to scratch first (in place, odd passes); 2: no passes, copy in -> out
-    int pad;
+    int niter;         // iterations (the resident kernel runs them all)
     long n;
 };
 
@@ -185,6 +189,105 @@ k_batch_round(const BatchCube* __restrict__ cubes, const BatchItem* __restrict__
     }
 }
 
+// LDS-resident cubes.  One workgroup holds the whole cube in LDS; with nth
+// threads (64 to kResThreads, sized to the cube so that small cubes share a
+// compute unit), voxel v = tid + nth k belongs to thread tid.  Each
+// step, every thread evaluates its voxels from LDS into registers with the
+// per-voxel formula of every other schedule (the edge terms and combine()
+// in the same order), the workgroup synchronises, the new values go back to
+// LDS, and it synchronises again.  A neighbour outside the cube is read as
+// the voxel itself, so its difference is +0 and its edge term +0, bitwise
+// what the closed coefficient gives.  HBM is read once and written once.
+constexpr int kResThreads = 1024;
+constexpr int kResPerThread = 32;
+
+template <int COND>
+__global__ void __launch_bounds__(kResThreads)
+k_batch_resident(const BatchCube* __restrict__ cubes, const int* __restrict__ res, const DevParams* __restrict__ prm,
+                 unsigned long long* __restrict__ stamps) {
+    extern __shared__ float lds[];
+    const int c = res[blockIdx.x];
+    const BatchCube& cb = cubes[c];
+    const DevParams P = prm[c];
+    if (P.abort) return;
+    const int nx = cb.g.nx, ny = cb.g.ny, nz = cb.g.nz;
+    const int plane = nx * ny, N = plane * nz;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int v = tid; v < N; v += nth) lds[v] = cb.in[v];
+    // which of the six neighbours of each of this thread's voxels exist: six
+    // bits per voxel, four voxels per register
+    // (coordinates stepped from voxel to voxel: v grows by nth)
+    unsigned fm[kResPerThread / 4];
+#pragma unroll
+    for (int j = 0; j < kResPerThread / 4; ++j) fm[j] = 0u;
+    {
+        const int dx = nth % nx, dy = (nth / nx) % ny, dz = nth / plane;
+        int x = tid % nx, y = (tid / nx) % ny, z = tid / plane;
+#pragma unroll
+        for (int k = 0; k < kResPerThread; ++k) {
+            const unsigned b = (x > 0 ? 1u : 0u) | (x + 1 < nx ? 2u : 0u) | (y > 0 ? 4u : 0u) |
+                               (y + 1 < ny ? 8u : 0u) | (z > 0 ? 16u : 0u) | (z + 1 < nz ? 32u : 0u);
+            fm[k / 4] |= b << (8 * (k % 4));
+            x += dx;
+            if (x >= nx) { x -= nx; ++y; }
+            y += dy;
+            if (y >= ny) { y -= ny; ++z; }
+            z += dz;
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < cb.niter; ++s) {
+        // recompute the neighbour addresses every step rather than keep 6 per
+        // voxel live across the loop (they would not fit in registers)
+        int t0 = tid;
+        asm volatile("" : "+v"(t0));
+        unsigned fs[kResPerThread / 4];
+#pragma unroll
+        for (int j = 0; j < kResPerThread / 4; ++j) {
+            fs[j] = fm[j];
+            asm volatile("" : "+v"(fs[j]));
+        }
+        float nv[kResPerThread];
+#pragma unroll
+        for (int k = 0; k < kResPerThread; ++k) {
+            const int v = t0 + nth * k;
+            if (v < N) {
+                const unsigned m = fs[k / 4] >> (8 * (k % 4));
+                const float I = lds[v];
+                const float xm = lds[(m & 1u) ? v - 1 : v], xp = lds[(m & 2u) ? v + 1 : v];
+                const float ym = lds[(m & 4u) ? v - nx : v], yp = lds[(m & 8u) ? v + nx : v];
+                const float zm = lds[(m & 16u) ? v - plane : v], zp = lds[(m & 32u) ? v + plane : v];
+                const float exm = edge_term<COND>(I - xm, P.coef[0], P.kap);
+                const float exp_ = edge_term<COND>(xp - I, P.coef[0], P.kap);
+                const float eym = edge_term<COND>(I - ym, P.coef[1], P.kap);
+                const float eyp = edge_term<COND>(yp - I, P.coef[1], P.kap);
+                const float ezm = edge_term<COND>(I - zm, P.coef[2], P.kap);
+                const float ezp = edge_term<COND>(zp - I, P.coef[2], P.kap);
+                nv[k] = combine<COND>(I, exm, exp_, eym, eyp, ezm, ezp, P.kap, P.tau);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kResPerThread; ++k) {
+            const int v = t0 + nth * k;
+            if (v < N) lds[v] = nv[k];
+        }
+        __syncthreads();
+    }
+    for (int v = tid; v < N; v += nth) cb.out[v] = lds[v];
+    __syncthreads();
+    if (tid == 0) stamps[1 + c] = wall_clock64();
+}
+
+using ResidentKernel = void (*)(const BatchCube*, const int*, const DevParams*, unsigned long long*);
+static ResidentKernel resident_kernel(int cond) {
+    switch (cond) {
+        case COND_INTENSITY: return k_batch_resident<COND_INTENSITY>;
+        case COND_PM_EXP: return k_batch_resident<COND_PM_EXP>;
+        default: return k_batch_resident<COND_PM_RATIONAL>;
+    }
+}
+
 using BatchKernel = void (*)(const BatchCube*, const BatchItem*, const Piece*, const DevParams*, int*,
                              unsigned long long*);
 
@@ -249,6 +352,12 @@ struct BatchPlan {
     DevBuf<DevParams> d_outsum;
     DevBuf<int> d_ctr;
     DevBuf<unsigned long long> d_stamps;
+    DevBuf<int> d_res;             // cubes run LDS-resident, grouped by workgroup size
+    int nres = 0;
+    std::vector<int> res_off{0};  // class j (64 << j threads): d_res[res_off[j], res_off[j+1])
+    std::vector<size_t> res_lds;  // per class: LDS bytes of its largest cube
+    std::vector<int> resident;    // per cube: wavefronts of its resident workgroup (0: not resident)
+    std::vector<int> niter;
     std::vector<int> round_off;   // items of round r: [round_off[r], round_off[r+1])
     int nitems = 0, nchunks = 0;
     size_t lds = 0;
@@ -264,9 +373,19 @@ struct BatchPlan {
 
 std::mutex g_mu;
 std::map<std::vector<uint64_t>, std::unique_ptr<BatchPlan>> g_cache;
+// The last call's items (validated) and plan: a call with byte-identical items
+// and the same settings reuses it without validating or hashing again.
+struct LastCall {
+    std::vector<ig_batch_item> items;
+    int device = -1, T = 0, W = 0, Z = 0, res = 0;
+    BatchPlan* plan = nullptr;
+};
+LastCall g_last;
 int g_batch_T = 0;    // 0: default choice
 int g_batch_W = 16;
 int g_batch_Z = 32;   // planes per z-chunk of a piece
+constexpr int kResidentMax = kResThreads * kResPerThread;   // 32768 voxels: 128 KiB of LDS
+int g_batch_res = kResidentMax;   // cubes of at most this many voxels run LDS-resident (0: none)
 
 std::vector<uint64_t> signature(const ig_batch_item* items, int count, int device) {
     std::vector<uint64_t> key;
@@ -274,6 +393,7 @@ std::vector<uint64_t> signature(const ig_batch_item* items, int count, int devic
     key.push_back((uint64_t)g_batch_T);
     key.push_back((uint64_t)g_batch_W);
     key.push_back((uint64_t)g_batch_Z);
+    key.push_back((uint64_t)g_batch_res);
     for (int i = 0; i < count; ++i) {
         uint64_t w[(sizeof(ig_params) + 7) / 8] = {};
         std::memcpy(w, &items[i].p, sizeof(ig_params));
@@ -288,17 +408,24 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     bp->device = device;
     bp->count = count;
     bp->cond = items[0].p.cond;
+    // LDS-resident: small cubes with at least one step
+    bp->resident.assign(count, 0);
+    bp->niter.assign(count, 0);
     int maxn = 0;
     long maxnx = 0;
     for (int i = 0; i < count; ++i) {
-        maxn = std::max(maxn, items[i].p.n_iter);
-        maxnx = std::max<long>(maxnx, items[i].p.nx);
+        const ig_params& p = items[i].p;
+        bp->niter[i] = p.n_iter;
+        bp->resident[i] = (g_batch_res > 0 && p.n_iter > 0 && p.nx * p.ny * p.nz <= g_batch_res) ? 1 : 0;
+        if (bp->resident[i]) continue;
+        maxn = std::max(maxn, p.n_iter);
+        maxnx = std::max<long>(maxnx, p.nx);
     }
     bp->W = g_batch_W;
     bp->Z = g_batch_Z;
     bp->T = g_batch_T > 0 ? g_batch_T : std::max(1, std::min(2, maxn));
     const int T = bp->T, W = bp->W;
-    if (maxnx > 256) return fail(IG_ERR_UNSUPPORTED, "batch items need nx <= 256");
+    if (maxnx > 256) return fail(IG_ERR_UNSUPPORTED, "batch items need nx <= 256 (unless LDS-resident)");
     int ncu = 256;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
 
@@ -313,11 +440,43 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     size_t scratch_total = 0;
     std::vector<size_t> scratch_off(count);
     size_t lds = 0;
+    constexpr int kResClasses = 5;   // 64, 128, 256, 512, 1024 threads
+    std::vector<std::vector<int>> res(kResClasses);
+    bp->res_lds.assign(kResClasses, 0);
     for (int c = 0; c < count; ++c) {
         const ig_params& p = items[c].p;
         const long n = (long)(p.nx * p.ny * p.nz);
         nvox[c] = n;
         scratch_off[c] = scratch_total;
+        chunk_first[c] = (int)chunks.size();
+        for (long off = 0; off < n; off += kChunk) chunks.push_back(SumChunk{c, 0, off, std::min(kChunk, n - off)});
+        ParamIn& q = pin[c];
+        q.K = p.K; q.tau = p.tau;
+        for (int a = 0; a < 3; ++a) q.C[a] = p.C[a];
+        q.cond = p.cond;
+        q.abort_on_nonfinite = 1;
+        q.rms = p.rms;
+        BatchCube& cb = cubes[c];
+        cb.in = (const float*)items[c].d_in;
+        cb.out = (float*)items[c].d_out;
+        cb.n = n;
+        cb.niter = p.n_iter;
+        if (bp->resident[c]) {   // no passes, no pieces, no scratch
+            cb.g = BlockGeom{};
+            cb.g.nx = (int)p.nx; cb.g.ny = (int)p.ny; cb.g.nz = (int)p.nz;
+            cb.V = 1;
+            cb.npieces = 0;
+            cb.piece_off = (int)pieces.size();
+            cb.npass = 0;
+            cb.stage = 0;
+            // the fewest threads (64 << j) that hold it at kResPerThread voxels each
+            int j = 0;
+            while (j + 1 < kResClasses && (64L << j) * kResPerThread < n) ++j;
+            res[j].push_back(c);
+            bp->resident[c] = 1 << j;
+            bp->res_lds[j] = std::max(bp->res_lds[j], (size_t)n * sizeof(float));
+            continue;
+        }
         scratch_total += (size_t)((n + 63) / 64 * 64);
         ig_schedule s{};
         s.kind = IG_SCHED_BLOCKED;
@@ -330,15 +489,11 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         if (why) return fail(IG_ERR_INVALID_ARG, "batch item %d: %s", c, why);
         if (pp.V != 4) return fail(IG_ERR_UNSUPPORTED, "batch item %d: layout with %d voxels per lane", c, pp.V);
         lds = std::max(lds, stream_lds_bytes(pp.V, T, W));
-        BatchCube& cb = cubes[c];
-        cb.in = (const float*)items[c].d_in;
-        cb.out = (float*)items[c].d_out;
         cb.g = pp.g;
         if (((uintptr_t)cb.in % (pp.V * 4)) || ((uintptr_t)cb.out % (pp.V * 4))) cb.g.vec = 0;
         cb.V = pp.V;
         cb.npieces = (int)pp.pieces.size();
         cb.piece_off = (int)pieces.size();
-        cb.n = n;
         pieces.insert(pieces.end(), pp.pieces.begin(), pp.pieces.end());
         // pass depths (a remainder pass is shallower); in place with an odd count: stage
         std::vector<int>& d = depths[c];
@@ -349,20 +504,20 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         cb.npass = (int)d.size();
         cb.stage = (items[c].d_in == items[c].d_out && cb.npass % 2 == 1) ? 1
                    : (cb.npass == 0 && items[c].d_in != items[c].d_out) ? 2 : 0;
-        chunk_first[c] = (int)chunks.size();
-        for (long off = 0; off < n; off += kChunk) chunks.push_back(SumChunk{c, 0, off, std::min(kChunk, n - off)});
-        ParamIn& q = pin[c];
-        q.K = p.K; q.tau = p.tau;
-        for (int a = 0; a < 3; ++a) q.C[a] = p.C[a];
-        q.cond = p.cond;
-        q.abort_on_nonfinite = 1;
-        q.rms = p.rms;
     }
     chunk_first[count] = (int)chunks.size();
     if (lds > kMaxLds) return fail(IG_ERR_UNSUPPORTED, "batch tile needs too much LDS");
     bp->lds = lds;
     bp->passes.resize(count);
-    for (int c = 0; c < count; ++c) bp->passes[c] = cubes[c].npass;
+    for (int c = 0; c < count; ++c) bp->passes[c] = bp->resident[c] ? 1 : cubes[c].npass;
+    std::vector<int> res_all;
+    bp->res_off.assign(1, 0);
+    for (int j = 0; j < kResClasses; ++j) {
+        res_all.insert(res_all.end(), res[j].begin(), res[j].end());
+        bp->res_off.push_back((int)res_all.size());
+        if (bp->res_lds[j] > kMaxLds) return fail(IG_ERR_UNSUPPORTED, "resident cube needs too much LDS");
+    }
+    bp->nres = (int)res_all.size();
 
     // rounds: round r holds pass r of every cube that has one, largest cubes first
     std::vector<int> order(count);
@@ -395,6 +550,9 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     HIP_TRY(bp->d_outsum.alloc(count));
     HIP_TRY(bp->d_ctr.alloc(kCtrDone + count));
     HIP_TRY(bp->d_stamps.alloc(1 + count));
+    HIP_TRY(bp->d_res.alloc(res_all.size()));
+    if (!res_all.empty())
+        HIP_TRY(hipMemcpy(bp->d_res.p, res_all.data(), res_all.size() * sizeof(int), hipMemcpyHostToDevice));
     // descriptor tables: fixed for the plan's signature, uploaded once
     HIP_TRY(hipMemcpy(bp->d_cubes.p, cubes.data(), count * sizeof(BatchCube), hipMemcpyHostToDevice));
     if (!its.empty())
@@ -409,8 +567,13 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     BatchKernel kern = batch_kernel(bp->cond, T);
     if (lds > 65536)
         HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ResidentKernel rkern = resident_kernel(bp->cond);
+    const size_t res_lds_max = *std::max_element(bp->res_lds.begin(), bp->res_lds.end());
+    if (res_lds_max > 65536)
+        HIP_TRY(hipFuncSetAttribute((const void*)rkern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)res_lds_max));
 
-    // capture: counter reset, noise-level pre-pass, staging, the rounds
+    // capture: counter reset, noise-level pre-pass, staging, resident cubes, the rounds
     HIP_TRY(hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal));
     hipStream_t s = bp->cap;
@@ -432,6 +595,13 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
                            bp->d_params.p);
         chk(hipGetLastError());
     }
+    for (size_t j = 0; j + 1 < bp->res_off.size(); ++j) {
+        const int n = bp->res_off[j + 1] - bp->res_off[j];
+        if (n <= 0) continue;
+        hipLaunchKernelGGL(rkern, dim3(n), dim3(64 << j), bp->res_lds[j], s, bp->d_cubes.p,
+                           bp->d_res.p + bp->res_off[j], bp->d_params.p, bp->d_stamps.p);
+        chk(hipGetLastError());
+    }
     for (size_t r = 0; r + 1 < bp->round_off.size(); ++r) {
         const int n = bp->round_off[r + 1] - bp->round_off[r];
         if (n <= 0) continue;
@@ -450,9 +620,23 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
 
 }  // namespace
 
+static bool same_as_last(const ig_batch_item* items, int count, int device) {
+    return g_last.plan && g_last.device == device && (int)g_last.items.size() == count && g_last.T == g_batch_T &&
+           g_last.W == g_batch_W && g_last.Z == g_batch_Z && g_last.res == g_batch_res &&
+           std::memcmp(g_last.items.data(), items, (size_t)count * sizeof(ig_batch_item)) == 0;
+}
+
 extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
                                      ig_stats* per_item, double* latency_ms) {
     if (!items || count < 1) return fail(IG_ERR_INVALID_ARG, "empty batch");
+    if (per_item)
+        for (int i = 0; i < count; ++i)
+            if (per_item[i].struct_size != sizeof(ig_stats))
+                return fail(IG_ERR_INVALID_ARG, "per_item[%d].struct_size", i);
+    // held for the whole call: a plan stays alive while it is used
+    std::lock_guard<std::mutex> lk(g_mu);
+    BatchPlan* bp = same_as_last(items, count, device) ? g_last.plan : nullptr;
+    if (!bp) {
     for (int i = 0; i < count; ++i) {
         ig_status st = igk_validate_params(&items[i].p);
         if (st != IG_OK) return st;
@@ -460,8 +644,6 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
         if (items[i].p.cond != items[0].p.cond)
             return fail(IG_ERR_UNSUPPORTED, "batch items must share one conductance");
         if (!items[i].d_in || !items[i].d_out) return fail(IG_ERR_INVALID_ARG, "batch item %d: NULL buffer", i);
-        if (per_item && per_item[i].struct_size != sizeof(ig_stats))
-            return fail(IG_ERR_INVALID_ARG, "per_item[%d].struct_size", i);
     }
     // buffers of distinct items must not overlap
     {
@@ -481,23 +663,28 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(IG_ERR_INVALID_ARG, "bad device %d", device);
+    }
     int prev = -1;
     (void)hipGetDevice(&prev);
     if (hipSetDevice(device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice(%d)", device);
     struct Restore { int d; ~Restore() { if (d >= 0) (void)hipSetDevice(d); } } restore{prev};
 
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto key = signature(items, count, device);
-    auto it = g_cache.find(key);
-    BatchPlan* bp;
-    if (it == g_cache.end()) {
-        auto plan = std::make_unique<BatchPlan>();
-        ig_status st = build_plan(items, count, device, plan.get());
-        if (st != IG_OK) return st;
-        bp = plan.get();
-        g_cache[key] = std::move(plan);
-    } else {
-        bp = it->second.get();
+    if (!bp) {
+        auto key = signature(items, count, device);
+        auto it = g_cache.find(key);
+        if (it == g_cache.end()) {
+            auto plan = std::make_unique<BatchPlan>();
+            ig_status st = build_plan(items, count, device, plan.get());
+            if (st != IG_OK) return st;
+            bp = plan.get();
+            g_cache[key] = std::move(plan);
+        } else {
+            bp = it->second.get();
+        }
+        g_last.items.assign(items, items + count);
+        g_last.device = device;
+        g_last.T = g_batch_T; g_last.W = g_batch_W; g_last.Z = g_batch_Z; g_last.res = g_batch_res;
+        g_last.plan = bp;
     }
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_TRY(hipGraphLaunch(bp->exec, s));
@@ -533,7 +720,8 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
             st.sum_out = osum[c].sum;
             st.nonfinite = prm[c].nonfinite;
             st.monotone = (2.0 * (double)p.tau * ((double)p.C[0] + p.C[1] + p.C[2]) <= 1.0) ? 1 : 0;
-            st.schedule = ig_schedule{IG_SCHED_BLOCKED, bp->T, bp->W, bp->Z, 4, 0, 0};
+            st.schedule = bp->resident[c] ? ig_schedule{IG_SCHED_BLOCKED, bp->niter[c], bp->resident[c], (int)p.nz, 1, 0, 0}
+                                          : ig_schedule{IG_SCHED_BLOCKED, bp->T, bp->W, bp->Z, 4, 0, 0};
         }
         if (prm[c].abort) bad = true;
     }
@@ -543,6 +731,7 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
 
 extern "C" void ig_batch_cache_clear(void) {
     std::lock_guard<std::mutex> lk(g_mu);
+    g_last = LastCall{};
     g_cache.clear();
 }
 
@@ -560,41 +749,53 @@ extern "C" ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count
     for (int i = 0; i < count; ++i) maxn = std::max(maxn, items[i].p.n_iter);
     // drop the plan of a candidate that is not kept (each plan holds scratch
     // cubes for the whole batch)
-    auto drop = [&](int T, int W, int Z) {
+    // small cubes: LDS-resident or streamed like the others (both are tried
+    // when some cube qualifies)
+    bool any_small = false;
+    for (int i = 0; i < count; ++i)
+        any_small |= items[i].p.n_iter > 0 && items[i].p.nx * items[i].p.ny * items[i].p.nz <= kResidentMax;
+    std::vector<int> res_modes = any_small ? std::vector<int>{kResidentMax, 0} : std::vector<int>{g_batch_res};
+    auto drop = [&](int T, int W, int Z, int R) {
         std::lock_guard<std::mutex> lk(g_mu);
-        const int t0 = g_batch_T, w0 = g_batch_W, z0 = g_batch_Z;
-        g_batch_T = T; g_batch_W = W; g_batch_Z = Z;
-        g_cache.erase(signature(items, count, device));
-        g_batch_T = t0; g_batch_W = w0; g_batch_Z = z0;
+        const int t0 = g_batch_T, w0 = g_batch_W, z0 = g_batch_Z, r0 = g_batch_res;
+        g_batch_T = T; g_batch_W = W; g_batch_Z = Z; g_batch_res = R;
+        auto it = g_cache.find(signature(items, count, device));
+        if (it != g_cache.end()) {
+            if (g_last.plan == it->second.get()) g_last = LastCall{};
+            g_cache.erase(it);
+        }
+        g_batch_T = t0; g_batch_W = w0; g_batch_Z = z0; g_batch_res = r0;
     };
     double best = 1e300;
-    int bT = 0, bW = 16, bZ = 32;
-    for (int T = 1; T <= std::max(1, std::min(4, maxn)); ++T)
-        for (int W : {8, 12, 16})
-            for (int Z : {32, 64}) {
-                if (W <= 2 * T) continue;
-                if (ig_batch_set_schedule(T, W, Z) != IG_OK) continue;
-                if (ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) != IG_OK) {   // build + warm
-                    drop(T, W, Z);
-                    continue;
+    int bT = 0, bW = 16, bZ = 32, bR = g_batch_res;
+    for (int R : res_modes)
+        for (int T = 1; T <= std::max(1, std::min(4, maxn)); ++T)
+            for (int W : {8, 12, 16})
+                for (int Z : {32, 64}) {
+                    if (W <= 2 * T) continue;
+                    if (ig_batch_set_schedule(T, W, Z) != IG_OK || ig_batch_set_resident(R) != IG_OK) continue;
+                    if (ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) != IG_OK) {   // build + warm
+                        drop(T, W, Z, R);
+                        continue;
+                    }
+                    float ms = 0.0f;
+                    bool ok = hipEventRecord(e0, s) == hipSuccess;
+                    for (int k = 0; k < 2 && ok; ++k)
+                        ok = ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) == IG_OK;
+                    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                    if (ok && ms / 2 < best) {
+                        if (best < 1e300) drop(bT, bW, bZ, bR);
+                        best = ms / 2; bT = T; bW = W; bZ = Z; bR = R;
+                    } else {
+                        drop(T, W, Z, R);
+                    }
                 }
-                float ms = 0.0f;
-                bool ok = hipEventRecord(e0, s) == hipSuccess;
-                for (int k = 0; k < 2 && ok; ++k)
-                    ok = ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) == IG_OK;
-                ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-                     hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-                if (ok && ms / 2 < best) {
-                    if (best < 1e300) drop(bT, bW, bZ);
-                    best = ms / 2; bT = T; bW = W; bZ = Z;
-                } else {
-                    drop(T, W, Z);
-                }
-            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (best >= 1e300) return fail(IG_ERR_UNSUPPORTED, "no batch schedule ran");
     ig_status st = ig_batch_set_schedule(bT, bW, bZ);
+    if (st == IG_OK) st = ig_batch_set_resident(bR);
     if (st != IG_OK) return st;
     if (best_t_block) *best_t_block = bT;
     if (best_waves) *best_waves = bW;
@@ -610,5 +811,20 @@ extern "C" ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves, int32
     g_batch_T = t_block;
     g_batch_W = waves;
     g_batch_Z = zchunk;
+    return IG_OK;
+}
+
+extern "C" ig_status ig_batch_set_resident(int32_t max_voxels) {
+    if (max_voxels < 0 || max_voxels > kResidentMax)
+        return fail(IG_ERR_INVALID_ARG, "resident limit must be in 0..%d voxels", kResidentMax);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_batch_res = max_voxels;
+    return IG_OK;
+}
+
+extern "C" ig_status ig_batch_get_resident(int32_t* max_voxels) {
+    if (!max_voxels) return fail(IG_ERR_INVALID_ARG, "max_voxels is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    *max_voxels = g_batch_res;
     return IG_OK;
 }

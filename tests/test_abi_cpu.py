@@ -194,3 +194,23 @@ def test_wavelet_rejects_invalid(kw, shape):
     assert rc in (ig.IG_ERR_INVALID_ARG, ig.IG_ERR_UNSUPPORTED), (kw, shape)
     if shape[2] > 10240 or shape[0] > 2560:
         assert rc == ig.IG_ERR_UNSUPPORTED
+
+
+def test_batch_resident_limit_validation():
+    """ig_batch_set_resident takes 0..32768 voxels and rejects the rest;
+    ig_batch_get_resident reads it back (host only, no GPU)."""
+    import ctypes
+    import paper_1609_03782_amd as ig
+    L = ig.lib()
+    v = ctypes.c_int32()
+    assert L.ig_batch_get_resident(ctypes.byref(v)) == ig.IG_OK
+    old = v.value
+    try:
+        for bad in (-1, 32769, 1 << 30):
+            assert L.ig_batch_set_resident(bad) == ig.IG_ERR_INVALID_ARG
+        for good in (0, 1, 32768):
+            assert L.ig_batch_set_resident(good) == ig.IG_OK
+            assert L.ig_batch_get_resident(ctypes.byref(v)) == ig.IG_OK and v.value == good
+        assert L.ig_batch_get_resident(None) == ig.IG_ERR_INVALID_ARG
+    finally:
+        L.ig_batch_set_resident(old)

@@ -105,3 +105,132 @@ def test_batch_nonfinite_item(dev):
     torch.cuda.synchronize()
     assert torch.equal(ref, oa)
     ig.batch_cache_clear()
+
+
+# --- LDS-resident cubes -------------------------------------------------------
+RES_SHAPES = [(32, 32, 32), (33, 32, 32), (1, 1, 40), (40, 1, 1), (1, 1, 1), (3, 1, 200), (17, 23, 29),
+              (8, 128, 32), (2, 2, 256)]
+
+
+@pytest.mark.parametrize("cond", ["pm_exp", "pm_rational", "intensity"])
+def test_resident_bitwise_equal_to_streamed(dev, oracle_lib, cond):
+    """A batch of small cubes gives the same bits with the LDS-resident path
+    as with the streamed passes; the oracle agrees; stats say which ran."""
+    import torch
+    import paper_1609_03782_amd as ig
+    rng = np.random.default_rng(7)
+    cubes, items = [], []
+    for k, shape in enumerate(RES_SHAPES):
+        c = igsynth.random_cube(shape, seed=300 + k, scale=1.5)
+        c.flat[rng.integers(c.size)] = 8.0
+        n_iter = int(rng.integers(1, 13))
+        K = float(rng.uniform(1.5, 3.0))
+        x = torch.from_numpy(c).to(dev)
+        kw = dict(K=K, tau=1 / 16 if cond != "intensity" else 0.0325, n_iter=n_iter,
+                  C=(1.0, 1.0, 1.0) if cond != "intensity" else (5.0, 5.0, 5.0), cond=cond)
+        cubes.append((c, kw))
+        items.append((x, torch.empty_like(x), kw))
+    outs = {}
+    try:
+        for lim in (32768, 0):
+            ig.batch_set_resident(lim)
+            assert ig.batch_get_resident() == lim
+            res = ig.batch(items, want_stats=True, want_latency=True)
+            torch.cuda.synchronize()
+            outs[lim] = [o.clone() for _, o, _ in items]
+            for (c, kw), st, lat in zip(cubes, res["stats"], res["latency_ms"]):
+                resident = lim > 0 and c.size <= lim
+                if resident:
+                    assert st.passes == 1 and st.schedule["t_block"] == kw["n_iter"]
+                    waves = 1
+                    while waves < 16 and 64 * waves * 32 < c.size:
+                        waves *= 2
+                    assert st.schedule["waves"] == waves, (c.shape, st.schedule)
+                assert lat > 0.0
+    finally:
+        ig.batch_set_resident(32768)
+        ig.batch_cache_clear()
+    for (c, kw), a, b in zip(cubes, outs[32768], outs[0]):
+        assert torch.equal(a, b), (c.shape, kw["n_iter"])
+        ref, rho = oracle_lib.run(c, cond, K=kw["K"], tau=kw["tau"], n_iter=kw["n_iter"], C=kw["C"])
+        err = float(np.abs(a.cpu().numpy().astype(np.float64) - ref).max())
+        assert err <= TOL * rho, (c.shape, err / rho)
+
+
+def test_resident_in_place_and_mixed_batch(dev):
+    """In-place resident cubes next to streamed ones of the same batch, against
+    single-cube runs (bitwise); a zero-iteration small cube is copied."""
+    import torch
+    import paper_1609_03782_amd as ig
+    shapes = [(16, 16, 16), (24, 70, 90), (30, 30, 30), (10, 10, 10)]
+    cubes, items = [], []
+    for k, shape in enumerate(shapes):
+        c = igsynth.random_cube(shape, seed=400 + k, scale=1.5)
+        x = torch.from_numpy(c).to(dev)
+        n_iter = 0 if k == 3 else 9
+        out = x if k == 0 else torch.empty_like(x)
+        kw = dict(K=2.0, tau=1 / 16, n_iter=n_iter)
+        cubes.append((c, kw))
+        items.append((x, out, kw))
+    res = ig.batch(items, want_stats=True)
+    torch.cuda.synchronize()
+    for (c, kw), (x, out, _), st in zip(cubes, items, res["stats"]):
+        single = ig.Filter(c.shape, **kw)
+        ys = single.run(torch.from_numpy(c).to(dev))
+        torch.cuda.synchronize()
+        assert torch.equal(ys, out), c.shape
+        assert st.sum_out == pytest.approx(float(ys.double().sum()), rel=1e-9, abs=1e-6)
+    assert res["stats"][0].passes == 1 and res["stats"][2].passes == 1
+    assert res["stats"][1].passes > 1 and res["stats"][3].passes == 0
+    ig.batch_cache_clear()
+
+
+def test_resident_graph_replay_bitwise(dev):
+    import torch
+    import paper_1609_03782_amd as ig
+    items = []
+    for k in range(6):
+        c = igsynth.random_cube((20 + k, 21, 22), seed=500 + k, scale=1.5)
+        x = torch.from_numpy(c).to(dev)
+        items.append((x, torch.empty_like(x), dict(K=2.0, tau=1 / 16, n_iter=15 + k)))
+    ig.batch(items)
+    torch.cuda.synchronize()
+    first = [o.clone() for _, o, _ in items]
+    for rep in range(3):
+        for _, o, _ in items:
+            o.fill_(-1.0)
+        torch.cuda.synchronize()
+        ig.batch(items)
+        torch.cuda.synchronize()
+        for a, (_, o, _) in zip(first, items):
+            assert torch.equal(a, o), rep
+    ig.batch_cache_clear()
+
+
+def test_batch_changed_parameters_or_settings_rebuild(dev):
+    """Repeated calls with identical items reuse the last plan; a changed
+    parameter or batch setting on the same tensors must not (each result is
+    checked against single-cube runs)."""
+    import torch
+    import paper_1609_03782_amd as ig
+    shapes = [(12, 13, 14), (40, 50, 60)]
+    xs = [torch.from_numpy(igsynth.random_cube(s, seed=600 + k, scale=1.5)).to(dev) for k, s in enumerate(shapes)]
+    outs = [torch.empty_like(x) for x in xs]
+    try:
+        for n_iter, K, res_lim, T in [(5, 2.0, 32768, 0), (5, 2.0, 32768, 0), (6, 2.0, 32768, 0),
+                                      (6, 2.5, 32768, 0), (6, 2.5, 0, 0), (6, 2.5, 0, 3)]:
+            ig.batch_set_resident(res_lim)
+            ig.batch_set_schedule(T, 16, 32)
+            kw = dict(K=K, tau=1 / 16, n_iter=n_iter)
+            prep = ig.batch_prepare([(x, o, kw) for x, o in zip(xs, outs)])
+            ig.batch(prep)
+            ig.batch(prep)
+            torch.cuda.synchronize()
+            for x, o in zip(xs, outs):
+                ref = ig.Filter(tuple(x.shape), **kw).run(x)
+                torch.cuda.synchronize()
+                assert torch.equal(ref, o), (tuple(x.shape), n_iter, K, res_lim, T)
+    finally:
+        ig.batch_set_resident(32768)
+        ig.batch_set_schedule(0, 16, 32)
+        ig.batch_cache_clear()
