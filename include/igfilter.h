@@ -19,7 +19,12 @@
  *     paper), index x + nx * (y + ny * z), densely packed.
  *   - Pointers named d_* are device pointers on the handle's device (e.g.
  *     torch tensors' data_ptr()).  The caller owns them; the library never
- *     frees them.  Handles own their scratch memory.
+ *     frees them.  Handles own their scratch memory.  Before any work is
+ *     enqueued, each such buffer is checked with the runtime: host memory
+ *     (pinned or not), memory of another device, or an allocation that ends
+ *     before the bytes the call uses gives IG_ERR_INVALID_ARG.  (The size
+ *     check sees whole runtime allocations: a tensor carved out of a larger
+ *     allocation by a caching allocator is checked against that allocation.)
  *   - hip_stream is a hipStream_t cast to void*; NULL means the null stream.
  *     Work is enqueued on that stream and the call returns without waiting,
  *     unless an output argument that lives on the host (stats, latency) is

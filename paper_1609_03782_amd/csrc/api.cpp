@@ -540,6 +540,35 @@ static ig_status enqueue_run(ig_filter* f, const ig_schedule& sched, const void*
     return IG_OK;
 }
 
+ig_status igk_check_buffer(const void* p, size_t bytes, int device, const char* what) {
+    if (!p) return fail(IG_ERR_INVALID_ARG, "%s is NULL", what);
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();   // not a sticky error: clear it for the caller's next check
+        return fail(IG_ERR_INVALID_ARG, "%s (%p) is not memory the GPU runtime knows", what, p);
+    }
+    const bool dev_mem = a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.isManaged;
+    if (!dev_mem) return fail(IG_ERR_INVALID_ARG, "%s (%p) is not device memory", what, p);
+    if (a.type == hipMemoryTypeDevice && a.device != device)
+        return fail(IG_ERR_INVALID_ARG, "%s lives on device %d, the call uses device %d", what, a.device, device);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) == hipSuccess && base) {
+        const uintptr_t b = (uintptr_t)base, q = (uintptr_t)p;
+        if (q < b || q - b > size || bytes > size - (q - b))
+            return fail(IG_ERR_INVALID_ARG, "%s: %zu bytes from %p run past the end of its allocation", what, bytes, p);
+    } else {
+        (void)hipGetLastError();
+    }
+    return IG_OK;
+}
+
+int igk_current_device() {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) d = 0;
+    return d;
+}
+
 static bool ranges_overlap(const void* a, const void* b, size_t bytes) {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
     return x < y + bytes && y < x + bytes;
@@ -559,6 +588,9 @@ extern "C" ig_status ig_filter_run(ig_filter* f, const void* d_in, void* d_out, 
         return fail(IG_ERR_INVALID_ARG, "buffer overlaps the handle's scratch");
     if (((uintptr_t)d_in % dtype_size(p.dtype)) || ((uintptr_t)d_out % dtype_size(p.dtype)))
         return fail(IG_ERR_INVALID_ARG, "buffers must be aligned to the element size");
+    ig_status cb = igk_check_buffer(d_in, bytes, f->device, "d_in");
+    if (cb == IG_OK) cb = igk_check_buffer(d_out, bytes, f->device, "d_out");
+    if (cb != IG_OK) return cb;
     DeviceGuard dg(f->device);
     if (!dg.ok) return fail(IG_ERR_DEVICE, "hipSetDevice(%d) failed", f->device);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -663,6 +695,12 @@ extern "C" ig_status ig_filter_autotune(ig_filter* f, const void* d_in, void* d_
                                         ig_schedule* best, double* best_ms) {
     if (!f || !d_in || !d_work || !best) return fail(IG_ERR_INVALID_ARG, "NULL argument");
     if (d_in == d_work) return fail(IG_ERR_INVALID_ARG, "d_work must differ from d_in");
+    {
+        const size_t bytes = (size_t)(f->p.nx * f->p.ny * f->p.nz) * dtype_size(f->p.dtype);
+        ig_status cb = igk_check_buffer(d_in, bytes, f->device, "d_in");
+        if (cb == IG_OK) cb = igk_check_buffer(d_work, bytes, f->device, "d_work");
+        if (cb != IG_OK) return cb;
+    }
     DeviceGuard dg(f->device);
     if (!dg.ok) return fail(IG_ERR_DEVICE, "hipSetDevice(%d) failed", f->device);
     hipDeviceProp_t prop;
@@ -738,6 +776,11 @@ extern "C" ig_status ig_compare(const void* d_x, int32_t x_dtype, const double* 
                                 int device, void* hip_stream, ig_compare_result* res) {
     if (!d_x || !d_ref || !res || n < 0) return fail(IG_ERR_INVALID_ARG, "bad argument");
     if (x_dtype < 0 || x_dtype > 2) return fail(IG_ERR_INVALID_ARG, "bad dtype");
+    {
+        ig_status cb = igk_check_buffer(d_x, (size_t)n * dtype_size(x_dtype), device, "d_x");
+        if (cb == IG_OK) cb = igk_check_buffer(d_ref, (size_t)n * sizeof(double), device, "d_ref");
+        if (cb != IG_OK) return cb;
+    }
     DeviceGuard dg(device);
     if (!dg.ok) return fail(IG_ERR_DEVICE, "hipSetDevice(%d) failed", device);
     ig_status st = util_scratch(device);
@@ -760,6 +803,10 @@ extern "C" ig_status ig_reduce(const void* d_x, int32_t x_dtype, int64_t n, int 
                                double* sum, double* sumsq, int64_t* nonfinite) {
     if (!d_x || n < 0) return fail(IG_ERR_INVALID_ARG, "bad argument");
     if (x_dtype < 0 || x_dtype > 2) return fail(IG_ERR_INVALID_ARG, "bad dtype");
+    {
+        ig_status cb = igk_check_buffer(d_x, (size_t)n * dtype_size(x_dtype), device, "d_x");
+        if (cb != IG_OK) return cb;
+    }
     DeviceGuard dg(device);
     if (!dg.ok) return fail(IG_ERR_DEVICE, "hipSetDevice(%d) failed", device);
     ig_status st = util_scratch(device);

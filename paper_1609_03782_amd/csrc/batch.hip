@@ -22,6 +22,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -644,6 +645,10 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
         if (items[i].p.cond != items[0].p.cond)
             return fail(IG_ERR_UNSUPPORTED, "batch items must share one conductance");
         if (!items[i].d_in || !items[i].d_out) return fail(IG_ERR_INVALID_ARG, "batch item %d: NULL buffer", i);
+        const size_t bytes = (size_t)(items[i].p.nx * items[i].p.ny * items[i].p.nz) * 4;
+        ig_status cb = igk_check_buffer(items[i].d_in, bytes, device, "batch item d_in");
+        if (cb == IG_OK) cb = igk_check_buffer(items[i].d_out, bytes, device, "batch item d_out");
+        if (cb != IG_OK) return fail(cb, "batch item %d: %s", i, std::string(ig_last_error()).c_str());
     }
     // buffers of distinct items must not overlap
     {

@@ -63,5 +63,11 @@ int resident_per_cu(int W, size_t lds);
 // nullptr on success, else the reason schedule s cannot serve p at depth T
 const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp);
 ig_status igk_validate_params(const ig_params* p);
+// A buffer a kernel will touch: device (or managed) memory of `device` whose
+// allocation covers [p, p + bytes).  A host pointer or a short allocation is
+// reported as IG_ERR_INVALID_ARG (naming `what`) instead of faulting on the GPU.
+ig_status igk_check_buffer(const void* p, size_t bytes, int device, const char* what);
+// The calling thread's current device (0 if it cannot be read).
+int igk_current_device();
 ig_status igk_fail(ig_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 size_t dtype_size(int dt);

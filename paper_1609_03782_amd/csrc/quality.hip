@@ -286,6 +286,13 @@ extern "C" ig_status ig_quality(const ig_quality_params* q, const float* d_orig,
         r[4] >= r[5])
         return fail(IG_ERR_INVALID_ARG, "ROI empty or outside the cube");
     if (device < 0 || device >= 64) return fail(IG_ERR_INVALID_ARG, "bad device %d", device);
+    {
+        const size_t bytes = (size_t)(nx * ny * nz) * 4;
+        ig_status cb = igk_check_buffer(d_orig, bytes, device, "d_orig");
+        if (cb == IG_OK) cb = igk_check_buffer(d_filt, bytes, device, "d_filt");
+        if (cb == IG_OK && d_model) cb = igk_check_buffer(d_model, bytes, device, "d_model");
+        if (cb != IG_OK) return cb;
+    }
     int prev = -1;
     (void)hipGetDevice(&prev);
     if (hipSetDevice(device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice(%d)", device);

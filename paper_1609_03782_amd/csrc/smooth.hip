@@ -324,6 +324,13 @@ extern "C" ig_status ig_smooth(const ig_smooth_params* s, const float* d_in, flo
         return fail(IG_ERR_INVALID_ARG, "bad cube size");
     const size_t bytes = (size_t)(nx * ny * nz) * sizeof(float);
     if (overlaps(d_in, d_out, bytes)) return fail(IG_ERR_INVALID_ARG, "d_in and d_out overlap");
+    {
+        const int dev = igk_current_device();
+        ig_status cb = igk_check_buffer(d_in, bytes, dev, "d_in");
+        if (cb == IG_OK) cb = igk_check_buffer(d_out, bytes, dev, "d_out");
+        if (cb == IG_OK && p.separable && d_work) cb = igk_check_buffer(d_work, bytes, dev, "d_work");
+        if (cb != IG_OK) return cb;
+    }
     hipStream_t st_ = (hipStream_t)hip_stream;
     if (p.separable) {
         if (!d_work) return fail(IG_ERR_INVALID_ARG, "the separable path needs d_work");

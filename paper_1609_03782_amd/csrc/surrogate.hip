@@ -322,6 +322,11 @@ extern "C" ig_status ig_surrogate_train_step(ig_surrogate* s, const float* const
     if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
     hipStream_t st = (hipStream_t)hip_stream;
     const long n = nx * ny * nz;
+    for (int k = 0; k < batch; ++k) {
+        ig_status cb = igk_check_buffer(d_x[k], (size_t)n * 4, s->device, "d_x[k]");
+        if (cb == IG_OK) cb = igk_check_buffer(d_t[k], (size_t)n * 4, s->device, "d_t[k]");
+        if (cb != IG_OK) return cb;
+    }
     ig_status rc = ensure_acts(s, n);
     if (rc != IG_OK) return rc;
     {   // weight-gradient partials for the largest layer, sized before any launch
@@ -396,6 +401,11 @@ extern "C" ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float
     if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
     hipStream_t st = (hipStream_t)hip_stream;
     const long n = nx * ny * nz;
+    {
+        ig_status cb = igk_check_buffer(d_x, (size_t)n * 4, s->device, "d_x");
+        if (cb == IG_OK) cb = igk_check_buffer(d_y, (size_t)n * 4, s->device, "d_y");
+        if (cb != IG_OK) return cb;
+    }
     const int H = s->L;   // receptive radius
     // activations are addressed with 32-bit offsets: voxels x 32 channels < 2^31
     auto fits = [&](long t) {

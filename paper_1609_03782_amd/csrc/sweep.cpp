@@ -47,6 +47,10 @@ extern "C" ig_status ig_filter_sweep(const ig_params* base, const ig_sweep_point
     if (q->struct_size != (int32_t)sizeof(ig_quality_params)) return fail(IG_ERR_INVALID_ARG, "q.struct_size");
     *best = -1;
     const long n = (long)(base->nx * base->ny * base->nz);
+    st = igk_check_buffer(d_in, (size_t)n * 4, device, "d_in");
+    if (st == IG_OK && d_model) st = igk_check_buffer(d_model, (size_t)n * 4, device, "d_model");
+    if (st == IG_OK && d_best) st = igk_check_buffer(d_best, (size_t)n * 4, device, "d_best");
+    if (st != IG_OK) return st;
     double rho = base->rms;
     if (!(rho > 0.0)) {
         double sum = 0.0, sumsq = 0.0;

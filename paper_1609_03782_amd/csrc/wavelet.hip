@@ -178,7 +178,10 @@ ig_status check(const ig_wavelet_params* p, const void* a, const void* b, int64_
     const size_t bytes = (size_t)(nx * ny * nz) * sizeof(float);
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
     if (x != y && x < y + bytes && y < x + bytes) return fail(IG_ERR_INVALID_ARG, "buffers overlap partially");
-    return IG_OK;
+    const int dev = igk_current_device();
+    ig_status cb = igk_check_buffer(a, bytes, dev, "input cube");
+    if (cb == IG_OK) cb = igk_check_buffer(b, bytes, dev, "output cube");
+    return cb;
 }
 
 // Lines per workgroup along y or z: the widest whose LDS tile stays within
