@@ -134,6 +134,15 @@ def bench_precision(cube_t, steps, ref_out, keep=None):
     return res
 
 
+def decade_histogram(d_over_rho):
+    """Voxel counts of |error| / rho per decade, 1e-9 to 1e-3 and beyond."""
+    import numpy as np
+    edges = [0.0] + [10.0 ** e for e in range(-9, -2)] + [np.inf]
+    counts, _ = np.histogram(d_over_rho, bins=edges)
+    names = ["<1e-9"] + [f"1e{e}..1e{e + 1}" for e in range(-9, -3)] + [">=1e-3"]
+    return {k: int(v) for k, v in zip(names, counts)}
+
+
 def errors_vs_oracle(outs, ref, rho, ms_f32):
     """Max-abs and RMS error of each GPU output against the FP64 oracle's
     output for the whole cube, in units of rho, with each 16-bit form's
@@ -143,6 +152,7 @@ def errors_vs_oracle(outs, ref, rho, ms_f32):
     for name, (y, ms) in outs.items():
         d = y.astype(np.float64) - ref
         res[name] = {"max_abs_in_rms": float(np.abs(d).max()) / rho,
+                     "histogram_in_rms": decade_histogram(np.abs(d) / rho) if name == "f32" else None,
                      "rmse_in_rms": float(np.sqrt(np.mean(d * d))) / rho,
                      "voxels_over_1e-5_rms": int((np.abs(d) > 1e-5 * rho).sum()),
                      "speedup_vs_f32_gpu": round(ms_f32 / ms, 4)}
@@ -161,7 +171,7 @@ def storage_floor(cube, ref, rho, n_iter, K, tau):
     r32, _ = oracle.run(cube, "pm_exp", K=K, tau=tau, n_iter=n_iter, rms=rho, round_to="f32")
     d = np.abs(r32 - ref)
     return {"max_abs_in_rms": float(d.max()) / rho, "rmse_in_rms": float(np.sqrt(np.mean(d * d))) / rho,
-            "voxels_over_1e-5_rms": int((d > 1e-5 * rho).sum())}
+            "voxels_over_1e-5_rms": int((d > 1e-5 * rho).sum()), "histogram_in_rms": decade_histogram(d / rho)}
 
 
 def bench_paper_defaults(x, steps):

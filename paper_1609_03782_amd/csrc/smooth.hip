@@ -53,14 +53,24 @@ k_sep_x(const float* __restrict__ src, float* __restrict__ dst, SepGeom g) {
     const long nrows = g.ny * g.nz;
     const long row0 = (long)blockIdx.y * kSepRowsX;
     sep_weights(g, w);
-    for (int k = 0; k < kSepRowsX; ++k) {
-        const long rw = row0 + k;
-        if (rw >= nrows) break;
-        for (int i = threadIdx.x; i < kSepRow + 2 * r; i += kSepRow) {
-            const long x = x0 - r + i;
-            row[k][i] = (x >= 0 && x < g.nx) ? src[rw * g.nx + x] : 0.0f;
+    // all loads of the tile first (each thread: up to two per row), then the
+    // LDS writes, so the loads are in flight together
+    float v[kSepRowsX][2];
+#pragma unroll
+    for (int k = 0; k < kSepRowsX; ++k)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = threadIdx.x + j * kSepRow;
+            const long rw = row0 + k, x = x0 - r + i;
+            v[k][j] = (i < kSepRow + 2 * r && rw < nrows && x >= 0 && x < g.nx) ? src[rw * g.nx + x] : 0.0f;
         }
-    }
+#pragma unroll
+    for (int k = 0; k < kSepRowsX; ++k)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = threadIdx.x + j * kSepRow;
+            if (i < kSepRow + 2 * r) row[k][i] = v[k][j];
+        }
     __syncthreads();
     const long x = x0 + threadIdx.x;
     if (x >= g.nx) return;
@@ -94,9 +104,21 @@ k_sep_yz(const float* __restrict__ src, float* __restrict__ dst, SepGeom g) {
     const long sa = AXIS == 1 ? g.nx : g.nx * g.ny;       // stride along the axis
     const long base = x + (AXIS == 1 ? other * g.nx * g.ny : other * g.nx);
     sep_weights(g, w);
-    for (int i = ty; i < kSepSeg + 2 * r; i += 2) {
-        const long a = a0 - r + i;
-        tile[i * kSepCols + tx] = (x < g.nx && a >= 0 && a < na) ? src[base + a * sa] : 0.0f;
+    // loads in groups of 8 rows, each group's loads in flight together
+    const int nrow = kSepSeg + 2 * r;
+    for (int i0 = ty; i0 < nrow; i0 += 16) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 2 * u;
+            const long a = a0 - r + i;
+            v[u] = (i < nrow && x < g.nx && a >= 0 && a < na) ? src[base + a * sa] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 2 * u;
+            if (i < nrow) tile[i * kSepCols + tx] = v[u];
+        }
     }
     __syncthreads();
     if (x >= g.nx) return;
@@ -111,6 +133,175 @@ k_sep_yz(const float* __restrict__ src, float* __restrict__ dst, SepGeom g) {
         }
         dst[base + a * sa] = acc / ws;
     }
+}
+
+// x pass for a half-width R known at compile time (1..8): the same tile of
+// kSepRowsX rows (row stride padded to 16 bytes), but thread t computes the 8
+// consecutive outputs 8 (t % 32) .. + 7 of row t / 32 from 8 + 2R values read
+// once from LDS, with the weights in registers and reciprocal weight sums.
+template <int R>
+__global__ void __launch_bounds__(kSepRow)
+k_sep_x_t(const float* __restrict__ src, float* __restrict__ dst, SepGeom g) {
+    __shared__ float w[2 * kSepMaxR + 1];
+    constexpr int S = (kSepRow + 2 * R + 3) / 4 * 4;
+    __shared__ __attribute__((aligned(16))) float row[kSepRowsX][S];
+    const long x0 = (long)blockIdx.x * kSepRow;
+    const long nrows = g.ny * g.nz;
+    const long row0 = (long)blockIdx.y * kSepRowsX;
+    sep_weights(g, w);
+    float v[kSepRowsX][2];
+#pragma unroll
+    for (int k = 0; k < kSepRowsX; ++k)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = threadIdx.x + j * kSepRow;
+            const long rw = row0 + k, x = x0 - R + i;
+            v[k][j] = (i < kSepRow + 2 * R && rw < nrows && x >= 0 && x < g.nx) ? src[rw * g.nx + x] : 0.0f;
+        }
+#pragma unroll
+    for (int k = 0; k < kSepRowsX; ++k)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int i = threadIdx.x + j * kSepRow;
+            if (i < kSepRow + 2 * R) row[k][i] = v[k][j];
+        }
+    __syncthreads();
+    const int k = threadIdx.x / 32, i0 = 8 * (threadIdx.x % 32);
+    const long rw = row0 + k, xs = x0 + i0;
+    if (rw >= nrows || xs >= g.nx) return;
+    float wr[2 * R + 1];
+    float wsum = 0.0f;
+#pragma unroll
+    for (int q = 0; q <= 2 * R; ++q) {
+        wr[q] = w[q];
+        wsum += wr[q];
+    }
+    const float inv = 1.0f / wsum;
+    constexpr int NV = (8 + 2 * R + 3) / 4;   // float4 reads covering the window
+    float t[4 * NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const float4 f = *reinterpret_cast<const float4*>(&row[k][i0 + 4 * q]);
+        t[4 * q] = f.x; t[4 * q + 1] = f.y; t[4 * q + 2] = f.z; t[4 * q + 3] = f.w;
+    }
+    float o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const long x = xs + j;
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q <= 2 * R; ++q) acc = __builtin_fmaf(wr[q], t[j + q], acc);
+        float scale = inv;
+        if (x < R || x + R >= g.nx) {   // taps outside the cube carry no weight
+            float ws = 0.0f;
+#pragma unroll
+            for (int q = 0; q <= 2 * R; ++q)
+                if (x + q - R >= 0 && x + q - R < g.nx) ws += wr[q];
+            scale = 1.0f / ws;
+        }
+        o[j] = acc * scale;
+    }
+    float* d = dst + rw * g.nx + xs;
+    if (xs + 8 <= g.nx && ((uintptr_t)d % 16) == 0) {
+        reinterpret_cast<float4*>(d)[0] = make_float4(o[0], o[1], o[2], o[3]);
+        reinterpret_cast<float4*>(d)[1] = make_float4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (xs + j < g.nx) d[j] = o[j];
+    }
+}
+
+// y or z pass for a half-width R known at compile time (1..8): the same
+// tile, but each thread computes 32 consecutive outputs along the axis from
+// 32 + 2R tile values read once into registers, with the weights in
+// registers; interior outputs use the reciprocal of the full weight sum, the
+// outputs within R of a face the sum of their in-cube taps.
+constexpr int kSepTMaxR = 8;
+template <int AXIS, int R>
+__global__ void __launch_bounds__(256)
+k_sep_yz_t(const float* __restrict__ src, float* __restrict__ dst, SepGeom g) {
+    __shared__ float w[2 * kSepMaxR + 1];
+    extern __shared__ float tile[];   // [kSepSeg + 2R][kSepCols]
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const long x = (long)blockIdx.x * kSepCols + tx;
+    const long a0 = (long)blockIdx.y * kSepSeg;
+    const long other = blockIdx.z;
+    const long na = AXIS == 1 ? g.ny : g.nz;
+    const long sa = AXIS == 1 ? g.nx : g.nx * g.ny;
+    const long base = x + (AXIS == 1 ? other * g.nx * g.ny : other * g.nx);
+    sep_weights(g, w);
+    constexpr int nrow = kSepSeg + 2 * R;
+    for (int i0 = ty; i0 < nrow; i0 += 16) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 2 * u;
+            const long a = a0 - R + i;
+            v[u] = (i < nrow && x < g.nx && a >= 0 && a < na) ? src[base + a * sa] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 2 * u;
+            if (i < nrow) tile[i * kSepCols + tx] = v[u];
+        }
+    }
+    __syncthreads();
+    if (x >= g.nx) return;
+    float wr[2 * R + 1];
+    float wsum = 0.0f;
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k) {
+        wr[k] = w[k];
+        wsum += wr[k];
+    }
+    const float inv = 1.0f / wsum;
+    constexpr int NO = kSepSeg / 2;   // outputs of this thread: rows [NO ty, NO ty + NO)
+    float t[NO + 2 * R];
+#pragma unroll
+    for (int i = 0; i < NO + 2 * R; ++i) t[i] = tile[(NO * ty + i) * kSepCols + tx];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+        const long a = a0 + NO * ty + j;
+        if (a >= na) break;
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k <= 2 * R; ++k) acc = __builtin_fmaf(wr[k], t[j + k], acc);
+        float scale = inv;
+        if (a < R || a + R >= na) {   // taps outside the cube carry no weight
+            float ws = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= 2 * R; ++k)
+                if (a + k - R >= 0 && a + k - R < na) ws += wr[k];
+            scale = 1.0f / ws;
+        }
+        dst[base + a * sa] = acc * scale;
+    }
+}
+
+// y (AXIS 1) or z (AXIS 2) pass: the register-window kernel for half-widths
+// 1..8, the general one otherwise.
+template <int AXIS>
+static hipError_t launch_yz(dim3 grid, hipStream_t st, const float* src, float* dst, const SepGeom& g) {
+    const size_t lds = (size_t)(kSepSeg + 2 * g.r) * kSepCols * sizeof(float);
+    const dim3 block(kSepCols, 2);
+#define IG_YZ_CASE(RR)                                                                                  \
+    case RR:                                                                                            \
+        hipLaunchKernelGGL((k_sep_yz_t<AXIS, RR>), grid, block, lds, st, src, dst, g);                  \
+        return hipGetLastError();
+    switch (g.r) {
+        IG_YZ_CASE(1) IG_YZ_CASE(2) IG_YZ_CASE(3) IG_YZ_CASE(4)
+        IG_YZ_CASE(5) IG_YZ_CASE(6) IG_YZ_CASE(7) IG_YZ_CASE(8)
+        default: break;
+    }
+#undef IG_YZ_CASE
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_sep_yz<AXIS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_sep_yz<AXIS>, grid, block, lds, st, src, dst, g);
+    return hipGetLastError();
 }
 
 struct DenseGeom {
@@ -344,29 +535,26 @@ extern "C" ig_status ig_smooth(const ig_smooth_params* s, const float* d_in, flo
         g.sigma = p.sigma[0];
         const long xrows = (ny * nz + kSepRowsX - 1) / kSepRowsX;
         if (xrows > 2147483647L) return fail(IG_ERR_UNSUPPORTED, "cube too large");
-        hipLaunchKernelGGL(k_sep_x, dim3((unsigned)((nx + kSepRow - 1) / kSepRow), (unsigned)xrows), dim3(kSepRow), 0,
-                           st_, d_in, d_out, g);
+        const dim3 xgrid((unsigned)((nx + kSepRow - 1) / kSepRow), (unsigned)xrows);
+        switch (g.r) {
+#define IG_X_CASE(RR) \
+            case RR: hipLaunchKernelGGL(k_sep_x_t<RR>, xgrid, dim3(kSepRow), 0, st_, d_in, d_out, g); break;
+            IG_X_CASE(1) IG_X_CASE(2) IG_X_CASE(3) IG_X_CASE(4)
+            IG_X_CASE(5) IG_X_CASE(6) IG_X_CASE(7) IG_X_CASE(8)
+#undef IG_X_CASE
+            default: hipLaunchKernelGGL(k_sep_x, xgrid, dim3(kSepRow), 0, st_, d_in, d_out, g); break;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(IG_ERR_DEVICE, "x pass: %s", hipGetErrorString(e));
         g.r = p.r[1];
         g.sigma = p.sigma[1];
         const unsigned gx = (unsigned)((nx + kSepCols - 1) / kSepCols);
-        size_t lds = (size_t)(kSepSeg + 2 * g.r) * kSepCols * sizeof(float);
-        if (lds > 65536 && (e = hipFuncSetAttribute((const void*)k_sep_yz<1>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
-            return fail(IG_ERR_DEVICE, "y pass: %s", hipGetErrorString(e));
-        hipLaunchKernelGGL(k_sep_yz<1>, dim3(gx, (unsigned)((ny + kSepSeg - 1) / kSepSeg), (unsigned)nz),
-                           dim3(kSepCols, 2), lds, st_, (const float*)d_out, d_work, g);
-        if ((e = hipGetLastError()) != hipSuccess) return fail(IG_ERR_DEVICE, "y pass: %s", hipGetErrorString(e));
+        e = launch_yz<1>(dim3(gx, (unsigned)((ny + kSepSeg - 1) / kSepSeg), (unsigned)nz), st_, d_out, d_work, g);
+        if (e != hipSuccess) return fail(IG_ERR_DEVICE, "y pass: %s", hipGetErrorString(e));
         g.r = p.r[2];
         g.sigma = p.sigma[2];
-        lds = (size_t)(kSepSeg + 2 * g.r) * kSepCols * sizeof(float);
-        if (lds > 65536 && (e = hipFuncSetAttribute((const void*)k_sep_yz<2>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
-            return fail(IG_ERR_DEVICE, "z pass: %s", hipGetErrorString(e));
-        hipLaunchKernelGGL(k_sep_yz<2>, dim3(gx, (unsigned)((nz + kSepSeg - 1) / kSepSeg), (unsigned)ny),
-                           dim3(kSepCols, 2), lds, st_, (const float*)d_work, d_out, g);
-        if ((e = hipGetLastError()) != hipSuccess) return fail(IG_ERR_DEVICE, "z pass: %s", hipGetErrorString(e));
+        e = launch_yz<2>(dim3(gx, (unsigned)((nz + kSepSeg - 1) / kSepSeg), (unsigned)ny), st_, d_work, d_out, g);
+        if (e != hipSuccess) return fail(IG_ERR_DEVICE, "z pass: %s", hipGetErrorString(e));
         return IG_OK;
     }
     int tz = 0;
