@@ -103,8 +103,20 @@ k_lift_x(const float* __restrict__ src, float* __restrict__ dst, LiftGeom g) {
     const long y = active ? L % g.by : 0, z = active ? L / g.by : 0;
     const long base = g.nx * (y + g.ny * z);
     float* line = X + ty * n;
-    if (active)
-        for (int j = tx; j < n; j += 64) line[FWD ? j : slot_of(j, ne)] = src[base + j];
+    // loads in groups of 8, each group in flight together before its LDS writes
+    for (int j0 = tx; j0 < n; j0 += 64 * 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + 64 * u;
+            v[u] = (active && j < n) ? src[base + j] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + 64 * u;
+            if (active && j < n) line[FWD ? j : slot_of(j, ne)] = v[u];
+        }
+    }
     __syncthreads();
     if (FWD) lift_forward<KIND>(line, 1, n, tx, 64, active);
     else lift_inverse<KIND>(line, 1, n, tx, 64, active);
@@ -126,8 +138,20 @@ k_lift_yz(const float* __restrict__ src, float* __restrict__ dst, LiftGeom g, in
     const long es = AXIS == 1 ? g.nx : g.nx * g.ny;
     const long base = x + (AXIS == 1 ? other * g.nx * g.ny : other * g.nx);
     float* col = X + tx;
-    if (active)
-        for (int j = ty; j < n; j += rows) col[(FWD ? j : slot_of(j, ne)) * W] = src[base + j * es];
+    // loads in groups of 8, each group in flight together before its LDS writes
+    for (int j0 = ty; j0 < n; j0 += rows * 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + rows * u;
+            v[u] = (active && j < n) ? src[base + j * es] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + rows * u;
+            if (active && j < n) col[(FWD ? j : slot_of(j, ne)) * W] = v[u];
+        }
+    }
     __syncthreads();
     if (FWD) lift_forward<KIND>(col, W, n, ty, rows, active);
     else lift_inverse<KIND>(col, W, n, ty, rows, active);
@@ -143,10 +167,11 @@ struct ThrGeom {
     double thr[IG_WAVELET_MAX_LEVELS + 1];   // level l at [l - 1]; the final approximation at [levels]
 };
 
+// one row segment of 256 voxels per workgroup: grid (ceil(nx / 256), ny, nz)
 __global__ void __launch_bounds__(256) k_wthresh(float* __restrict__ c, ThrGeom g) {
-    const long n = g.nx * g.ny * g.nz;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-        const long x = i % g.nx, t = i / g.nx, y = t % g.ny, z = t / g.ny;
+    const long x = (long)blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x < g.nx) {
+        const long i = x + g.nx * (y + g.ny * z);
         int lv = g.levels + 1;
         for (int l = 1; l <= g.levels; ++l)
             if (x >= g.sx[l] || y >= g.sy[l] || z >= g.sz[l]) {
@@ -323,9 +348,9 @@ extern "C" ig_status ig_wavelet_denoise(const ig_wavelet_params* p, const float*
     }
     for (int l = 0; l < p->levels; ++l) g.thr[l] = p->t[l] * rms;
     g.thr[p->levels] = p->t[p->levels - 1] * rms;
-    const long n = (long)(nx * ny * nz);
-    const unsigned blocks = (unsigned)std::min<long>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_wthresh, dim3(blocks), dim3(256), 0, s, d_out, g);
+    // ny, nz <= kMaxLineYZ and nx <= kMaxLineX keep the grid within its limits
+    hipLaunchKernelGGL(k_wthresh, dim3((unsigned)((nx + 255) / 256), (unsigned)ny, (unsigned)nz), dim3(256), 0, s,
+                       d_out, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(IG_ERR_DEVICE, "threshold: %s", hipGetErrorString(e));
     return inverse_impl(p, d_out, d_out, nx, ny, nz, s);
