@@ -6,6 +6,8 @@ accumulation order: raw convolution outputs must agree to 1e-5 of the
 largest |term| sum.  Outputs stored as bf16 are allowed one bf16 rounding
 step (relative 2^-8).
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -44,7 +46,7 @@ SHAPES = [(5, 6, 40), (3, 9, 33), (7, 4, 70)]
 def test_conv_forward_raw(dev, shape, cin, cout):
     import torch
     from paper_1609_03782_amd import surrogate as sg
-    rng = np.random.default_rng(hash((shape, cin, cout)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(repr((shape, cin, cout)).encode()))
     a, ta = _bf(rng.standard_normal(shape + (cin,)))
     W, _ = _bf(rng.standard_normal((27, cin, cout)) * 0.2)
     b = rng.standard_normal(cout).astype(np.float32)
