@@ -404,6 +404,115 @@ k_dense(const float* __restrict__ src, float* __restrict__ dst, DenseGeom g) {
     }
 }
 
+// Dense pass with 8 outputs along z per thread and the z half-width RZ known
+// at compile time (1..8): the loops run over (dy, dx) outside and dz inside,
+// so each input column of 8 + 2 RZ values is read from LDS once into
+// registers and serves all (2 RZ + 1) x 8 products of that column (about a
+// third of the LDS reads of the general loop order).
+template <int RZ>
+__global__ void __launch_bounds__(256)
+k_dense_t(const float* __restrict__ src, float* __restrict__ dst, DenseGeom g) {
+    constexpr int TZ = 8, KZ = 2 * RZ + 1, NC = TZ + 2 * RZ;
+    extern __shared__ float sm[];
+    const int rx = g.rx, ry = g.ry;
+    const int kx = 2 * rx + 1, ky = 2 * ry + 1;
+    const int nw = kx * ky * KZ;
+    const int TXh = 64 + 2 * rx, TYh = 4 + 2 * ry;
+    const int plane = TXh * TYh;
+    float* W = sm;
+    float* T = sm + nw;
+    __shared__ float total_sh;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+    const long x0 = (long)blockIdx.x * 64, y0 = (long)blockIdx.y * 4, z0 = (long)blockIdx.z * TZ;
+    {
+        const double cx = cos(g.theta[0]), sx = sin(g.theta[0]);
+        const double cy = cos(g.theta[1]), sy = sin(g.theta[1]);
+        const double cz = cos(g.theta[2]), sz = sin(g.theta[2]);
+        const double R00 = cz * cy, R01 = cz * sy * sx - sz * cx, R02 = cz * sy * cx + sz * sx;
+        const double R10 = sz * cy, R11 = sz * sy * sx + cz * cx, R12 = sz * sy * cx - cz * sx;
+        const double R20 = -sy, R21 = cy * sx, R22 = cy * cx;
+        for (int t = tid; t < nw; t += 256) {
+            const int ix = t % kx, iy = (t / kx) % ky, iz = t / (kx * ky);
+            const double dx = ix - rx, dy = iy - ry, dz = iz - RZ;
+            const double u0 = R00 * dx + R10 * dy + R20 * dz;
+            const double u1 = R01 * dx + R11 * dy + R21 * dz;
+            const double u2 = R02 * dx + R12 * dy + R22 * dz;
+            const double e = u0 * u0 / (2.0 * g.sigma[0] * g.sigma[0]) + u1 * u1 / (2.0 * g.sigma[1] * g.sigma[1]) +
+                             u2 * u2 / (2.0 * g.sigma[2] * g.sigma[2]);
+            W[t] = (float)exp(-e);
+        }
+    }
+    const int ntile = plane * NC;
+    for (int i0 = tid; i0 < ntile; i0 += 256 * 8) {   // loads in groups of 8
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 256 * u;
+            const int ix = i % TXh, iy = (i / TXh) % TYh, iz = i / plane;
+            const long x = x0 - rx + ix, y = y0 - ry + iy, z = z0 - RZ + iz;
+            v[u] = (i < ntile && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz)
+                       ? src[x + g.nx * (y + g.ny * z)]
+                       : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + 256 * u < ntile) T[i0 + 256 * u] = v[u];
+    }
+    __syncthreads();
+    if (tid < 64) {
+        float s = 0.0f;
+        for (int t = tid; t < nw; t += 64) s += W[t];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (tid == 0) total_sh = s;
+    }
+    const bool edge = x0 - rx < 0 || x0 + 63 + rx >= g.nx || y0 - ry < 0 || y0 + 3 + ry >= g.ny || z0 - RZ < 0 ||
+                      z0 + TZ - 1 + RZ >= g.nz;
+    float acc[TZ], ws[TZ];
+#pragma unroll
+    for (int j = 0; j < TZ; ++j) {
+        acc[j] = 0.0f;
+        ws[j] = 0.0f;
+    }
+    for (int dy = -ry; dy <= ry; ++dy) {
+        const long yy = y0 + ty + dy;
+        for (int dx = -rx; dx <= rx; ++dx) {
+            const float* col = T + (ty + ry + dy) * TXh + tx + rx + dx;
+            float c[NC];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) c[i] = col[i * plane];
+            const float* wz = W + (dy + ry) * kx + (dx + rx);   // + (dz + RZ) kx ky
+#pragma unroll
+            for (int k = 0; k < KZ; ++k) {
+                const float wv = wz[k * kx * ky];
+#pragma unroll
+                for (int j = 0; j < TZ; ++j) acc[j] = __builtin_fmaf(wv, c[j + k], acc[j]);
+            }
+            if (edge) {
+                const long xx = x0 + tx + dx;
+                const bool in_xy = xx >= 0 && xx < g.nx && yy >= 0 && yy < g.ny;
+#pragma unroll
+                for (int k = 0; k < KZ; ++k) {
+                    const float wv = wz[k * kx * ky];
+#pragma unroll
+                    for (int j = 0; j < TZ; ++j) {
+                        const long zz = z0 + j + k - RZ;
+                        ws[j] += (in_xy && zz >= 0 && zz < g.nz) ? wv : 0.0f;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const float total = total_sh;
+    const long x = x0 + tx, y = y0 + ty;
+    if (x >= g.nx || y >= g.ny) return;
+#pragma unroll
+    for (int j = 0; j < TZ; ++j) {
+        const long z = z0 + j;
+        if (z < g.nz) dst[x + g.nx * (y + g.ny * z)] = acc[j] / (edge ? ws[j] : total);
+    }
+}
+
 }  // namespace igk
 
 // ====================================================================== host
@@ -481,9 +590,25 @@ bool overlaps(const void* a, const void* b, size_t bytes) {
     return a && b && x < y + bytes && y < x + bytes;
 }
 
+template <int RZ>
+void (*dense_t_kernel())(const float*, float*, DenseGeom) { return k_dense_t<RZ>; }
+
 template <int TZ>
 hipError_t launch_dense(const float* in, float* out, const DenseGeom& g, size_t lds, hipStream_t st) {
     auto k = k_dense<TZ>;
+    if constexpr (TZ == 8) {   // the register-column kernel for z half-widths 1..8
+        switch (g.rz) {
+            case 1: k = dense_t_kernel<1>(); break;
+            case 2: k = dense_t_kernel<2>(); break;
+            case 3: k = dense_t_kernel<3>(); break;
+            case 4: k = dense_t_kernel<4>(); break;
+            case 5: k = dense_t_kernel<5>(); break;
+            case 6: k = dense_t_kernel<6>(); break;
+            case 7: k = dense_t_kernel<7>(); break;
+            case 8: k = dense_t_kernel<8>(); break;
+            default: break;
+        }
+    }
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
