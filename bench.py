@@ -43,7 +43,79 @@ def cpu_baseline(cube, n_iter, K, tau, nz_s=None):
     what = "the whole cube" if nz_s is None else "a slab of the same cube"
     rec = {"value": round(vi / dt / 1e9, 5), "unit": "Gvoxel-iter/s", "cores": oracle.threads(), "kind": "oracle",
            "sample": f"{what}: {nx}x{ny}x{nz}, {n_iter} iterations, rms estimated, FP64 ({dt:.1f} s)"}
+    # one core on the first 16 planes (the same voxels' arithmetic; rms given,
+    # as the whole-cube run found it)
+    nthreads = oracle.threads()
+    slab1 = cube[:16]
+    try:
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        oracle.run(slab1, "pm_exp", K=K, tau=tau, n_iter=n_iter, rms=rho)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(nthreads)
+    rec["single_core"] = {"value": round(slab1.size * n_iter / dt1 / 1e9, 5), "unit": "Gvoxel-iter/s",
+                          "sample": f"16 planes of the cube: {nx}x{ny}x16, {n_iter} iterations ({dt1:.1f} s)"}
+    rec["host"] = host_info()
     return rec, out, rho
+
+
+def gpu_info():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "memory_GiB": round(p.total_memory / 2 ** 30, 1)}
+
+
+def host_info():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "cpus_visible": os.cpu_count(), "cpus_usable": usable}
+
+
+def per_run_ms(f, x, out, runs=20):
+    """Distribution of single-run times (HIP events around each run)."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream(x.device)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(runs)]
+    for a, b in ev:
+        a.record(stream)
+        f.run(x, out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"runs": runs, "p10": round(float(np.percentile(t, 10)), 4), "p50": round(float(np.percentile(t, 50)), 4),
+            "p90": round(float(np.percentile(t, 90)), 4)}
+
+
+def copy_gbps(x, reps=10):
+    """Device-to-device copy of the cube (torch copy_): bytes read + written / time."""
+    import torch
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del y
+    return 2.0 * x.numel() * x.element_size() / (ms * 1e-3) / 1e9
 
 
 # Algorithmic ALU work of one voxel-iteration of the edge-shared exponential
@@ -557,6 +629,14 @@ def main():
                              "frac": round(eff_launch / HBM_PEAK_GBS, 4)}
     roof.update({"kernel": "k_stream", "avg_launch_ms": round(avg_ms, 5), "launches": k_launches,
                  "iterations_per_launch": T})
+    # the same rates against what a plain device copy of the cube reaches here
+    cp = copy_gbps(x)
+    roof["measured_copy_GBps"] = round(cp, 1)
+    hbm["frac_of_copy"] = round(achieved_gbs / cp, 4)
+    roof["effective_hbm"]["frac_of_copy"] = round(eff_launch / cp, 4)
+    if roof["bound"] == "hbm":
+        roof["frac_of_copy"] = hbm["frac_of_copy"]
+    runs = per_run_ms(f, x, out)
 
     res = {
         "metric": METRIC,
@@ -566,6 +646,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_single_runs": runs,
+        "gpu": gpu_info(),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

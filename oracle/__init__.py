@@ -75,6 +75,8 @@ def _load():
         lib.oracle_round_f16.restype = d
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = i32
+        lib.oracle_set_threads.argtypes = [i32]
+        lib.oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -115,6 +117,11 @@ def rms(cube):
 def threads() -> int:
     """OpenMP threads the oracle uses."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops (this Python thread)."""
+    _load().oracle_set_threads(int(n))
 
 
 def round_bf16(x):

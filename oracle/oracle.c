@@ -38,6 +38,16 @@
 #include <omp.h>
 #endif
 
+/* Threads of later parallel loops (n > 0; the calling thread's setting). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of threads the oracle's parallel loops use. */
 int oracle_threads(void)
 {
