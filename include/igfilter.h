@@ -99,8 +99,11 @@ typedef struct {
     int32_t zchunk;    /* 0: split the cube into pieces of equal work, a whole number of
                           rounds of the workgroups the GPU holds at once; > 0: pieces
                           of zchunk output planes (BLOCKED) */
-    int32_t vec;       /* x voxels per lane: 1, 2, 4 or 8; 0 = automatic (8 above nx = 256,
-                          else 4 with `rows` chosen to cover nx) */
+    int32_t vec;       /* x voxels per lane: 1, 2, 4 or 8; 0 = automatic (8 for
+                          256 < nx <= 512, 4 above 512 (256-voxel x tiles), else 4 with
+                          `rows` chosen to cover nx).  Cubes wider than one tile
+                          (64 vec voxels) are cut into x tiles whose halo is t_block
+                          rounded up to a multiple of vec */
     int32_t rounds;    /* zchunk == 0: rounds of resident workgroups; 0 = as few as possible */
     int32_t rows;      /* rows per wavefront: 1, 2 or 4 (a tile has waves * rows rows); more
                           than 1 needs vec 4 and nx <= 256 / rows (one x tile); 0 = automatic

@@ -40,6 +40,7 @@ struct BlockGeom {
     int W;                // wavefronts per workgroup (== blockDim.y)
     int vec;              // 1: lane chunks are whole and aligned (vector I/O)
     int R;                // rows per wavefront (1, 2 or 4); a tile has W * R rows
+    int hx;               // x halo of a tile when ntx > 1 (t_block rounded up to whole lane chunks)
 };
 
 __device__ __forceinline__ float lane_shr1(float v) {  // lane i <- lane i-1, lane 0 <- 0
@@ -282,20 +283,22 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     const int ox0 = pc.tx * g.ox, oy0 = pc.ty * g.oy;
     const int ox1 = min(ox0 + g.ox, nx), oy1 = min(oy0 + g.oy, ny);
     const int oz0 = pc.z0, oz1 = pc.z1;
-    const int rx0 = g.ntx > 1 ? ox0 - T : 0;
+    const int rx0 = g.ntx > 1 ? ox0 - g.hx : 0;
     const int ry0 = g.nty > 1 ? oy0 - T : 0;
     const int zin0 = max(oz0 - T, 0), zin1 = min(oz1 + T, nz);
     const int nin = zin1 - zin0;
     const int y = ry0 + w * R + sr;               // this lane's row
     const int xl0 = rx0 + lr * V;
 
-    // x edge coefficients.  Vector path (one x tile, nx a multiple of V): the
-    // edges inside a lane's chunk are open (or belong to a lane past the end
-    // of the row, whose values are never used); only the edge to the next
-    // lane can be closed.  Scalar path: per edge.
+    // x edge coefficients.  Vector path (nx a multiple of V, tile origins
+    // multiples of V): a lane's chunk lies wholly inside or wholly outside the
+    // cube, so the edges inside a chunk are open (a chunk outside the cube
+    // holds clamped, finite values that never reach the cube), and only the
+    // edge to the next lane can cross a face: closed unless both of its
+    // voxels are in the cube.  Scalar path: per edge.
     float cx[VEC ? 1 : V];
     if constexpr (VEC) {
-        cx[0] = (xl0 + V < nx) ? P.coef[0] : P.closed;
+        cx[0] = (xl0 + V >= 1 && xl0 + V < nx) ? P.coef[0] : P.closed;
     } else {
 #pragma unroll
         for (int i = 0; i < V; ++i) {
@@ -314,8 +317,8 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
 
     const int ycl = min(max(y, 0), ny - 1);
     // 16-bit storage, vector path: input and output rows move through raw
-    // buffers over this tile's rows of one plane (at most 64 rows of at most
-    // 512 voxels).  A plane with nothing to load or store gets a buffer of size
+    // buffers over this tile's rows of one plane (at most 64 rows; the planner
+    // keeps them below 2^30 bytes).  A plane with nothing to load or store gets a buffer of size
     // 0 and a lane outside the output rows or columns a store offset past the
     // end, so every step issues the same memory operations and the compiler's
     // waits for an input plane count exactly the operations issued after it

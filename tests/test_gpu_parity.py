@@ -221,3 +221,42 @@ def test_reduce_and_compare(dev):
     ref = torch.from_numpy(d + 1e-3).to(dev)
     r = ig.compare(x, ref, tol=5e-4)
     assert r["max_abs"] == pytest.approx(1e-3, rel=1e-4) and r["n_over"] == cube.size
+
+
+# Cubes wider than one x tile (64 V voxels): tiles start at multiples of V,
+# so with nx a multiple of V the vector path serves them (1040, 600), else
+# the scalar one (1037).  Bitwise against the naive schedule, in FP32 and in
+# bfloat16 storage (buffer loads and stores), and FP32 against the oracle.
+WIDE_SHAPES = [(4, 5, 1040), (3, 4, 1037), (6, 9, 600)]
+
+
+@pytest.mark.parametrize("cond", CONDS)
+@pytest.mark.parametrize("shape", WIDE_SHAPES)
+def test_wide_cubes_bitwise(dev, oracle_lib, cond, shape):
+    import torch
+    import paper_1609_03782_amd as ig
+    cube = igsynth.random_cube(shape, seed=sum(shape) + 3, scale=2.0)
+    cube[shape[0] // 2, shape[1] // 2, shape[2] - 3] = 10.0
+    kw = dict(K=1.7, tau=0.05, n_iter=6, C=(1.0, 0.8, 1.3), cond=cond)
+    ref, rho = oracle_lib.run(cube, cond, K=1.7, tau=0.05, n_iter=6, C=(1.0, 0.8, 1.3))
+    for dtype in ("f32", "bf16"):
+        x = torch.from_numpy(cube).to(dev)
+        if dtype == "bf16":
+            x = x.to(torch.bfloat16)
+        outs = []
+        for s in (dict(kind="naive"), None, dict(kind="blocked", t_block=3, waves=10, vec=8),
+                  dict(kind="blocked", t_block=2, waves=12, vec=4)):
+            f = ig.Filter(shape, dtype=dtype, **kw)
+            if s is not None:
+                f.set_schedule(**s)
+            y = f.run(x)
+            torch.cuda.synchronize()
+            if s is None:
+                sc = f.schedule()
+                assert sc["kind"] == "blocked"
+            outs.append(y.float().cpu().numpy())
+            f.close()
+        for k, y in enumerate(outs[1:], 1):
+            assert np.array_equal(y, outs[0]), (dtype, k)
+        if dtype == "f32":
+            assert _err(outs[0], ref) <= TOL * rho
