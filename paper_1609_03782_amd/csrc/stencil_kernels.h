@@ -156,6 +156,52 @@ template <typename ST, int V> struct Vec16 {
 template <int V> struct Vec<__hip_bfloat16, V> : Vec16<__hip_bfloat16, V> {};
 template <int V> struct Vec<__half, V> : Vec16<__half, V> {};
 
+// V consecutive values at an address aligned only to the element: rows of a
+// cube whose nx is not a multiple of V start anywhere.  The types carry the
+// element's alignment, so the compiler emits wide accesses only where the
+// target allows unaligned ones and splits them otherwise.
+template <typename ST, int V> struct VecU;
+template <int V> struct VecU<float, V> {
+    typedef float vt __attribute__((ext_vector_type(V), aligned(4)));
+    static __device__ __forceinline__ void load(const float* p, float (&o)[V]) {
+        const vt q = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = q[i];
+    }
+    static __device__ __forceinline__ void store(float* p, const float (&v)[V]) {
+        vt q;
+#pragma unroll
+        for (int i = 0; i < V; ++i) q[i] = v[i];
+        *reinterpret_cast<vt*>(p) = q;
+    }
+};
+template <typename ST, int V> struct VecU16 {
+    typedef unsigned short vt __attribute__((ext_vector_type(V), aligned(2)));
+    static __device__ __forceinline__ void load(const ST* p, float (&o)[V]) {
+        const vt q = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const unsigned short u = q[i];
+            ST h;
+            __builtin_memcpy(&h, &u, 2);
+            o[i] = Store<ST>::load(h);
+        }
+    }
+    static __device__ __forceinline__ void store(ST* p, const float (&v)[V]) {
+        vt q;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const ST h = Store<ST>::store(v[i]);
+            unsigned short u;
+            __builtin_memcpy(&u, &h, 2);
+            q[i] = u;
+        }
+        *reinterpret_cast<vt*>(p) = q;
+    }
+};
+template <int V> struct VecU<__hip_bfloat16, V> : VecU16<__hip_bfloat16, V> {};
+template <int V> struct VecU<__half, V> : VecU16<__half, V> {};
+
 // Raw buffer access for the 16-bit storage types.  The hardware drops an
 // access at or past the buffer's byte size (a load returns zeros), so an
 // access that must not happen can still be issued: give the buffer size 0, or
@@ -372,6 +418,8 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
 
     float pf[V];
     const int ld_off = ((ycl - yb) * nx + xv) * (int)sizeof(ST);
+    // scalar path: this lane's chunk lies wholly inside the row
+    const bool inside = xl0 >= 0 && xl0 + V <= nx;
     // input plane zin0 + k into pf (buffer path: zeros, with no memory access,
     // when k is past the input range; otherwise not issued then)
     auto load = [&](int k) {
@@ -384,6 +432,8 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
             const ST* r = rowp + (long)(zin0 + k) * plane;
             if constexpr (VEC) {
                 Vec<ST, V>::load(r + xv, pf);
+            } else if (inside) {   // a chunk wholly in the row: one (unaligned) vector access
+                VecU<ST, V>::load(r + xl0, pf);
             } else {
 #pragma unroll
                 for (int i = 0; i < V; ++i) pf[i] = Store<ST>::load(r[min(max(xl0 + i, 0), nx - 1)]);
@@ -463,6 +513,8 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
                 ST* r = dst + (long)pz * plane + (long)y * nx;
                 if constexpr (VEC) {
                     if (xl0 >= ox0 && xl0 + V <= ox1) Vec<ST, V>::store(r + xl0, out);
+                } else if (inside && xl0 >= ox0 && xl0 + V <= ox1) {
+                    VecU<ST, V>::store(r + xl0, out);
                 } else {
 #pragma unroll
                     for (int i = 0; i < V; ++i) {
