@@ -132,6 +132,7 @@ void auto_vec_rows(int64_t nx, int* V, int* R) {
     // nx = 1024, 860 against 648 at 2048, 574 against 344 at 600)
     if (nx > 512) { *V = 4; *R = 1; return; }
     if (nx > 256) { *V = 8; *R = 1; return; }
+    if (nx < 4) { *V = nx >= 2 ? 2 : 1; *R = 1; return; }   // a lane's chunk never exceeds the row
     *V = 4;
     *R = nx <= 64 ? 4 : nx <= 128 ? 2 : 1;
 }
@@ -158,6 +159,10 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
     if (R == 0) R = 1;
     const int W = s.waves;
     if (!(V == 1 || V == 2 || V == 4 || V == 8)) return "vec must be 1, 2, 4 or 8";
+    if (V > nx) return "vec must not exceed nx";
+    // a tile's rows of one plane are addressed with 32-bit byte offsets below 2^30
+    if ((long)s.waves * std::max(R, 1) * nx * (long)dtype_size(p.dtype) >= (1L << 30))
+        return "rows too long for the blocked schedule (use naive)";
     if (!(R == 1 || R == 2 || R == 4)) return "rows must be 1, 2 or 4";
     if (R > 1 && (V != 4 || (64 / R) * V < nx)) return "rows > 1 needs vec 4 and nx <= 256 / rows";
     if (W < 1 || W > 16) return "waves must be in 1..16";
@@ -273,6 +278,11 @@ static ig_schedule auto_schedule(const ig_params* p) {
     if (stream_lds_bytes(s.vec, s.t_block, s.waves) > kMaxLds) s.waves = 8;
     s.zchunk = 0;
     s.rounds = 1;
+    if ((long)s.waves * s.rows * p->nx * (long)dtype_size(p->dtype) >= (1L << 30)) {   // absurdly long rows
+        ig_schedule n{};
+        n.kind = IG_SCHED_NAIVE;
+        return n;
+    }
     return s;
 }
 

@@ -144,11 +144,20 @@ k_batch_stage(const BatchCube* __restrict__ cubes, const SumChunk* __restrict__ 
 }
 
 // Batch cubes have nx <= 256, so the automatic layout is 4 voxels per lane
-// with 1, 2 or 4 rows per wavefront.
+// with 1, 2 or 4 rows per wavefront, or 1 or 2 voxels per lane when nx < 4.
 template <int COND, int T, int D>
 __device__ __forceinline__ void run_piece_v(const BatchCube& cb, const float* src, float* dst, const Piece pc,
                                             const DevParams& P, float* lds) {
     const bool vec = cb.g.vec;
+    if (cb.V == 1) {
+        stream_piece<COND, float, 1, D, true, 1>(src, dst, cb.g, pc, P, lds);
+        return;
+    }
+    if (cb.V == 2) {
+        vec ? stream_piece<COND, float, 2, D, true, 1>(src, dst, cb.g, pc, P, lds)
+            : stream_piece<COND, float, 2, D, false, 1>(src, dst, cb.g, pc, P, lds);
+        return;
+    }
     switch (cb.g.R) {
         case 4: vec ? stream_piece<COND, float, 4, D, true, 4>(src, dst, cb.g, pc, P, lds)
                     : stream_piece<COND, float, 4, D, false, 4>(src, dst, cb.g, pc, P, lds); break;
@@ -488,7 +497,8 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         PassPlan pp;
         const char* why = plan_pass(p, s, T, ncu, &pp);
         if (why) return fail(IG_ERR_INVALID_ARG, "batch item %d: %s", c, why);
-        if (pp.V != 4) return fail(IG_ERR_UNSUPPORTED, "batch item %d: layout with %d voxels per lane", c, pp.V);
+        if (pp.V != 4 && pp.V != 2 && pp.V != 1)
+            return fail(IG_ERR_UNSUPPORTED, "batch item %d: layout with %d voxels per lane", c, pp.V);
         lds = std::max(lds, stream_lds_bytes(pp.V, T, W));
         cb.g = pp.g;
         if (((uintptr_t)cb.in % (pp.V * 4)) || ((uintptr_t)cb.out % (pp.V * 4))) cb.g.vec = 0;

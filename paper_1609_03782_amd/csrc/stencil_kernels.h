@@ -202,6 +202,29 @@ template <typename ST, int V> struct VecU16 {
 template <int V> struct VecU<__hip_bfloat16, V> : VecU16<__hip_bfloat16, V> {};
 template <int V> struct VecU<__half, V> : VecU16<__half, V> {};
 
+// o[i] = q[clamp(i + sh, 0, V - 1)]: a lane's loaded chunk moved to where its
+// voxels are, the row's end value repeated past it.  sh < 0 only occurs for a
+// chunk wholly left of the cube (tiles start at multiples of V), whose voxels
+// all take the row's first value, q[0].  log2 V select stages.
+template <int V>
+__device__ __forceinline__ void shift_clamp(const float (&q)[V], int sh, float (&o)[V]) {
+    float t[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) t[i] = q[i];
+    const int s = sh < 0 ? 0 : (sh > V - 1 ? V - 1 : sh);
+#pragma unroll
+    for (int b = 1; b < V; b <<= 1) {
+        const bool on = (s & b) != 0;
+        float u[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) u[i] = t[i + b < V ? i + b : V - 1];
+#pragma unroll
+        for (int i = 0; i < V; ++i) t[i] = on ? u[i] : t[i];
+    }
+#pragma unroll
+    for (int i = 0; i < V; ++i) o[i] = sh < 0 ? q[0] : t[i];
+}
+
 // Raw buffer access for the 16-bit storage types.  The hardware drops an
 // access at or past the buffer's byte size (a load returns zeros), so an
 // access that must not happen can still be issued: give the buffer size 0, or
@@ -266,6 +289,46 @@ template <typename ST, int V> struct BufRow16 {
         }
     }
 };
+
+// FP32 scalar path, branch-free output: a lane whose chunk lies wholly in the
+// output range stores it whole at byte offset `full` (else kBufOffNone); the
+// lane at the row's end stores its first k values (k < V) as chunks of 4, 2
+// and 1 chosen by the bits of k, at byte offset `tail` (else kBufOffNone).
+// Every lane issues the same stores; the hardware drops those past the end.
+template <int V>
+__device__ __forceinline__ void store_row_f32(__amdgpu_buffer_rsrc_t r, int full, int tail, int k,
+                                              const float (&v)[V]) {
+    typedef unsigned u32x4_ __attribute__((ext_vector_type(4)));
+    typedef unsigned u32x2_ __attribute__((ext_vector_type(2)));
+    unsigned w[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) w[i] = __builtin_bit_cast(unsigned, v[i]);
+    if constexpr (V >= 4) {
+#pragma unroll
+        for (int c = 0; c < V / 4; ++c)
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4_{w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]}, r,
+                                                   full == kBufOffNone ? kBufOffNone : full + 16 * c, 0, 0);
+    } else if constexpr (V == 2) {
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2_{w[0], w[1]}, r, full, 0, 0);
+    }
+    if constexpr (V >= 2) {
+        // chunk of 4 at element 0 (V = 8 only: k < 8), of 2 at element k & 4,
+        // of 1 at element k & 6
+        if constexpr (V == 8)
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4_{w[0], w[1], w[2], w[3]}, r,
+                                                   (k & 4) ? tail : kBufOffNone, 0, 0);
+        if constexpr (V >= 4) {
+            const bool hi = (k & 4) != 0;
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2_{hi ? w[4 % V] : w[0], hi ? w[5 % V] : w[1]}, r,
+                                                  (k & 2) ? tail + 4 * (k & 4) : kBufOffNone, 0, 0);
+        }
+        const int e = k & 6;
+        unsigned x1 = w[0];
+#pragma unroll
+        for (int i = 2; i < V; i += 2) x1 = e == i ? w[i] : x1;
+        __builtin_amdgcn_raw_buffer_store_b32(x1, r, (k & 1) ? tail + 4 * e : kBufOffNone, 0, 0);
+    }
+}
 
 // ---------------------------------------------------------------- streaming
 // One workgroup = W wavefronts = W*R consecutive rows of a tile; R rows per
@@ -418,8 +481,17 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
 
     float pf[V];
     const int ld_off = ((ycl - yb) * nx + xv) * (int)sizeof(ST);
-    // scalar path: this lane's chunk lies wholly inside the row
+    // scalar path: this lane's chunk lies wholly inside the row; its loads
+    // start at xs (nx >= V, which the planner guarantees) and shift by sh
     const bool inside = xl0 >= 0 && xl0 + V <= nx;
+    const int xs = min(max(xl0, 0), nx - V), sh = xl0 - xs;
+    // FP32 scalar path stores (store_row_f32): whole chunks in the output
+    // range, or the first k values of the chunk that reaches the range's end
+    constexpr bool RAG = !VEC && sizeof(ST) == 4 && V >= 2;
+    const int rag_k = ox1 - xl0;
+    const bool rag_rowok = row_store && xl0 >= ox0;
+    const int rag_full = (rag_rowok && xl0 + V <= ox1) ? ((y - yb) * nx + xl0) * 4 : kBufOffNone;
+    const int rag_tail = (rag_rowok && rag_k > 0 && rag_k < V) ? ((y - yb) * nx + xl0) * 4 : kBufOffNone;
     // input plane zin0 + k into pf (buffer path: zeros, with no memory access,
     // when k is past the input range; otherwise not issued then)
     auto load = [&](int k) {
@@ -432,11 +504,12 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
             const ST* r = rowp + (long)(zin0 + k) * plane;
             if constexpr (VEC) {
                 Vec<ST, V>::load(r + xv, pf);
-            } else if (inside) {   // a chunk wholly in the row: one (unaligned) vector access
-                VecU<ST, V>::load(r + xl0, pf);
             } else {
-#pragma unroll
-                for (int i = 0; i < V; ++i) pf[i] = Store<ST>::load(r[min(max(xl0 + i, 0), nx - 1)]);
+                // every lane: one vector access (aligned to the element only)
+                // at its chunk clamped into the row; shift_clamp moves the
+                // values into place when the plane is used (no branch around
+                // the load, so the loop's waits stay exact)
+                VecU<ST, V>::load(r + xs, pf);
             }
         }
     };
@@ -456,14 +529,18 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
         constexpr int p = decltype(parity)::value, q = p ^ 1;
         constexpr bool STEADY = decltype(steady)::value;
         if (STEADY || s < nin) {
+            if constexpr (VEC) {
 #pragma unroll
-            for (int i = 0; i < V; ++i) lv[0][q][i] = pf[i];
+                for (int i = 0; i < V; ++i) lv[0][q][i] = pf[i];
+            } else {
+                shift_clamp<V>(pf, sh, lv[0][q]);
+            }
         }
         load(s + 1);
 
         // every level advances one plane; out holds the last level's new row
         float out[V];
-        if constexpr (BUF) {
+        if constexpr (BUF || RAG) {
 #pragma unroll
             for (int i = 0; i < V; ++i) out[i] = 0.0f;
         }
@@ -509,7 +586,7 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
                 if (t + 1 < T) lv[t + 1][q][i] = Store<ST>::quant(o);
                 else out[i] = Store<ST>::quant(o);
             }
-            if (!BUF && t == T - 1 && row_store && pz >= oz0 && pz < oz1) {
+            if (!BUF && !RAG && t == T - 1 && row_store && pz >= oz0 && pz < oz1) {
                 ST* r = dst + (long)pz * plane + (long)y * nx;
                 if constexpr (VEC) {
                     if (xl0 >= ox0 && xl0 + V <= ox1) Vec<ST, V>::store(r + xl0, out);
@@ -528,6 +605,14 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
         // the per-row skip above (a row that skipped it is never an output
         // row, so its lanes hold kBufOffNone; a plane the step does not
         // produce gets a buffer of size 0)
+        if constexpr (RAG) {
+            const int pz = zin0 + s - T;
+            const bool zon = pz >= oz0 && pz < oz1;
+            const int pzc = max(min(pz, zin1 - 1), zin0);
+            const auto rs = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + (long)pzc * plane + (long)yb * nx), 0,
+                                                              zon ? tile_bytes : 0, kBufWord3);
+            store_row_f32<V>(rs, rag_full, rag_tail, rag_k, out);
+        }
         if constexpr (BUF) {
             const int pz = zin0 + s - T;
             const bool zon = pz >= oz0 && pz < oz1;
