@@ -51,3 +51,43 @@ def test_balanced_split_whole_rounds():
     for j in range(8):
         zs = pcs[j::8][:, 2]
         assert zs.max() - zs.min() < 512 // 2
+
+
+def test_vec_never_exceeds_nx():
+    """A lane's chunk never reaches past the row: explicit vec > nx is
+    rejected, the automatic layout takes 1 or 2 voxels per lane below nx = 4."""
+    for nx, want in [(1, 1), (2, 2), (3, 2), (4, 4), (5, 4)]:
+        g, _ = ig.schedule_plan((3, 5, nx), dict(kind="blocked", t_block=1, waves=4), 1)
+        assert g["V"] == want, (nx, g)
+    assert ig.schedule_check((3, 5, 3), dict(kind="blocked", t_block=1, waves=4, vec=4), n_iter=1) is not None
+    assert ig.schedule_check((3, 5, 8), dict(kind="blocked", t_block=1, waves=4, vec=8), n_iter=1) is None
+
+
+def test_x_tiles_start_at_whole_lane_chunks():
+    """Cubes wider than one tile: tile origins (output start minus the halo)
+    are multiples of vec, the halo covers t_block, and vector I/O is used
+    exactly when nx is a multiple of vec."""
+    for nx in (600, 1037, 1040, 2048):
+        for V in (2, 4, 8):
+            for T in (1, 2, 3, 4):
+                s = dict(kind="blocked", t_block=T, waves=12, vec=V)
+                if ig.schedule_check((2, 30, nx), s, n_iter=T) is not None:
+                    continue
+                g, _ = ig.schedule_plan((2, 30, nx), s, T)
+                if g["ntx"] == 1:
+                    continue
+                hx = (64 * V - g["ox"]) // 2
+                assert hx >= T and hx % V == 0 and g["ox"] % V == 0, (nx, V, T, g)
+                assert g["vec_io"] == (1 if nx % V == 0 else 0), (nx, V, T, g)
+
+
+def test_automatic_layout_by_width():
+    for nx, want in [(200, 4), (300, 8), (512, 8), (513, 4), (1024, 4), (4096, 4)]:
+        g, _ = ig.schedule_plan((2, 30, nx), dict(kind="blocked", t_block=2, waves=12), 2)
+        assert g["V"] == want, (nx, g)
+
+
+def test_rows_too_long_for_blocked_schedule():
+    # a tile's rows of one plane must stay below 2^30 bytes (32-bit offsets)
+    why = ig.schedule_check((1, 1, 1 << 24), dict(kind="blocked", t_block=1, waves=16, vec=8), n_iter=1)
+    assert why is not None and "too long" in why
