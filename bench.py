@@ -414,8 +414,7 @@ def bench_smooth(x):
              "gauss_iso_fwhm3": ("gauss", (3.0, 3.0, 3.0), (0, 0, 0)),
              "gauss_aniso_fwhm2x3x3": ("gauss", (2.0, 3.0, 3.0), (0, 0, 0)),
              "gauss_rotated_fwhm2x3x3_10_20_30deg": ("gauss", (2.0, 3.0, 3.0), (10.0, 20.0, 30.0))}
-    res = {}
-    for name, (kind, size, theta) in cases.items():
+    def timed(kind, size, theta):
         ig.smooth(x, kind, size, theta, out=out, work=work)
         torch.cuda.synchronize()
         s = torch.cuda.current_stream(x.device)
@@ -425,10 +424,22 @@ def bench_smooth(x):
             ig.smooth(x, kind, size, theta, out=out, work=work)
         e1.record(s)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 5
+        return e0.elapsed_time(e1) / 5
+
+    res = {}
+    for name, (kind, size, theta) in cases.items():
+        ms = timed(kind, size, theta)
         r, sep = ig.smooth_geometry(kind, size, theta)
         res[name] = {"ms": round(ms, 3), "Gvoxel_s": round(x.numel() / ms / 1e6, 1), "half_widths": r,
                      "separable": sep}
+        if sep:
+            # the fused pass moves 8 B per voxel; the three passes, timed beside it, 24 B
+            res[name]["algorithmic_TBps"] = round(8 * x.numel() / ms / 1e9, 2)
+            try:
+                ig.smooth_set_path(1)
+                res[name]["three_pass_ms"] = round(timed(kind, size, theta), 3)
+            finally:
+                ig.smooth_set_path(0)
     res["paper_gpu_s_for_1.4e8_voxels"] = {"gauss_iso": 1.8, "gauss_aniso": 3.5}
     return res
 

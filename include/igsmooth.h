@@ -15,11 +15,15 @@
  * the weighted mean runs over the neighbours inside the cube (weights
  * renormalised over them).
  *
- * The box and the axis-aligned Gaussian are separable and run as three 1-D
- * passes (x, y, z), each renormalised over its in-cube taps, which gives the
- * 3-D definition exactly (up to rounding).  A rotated Gaussian runs as one
- * dense 3-D pass.  Weights are computed on the device in FP64 and stored as
- * FP32; sums are FP32.
+ * The box and the axis-aligned Gaussian are separable: 1-D sums along x, y
+ * and z, each renormalised over its in-cube taps, give the 3-D definition
+ * exactly (up to rounding).  For half-widths up to 8 one fused pass computes
+ * all three sums while streaming the cube along z (each voxel read and
+ * written once); larger half-widths, or rows longer than 5,592,405 voxels,
+ * run three passes (x, y, z) through d_work.  Both routes compute the same
+ * sums in the same order, so they give the same values.  A rotated Gaussian
+ * runs as one dense 3-D pass.  Weights are computed on the device in FP64 and
+ * stored as FP32; sums are FP32.
  */
 #ifndef IGSMOOTH_H
 #define IGSMOOTH_H
@@ -49,8 +53,9 @@ ig_status ig_smooth_geometry(const ig_smooth_params* s, int32_t* radius, int32_t
 
 /* Smooth d_in (FP32, nx*ny*nz voxels, x fastest) into d_out on hip_stream;
  * the buffers and the stream belong to the calling thread's current device.
- * d_work: nx*ny*nz FP32 device scratch, required by the separable path (it
- * holds the middle pass), ignored (may be NULL) by the dense one.  d_in is only
+ * d_work: nx*ny*nz FP32 device scratch, required by the separable kernels (the
+ * three-pass route holds its middle pass there; the fused pass leaves it
+ * untouched), ignored (may be NULL) by the dense one.  d_in is only
  * read; d_in, d_out and d_work must not overlap.  Asynchronous.  Errors:
  * IG_ERR_INVALID_ARG (NULL or overlapping buffers, bad sizes, even or
  * non-integer box sizes, FWHM <= 0, non-finite values, non-zero reserved or box
@@ -61,6 +66,13 @@ ig_status ig_smooth_geometry(const ig_smooth_params* s, int32_t* radius, int32_t
  * IG_ERR_DEVICE. */
 ig_status ig_smooth(const ig_smooth_params* s, const float* d_in, float* d_out, float* d_work, int64_t nx,
                     int64_t ny, int64_t nz, void* hip_stream);
+
+/* Route of the separable kernels for later ig_smooth calls, process-wide:
+ * 0 (the default) the fused pass wherever it applies, 1 always the three
+ * passes (for comparisons and measurements; the values are the same).  Not
+ * synchronised with ig_smooth calls running in other threads.  Errors:
+ * IG_ERR_INVALID_ARG for any other value.  Host only. */
+ig_status ig_smooth_set_path(int32_t path);
 
 #ifdef __cplusplus
 }

@@ -124,6 +124,7 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_int32)]),
     "ig_smooth": (ctypes.c_int, [ctypes.POINTER(IgSmoothParams), _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_int64, _P]),
+    "ig_smooth_set_path": (ctypes.c_int, [ctypes.c_int32]),
     "ig_wavelet_forward": (ctypes.c_int, [ctypes.POINTER(IgWaveletParams), _P, _P, ctypes.c_int64, ctypes.c_int64,
                                           ctypes.c_int64, _P]),
     "ig_wavelet_inverse": (ctypes.c_int, [ctypes.POINTER(IgWaveletParams), _P, _P, ctypes.c_int64, ctypes.c_int64,
@@ -550,6 +551,12 @@ def smooth(x, kind="gauss", size=(3.0, 3.0, 3.0), theta=(0.0, 0.0, 0.0), truncat
                            ctypes.c_void_p(work.data_ptr()) if work is not None else None, nx, ny, nz,
                            _stream_ptr(x)), "ig_smooth")
     return out
+
+
+def smooth_set_path(path):
+    """Route of the box and axis-aligned Gaussian smoothing, process-wide
+    (ig_smooth_set_path): 0 the fused pass where it applies, 1 three passes."""
+    _check(lib().ig_smooth_set_path(int(path)), "ig_smooth_set_path")
 
 
 def wavelet_params(kind="haar", levels=3, t=(0.5, 0.8, 1.1), rms=0.0):

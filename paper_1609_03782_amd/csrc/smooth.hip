@@ -1,10 +1,12 @@
 // Box and Gaussian smoothing (Section 3.1-3.2); see include/igsmooth.h.
 //
-// Separable kernels (box, axis-aligned Gaussian): three 1-D passes x -> out,
-// y -> work, z -> out.  Each pass stages a segment of its axis plus the halo
-// in LDS (coalesced loads along x), computes its weights in FP64 at block
-// start, and divides every output by the sum of the weights of its in-cube
-// taps: the product of the three per-axis renormalisations is the 3-D one.
+// Separable kernels (box, axis-aligned Gaussian): 1-D sums along x, y and z,
+// each divided by the sum of the weights of its in-cube taps (the product of
+// the three per-axis renormalisations is the 3-D one), with the weights
+// computed in FP64 at block start.  Half-widths up to 8: one fused pass that
+// streams the cube along z (k_sep3_t).  Otherwise three passes x -> out,
+// y -> work, z -> out, each staging a segment of its axis plus the halo in LDS
+// (coalesced loads along x).
 //
 // Rotated Gaussian: one dense pass.  A workgroup of 64 x 4 threads owns an
 // output tile of 64 x 4 x TZ voxels, stages the input tile plus halo and the
@@ -304,6 +306,184 @@ static hipError_t launch_yz(dim3 grid, hipStream_t st, const float* src, float* 
     return hipGetLastError();
 }
 
+// Fused separable pass for half-widths up to 8: x, y and z in one sweep.
+// A workgroup of 64 x 8 threads owns an output tile of 64 (x) x 32 (y) voxels
+// and a chunk of g.tz planes along z, and streams its input planes (the chunk
+// plus R on each side) through LDS: each plane's tile plus its x and y halos
+// is loaded (zeros outside the cube), smoothed along x into a second LDS tile
+// (all 32 + 2R rows), then along y in registers; thread (tx, ty) keeps rows
+// 4 ty .. 4 ty + 3 of column tx and the last 2R + 1 of its y-smoothed planes,
+// from which it forms the z sums.  HBM sees each voxel read once (plus the
+// halos) and written once, against three reads and three writes for three
+// passes.  R is the largest of the three half-widths; an axis with a smaller
+// one gets zero weights at its outer taps, which leaves every sum and every
+// renormalisation what the three-pass kernels compute, term by term.  Loads
+// and stores go through raw buffers: a lane whose voxel lies outside the cube
+// gets an offset past the buffer's end, and a plane outside the cube or the
+// chunk a buffer of size 0, so no branch surrounds a memory access.
+constexpr int kF3X = 64;              // tile width (one lane per column)
+constexpr int kF3Y = 32;              // tile height (four rows per thread)
+constexpr int kF3Threads = 512;
+constexpr int kF3MaxR = 8;
+constexpr int kSmBufWord3 = 0x00020000;   // gfx9 raw buffer: 32-bit format, no swizzle or stride
+constexpr int kSmOffNone = 0x40000000;    // past the end of every buffer made here
+
+struct Sep3Geom {
+    long nx, ny, nz;
+    int r[3];          // per-axis half-widths (<= R)
+    int kind;
+    int tz;            // output planes per workgroup
+    double sigma[3];
+};
+
+// renormalisation factor of the output at coordinate c along an axis of n voxels
+template <int R>
+__device__ __forceinline__ float axis_scale(const float (&w)[2 * R + 1], float inv, long c, long n) {
+    if (c >= R && c + R < n) return inv;
+    float ws = 0.0f;
+#pragma unroll
+    for (int k = 0; k <= 2 * R; ++k)
+        if (c + k - R >= 0 && c + k - R < n) ws += w[k];
+    return ws > 0.0f ? 1.0f / ws : 0.0f;   // 0: a column outside the cube (never stored)
+}
+
+template <int R>
+__global__ void __launch_bounds__(kF3Threads)
+k_sep3_t(const float* __restrict__ src, float* __restrict__ dst, Sep3Geom g) {
+    constexpr int W = 2 * R + 1;
+    constexpr int NR = kF3Y + 2 * R;                      // tile rows with the y halo
+    constexpr int RX = kF3X + 2 * R;                      // tile row length with the x halo
+    constexpr int NV = (4 + 2 * R + 3) / 4;               // 16-byte LDS reads per 4 x outputs
+    constexpr int RS = 60 + 4 * NV;                       // row stride: the last window ends at it
+    static_assert(RS >= RX && RS % 4 == 0, "row stride");
+    constexpr int NE = NR * RX;                           // tile elements per plane
+    constexpr int NL = (NE + kF3Threads - 1) / kF3Threads;
+    constexpr int NXI = (NR * (kF3X / 4) + kF3Threads - 1) / kF3Threads;
+    __shared__ float wt[3][W];
+    __shared__ __attribute__((aligned(16))) float raw[NR * RS + 4];   // + a slot for lanes with no element
+    __shared__ float xs[NR * kF3X];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const long nx = g.nx, ny = g.ny, nz = g.nz;
+    const long x0 = (long)blockIdx.x * kF3X, y0 = (long)blockIdx.y * kF3Y;
+    for (int k = tid; k < 3 * W; k += kF3Threads) {
+        const int a = k / W, d = k % W - R;
+        float w = 0.0f;
+        if (d >= -g.r[a] && d <= g.r[a])
+            w = g.kind == IG_SMOOTH_BOX ? 1.0f : (float)exp(-(double)d * d / (2.0 * g.sigma[a] * g.sigma[a]));
+        wt[a][k % W] = w;
+    }
+    // this thread's tile elements: byte offset from the first input row (or
+    // kSmOffNone outside the cube) and LDS slot (the spare slot past the tile)
+    const long yb = max(y0 - R, 0L);
+    const int in_bytes = (int)((min(y0 + kF3Y + R, ny) - yb) * nx * 4);
+    int loff[NL], lidx[NL];
+#pragma unroll
+    for (int m = 0; m < NL; ++m) {
+        const int e = tid + m * kF3Threads;
+        const int row = e / RX, col = e - row * RX;
+        const long y = y0 - R + row, x = x0 - R + col;
+        const bool ok = e < NE && y >= 0 && y < ny && x >= 0 && x < nx;
+        loff[m] = ok ? (int)(((y - yb) * nx + x) * 4) : kSmOffNone;
+        lidx[m] = e < NE ? row * RS + col : NR * RS;
+    }
+    // this thread's outputs: rows 4 ty + j of column x0 + tx
+    const int rows_out = (int)min((long)kF3Y, ny - y0);
+    const int out_bytes = (int)(rows_out * nx * 4);
+    int soff[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        soff[j] = (4 * ty + j < rows_out && x0 + tx < nx) ? (int)(((4 * ty + j) * nx + x0 + tx) * 4) : kSmOffNone;
+    __syncthreads();
+    float wx[W], wy[W], wz[W];
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        wx[k] = wt[0][k];
+        wy[k] = wt[1][k];
+        wz[k] = wt[2][k];
+        sx += wx[k];
+        sy += wy[k];
+        sz += wz[k];
+    }
+    const float ix = 1.0f / sx, iy = 1.0f / sy, iz = 1.0f / sz;
+    float ys[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ys[j] = axis_scale<R>(wy, iy, y0 + 4 * ty + j, ny);
+
+    const long plane = nx * ny;
+    const long z0 = (long)blockIdx.z * g.tz, z1 = min(z0 + g.tz, nz);
+    const long zb = z0 - R, ze = z1 + R;
+    float pf[NL];
+    auto load = [&](long zi) {
+        const bool on = zi >= 0 && zi < nz && zi < ze;
+        const auto rs = __builtin_amdgcn_make_buffer_rsrc((void*)(src + (on ? zi : 0) * plane + yb * nx), 0,
+                                                          on ? in_bytes : 0, kSmBufWord3);
+#pragma unroll
+        for (int m = 0; m < NL; ++m)
+            pf[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, loff[m], 0, 0));
+    };
+    float ring[4][W];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < W; ++k) ring[j][k] = 0.0f;
+    load(zb);
+    for (long zi = zb; zi < ze; ++zi) {
+#pragma unroll
+        for (int m = 0; m < NL; ++m) raw[lidx[m]] = pf[m];
+        load(zi + 1);
+        __syncthreads();
+        // x: outputs 4c .. 4c + 3 of tile row `row`, from 4 + 2R values
+#pragma unroll
+        for (int m = 0; m < NXI; ++m) {
+            const int it = tid + m * kF3Threads;
+            const int row = it >> 4, c = it & 15;
+            if (row < NR) {
+                float t[4 * NV];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    const float4 f = *reinterpret_cast<const float4*>(&raw[row * RS + 4 * c + 4 * q]);
+                    t[4 * q] = f.x; t[4 * q + 1] = f.y; t[4 * q + 2] = f.z; t[4 * q + 3] = f.w;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) acc = __builtin_fmaf(wx[k], t[j + k], acc);
+                    xs[row * kF3X + 4 * c + j] = acc * axis_scale<R>(wx, ix, x0 + 4 * c + j, nx);
+                }
+            }
+        }
+        __syncthreads();
+        // y: rows 4 ty .. 4 ty + 3 of column tx, from 4 + 2R values
+        float t[4 + 2 * R];
+#pragma unroll
+        for (int i = 0; i < 4 + 2 * R; ++i) t[i] = xs[(4 * ty + i) * kF3X + tx];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < W; ++k) acc = __builtin_fmaf(wy[k], t[j + k], acc);
+#pragma unroll
+            for (int k = 0; k + 1 < W; ++k) ring[j][k] = ring[j][k + 1];
+            ring[j][W - 1] = acc * ys[j];
+        }
+        // z: output plane zi - R from the ring (planes zi - 2R .. zi)
+        const long zo = zi - R;
+        const bool zon = zo >= z0 && zo < z1;
+        const float zsc = axis_scale<R>(wz, iz, zo, nz);
+        const auto rd = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + (zon ? zo : 0) * plane + y0 * nx), 0,
+                                                          zon ? out_bytes : 0, kSmBufWord3);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < W; ++k) acc = __builtin_fmaf(wz[k], ring[j][k], acc);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, acc * zsc), rd, soff[j], 0, 0);
+        }
+    }
+}
+
 struct DenseGeom {
     long nx, ny, nz;
     int rx, ry, rz;
@@ -523,6 +703,41 @@ namespace {
 
 constexpr double kFwhmToSigma = 0.42466090014400953;   // 1 / (2 sqrt(2 ln 2))
 
+int g_smooth_path = 0;   // 0: the fused pass where it applies, 1: always three passes
+
+// the fused separable pass applies for half-widths up to kF3MaxR and rows
+// short enough that a tile's rows stay below 2^30 bytes (32-bit buffer offsets)
+bool fused_applies(int rmax, long nx) {
+    return g_smooth_path == 0 && rmax <= kF3MaxR && (long)(kF3Y + 2 * kF3MaxR) * nx * 4 <= (1L << 30);
+}
+
+template <int R>
+hipError_t launch_sep3(dim3 grid, hipStream_t st, const float* in, float* out, const Sep3Geom& g) {
+    hipLaunchKernelGGL(k_sep3_t<R>, grid, dim3(kF3Threads), 0, st, in, out, g);
+    return hipGetLastError();
+}
+
+hipError_t run_sep3(int rmax, const float* in, float* out, const Sep3Geom& g0, hipStream_t st) {
+    Sep3Geom g = g0;
+    const long gx = (g.nx + kF3X - 1) / kF3X, gy = (g.ny + kF3Y - 1) / kF3Y;
+    // about 1024 workgroups (four per compute unit), at least 8 planes each
+    const long tz = std::min(g.nz, std::max(8L, (g.nz * gx * gy + 1023) / 1024));
+    g.tz = (int)tz;
+    const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)((g.nz + tz - 1) / tz));
+    switch (rmax) {
+        case 0: return launch_sep3<0>(grid, st, in, out, g);
+        case 1: return launch_sep3<1>(grid, st, in, out, g);
+        case 2: return launch_sep3<2>(grid, st, in, out, g);
+        case 3: return launch_sep3<3>(grid, st, in, out, g);
+        case 4: return launch_sep3<4>(grid, st, in, out, g);
+        case 5: return launch_sep3<5>(grid, st, in, out, g);
+        case 6: return launch_sep3<6>(grid, st, in, out, g);
+        case 7: return launch_sep3<7>(grid, st, in, out, g);
+        case 8: return launch_sep3<8>(grid, st, in, out, g);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 struct SmoothPlan {
     int r[3];
     bool separable;
@@ -655,6 +870,13 @@ extern "C" ig_status ig_smooth(const ig_smooth_params* s, const float* d_in, flo
         for (int a = 0; a < 3; ++a)
             if (p.r[a] > kSepMaxR) return fail(IG_ERR_UNSUPPORTED, "half-width %d above %d", p.r[a], kSepMaxR);
         if (ny > 65535 || nz > 65535) return fail(IG_ERR_UNSUPPORTED, "ny and nz must be <= 65535");
+        const int rmax = std::max(p.r[0], std::max(p.r[1], p.r[2]));
+        if (fused_applies(rmax, nx)) {
+            const Sep3Geom g3{nx, ny, nz, {p.r[0], p.r[1], p.r[2]}, s->kind, 0, {p.sigma[0], p.sigma[1], p.sigma[2]}};
+            const hipError_t e = run_sep3(rmax, d_in, d_out, g3, st_);
+            if (e != hipSuccess) return fail(IG_ERR_DEVICE, "fused pass: %s", hipGetErrorString(e));
+            return IG_OK;
+        }
         SepGeom g{nx, ny, nz, 0, s->kind, 0.0};
         g.r = p.r[0];
         g.sigma = p.sigma[0];
@@ -699,5 +921,11 @@ extern "C" ig_status ig_smooth(const ig_smooth_params* s, const float* d_in, flo
                    : tz == 2 ? launch_dense<2>(d_in, d_out, g, lds, st_)
                              : launch_dense<1>(d_in, d_out, g, lds, st_);
     if (e != hipSuccess) return fail(IG_ERR_DEVICE, "dense pass: %s", hipGetErrorString(e));
+    return IG_OK;
+}
+
+extern "C" ig_status ig_smooth_set_path(int32_t path) {
+    if (path != 0 && path != 1) return fail(IG_ERR_INVALID_ARG, "path must be 0 or 1");
+    g_smooth_path = path;
     return IG_OK;
 }

@@ -214,3 +214,10 @@ def test_batch_resident_limit_validation():
         assert L.ig_batch_get_resident(None) == ig.IG_ERR_INVALID_ARG
     finally:
         L.ig_batch_set_resident(old)
+
+
+def test_smooth_set_path_validation():
+    assert ig.lib().ig_smooth_set_path(2) == ig.IG_ERR_INVALID_ARG
+    assert ig.lib().ig_smooth_set_path(-1) == ig.IG_ERR_INVALID_ARG
+    assert ig.lib().ig_smooth_set_path(1) == ig.IG_OK
+    assert ig.lib().ig_smooth_set_path(0) == ig.IG_OK

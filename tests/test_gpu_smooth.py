@@ -94,3 +94,41 @@ def test_smooth_fullsize_sampled(dev):
             x0, x1 = max(0, xx - rx), min(512, xx + rx + 1)
             ref = Sm.smooth(cube[z0:z1, y0:y1, x0:x1], k)[z - z0, yy - y0, xx - x0]
             assert abs(y[z, yy, xx] - ref) <= _tol(cube, kind, theta), (kind, (z, yy, xx))
+
+
+FUSED_CASES = [("box", (1, 1, 1)), ("box", (3, 3, 3)), ("box", (3, 5, 5)), ("box", (7, 3, 1)), ("box", (17, 3, 9)),
+               ("gauss", (3.0, 3.0, 3.0)), ("gauss", (2.0, 3.0, 3.0)), ("gauss", (1.5, 4.0, 2.5)),
+               ("gauss", (5.0, 2.0, 6.5)), ("gauss", (7.0, 3.0, 3.0))]
+
+
+@pytest.mark.parametrize("shape", [(150, 70, 130), (23, 29, 71), (9, 1, 65), (1, 1, 300), (17, 40, 1)])
+def test_fused_pass_equals_three_passes(dev, shape):
+    """The fused separable pass (half-widths up to 8) computes the three
+    passes' sums term by term: the same values, on cubes of several tiles and
+    z chunks with ragged edges (FWHM 7 has half-width 9: three passes both times)."""
+    import torch
+    import paper_1609_03782_amd as ig
+    x = torch.from_numpy(igsynth.random_cube(shape, seed=21)).to(dev)
+    for kind, size in FUSED_CASES:
+        try:
+            ig.smooth_set_path(1)
+            a = ig.smooth(x, kind, size)
+        finally:
+            ig.smooth_set_path(0)
+        b = ig.smooth(x, kind, size)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), (shape, kind, size, float((a - b).abs().max()))
+
+
+def test_fused_pass_matches_oracle_across_chunks(dev):
+    """A cube of 3 x 2 tiles in x, y and 9 z chunks of 8 planes against the
+    FP64 oracle."""
+    import torch
+    import paper_1609_03782_amd as ig
+    cube = igsynth.random_cube((70, 45, 130), seed=8)
+    x = torch.from_numpy(cube).to(dev)
+    for kind, size in [("box", (3, 5, 5)), ("gauss", (2.0, 3.0, 3.0)), ("gauss", (5.0, 2.0, 6.5))]:
+        y = ig.smooth(x, kind, size).cpu().numpy()
+        ref = Sm.smooth(cube, _kernel(kind, size))
+        assert np.abs(y - ref).max() <= _tol(cube, kind, (0, 0, 0)), (kind, size)
+
