@@ -427,11 +427,25 @@ k_sep3_t(const float* __restrict__ src, float* __restrict__ dst, Sep3Geom g) {
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int k = 0; k < W; ++k) ring[j][k] = 0.0f;
+    // the outputs of plane zi - R are stored one iteration later, after the
+    // next plane's loads are issued, so waiting for those loads never waits
+    // for the stores
+    float ob[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    long zs = zb - R - 1;   // plane held in ob (none yet)
+    auto store = [&]() {
+        const bool zon = zs >= z0 && zs < z1;
+        const auto rd = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + (zon ? zs : 0) * plane + y0 * nx), 0,
+                                                          zon ? out_bytes : 0, kSmBufWord3);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, ob[j]), rd, soff[j], 0, 0);
+    };
     load(zb);
     for (long zi = zb; zi < ze; ++zi) {
 #pragma unroll
         for (int m = 0; m < NL; ++m) raw[lidx[m]] = pf[m];
         load(zi + 1);
+        store();
         __syncthreads();
         // x: outputs 4c .. 4c + 3 of tile row `row`, from 4 + 2R values
 #pragma unroll
@@ -469,19 +483,17 @@ k_sep3_t(const float* __restrict__ src, float* __restrict__ dst, Sep3Geom g) {
             ring[j][W - 1] = acc * ys[j];
         }
         // z: output plane zi - R from the ring (planes zi - 2R .. zi)
-        const long zo = zi - R;
-        const bool zon = zo >= z0 && zo < z1;
-        const float zsc = axis_scale<R>(wz, iz, zo, nz);
-        const auto rd = __builtin_amdgcn_make_buffer_rsrc((void*)(dst + (zon ? zo : 0) * plane + y0 * nx), 0,
-                                                          zon ? out_bytes : 0, kSmBufWord3);
+        zs = zi - R;
+        const float zsc = axis_scale<R>(wz, iz, zs, nz);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             float acc = 0.0f;
 #pragma unroll
             for (int k = 0; k < W; ++k) acc = __builtin_fmaf(wz[k], ring[j][k], acc);
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, acc * zsc), rd, soff[j], 0, 0);
+            ob[j] = acc * zsc;
         }
     }
+    store();
 }
 
 struct DenseGeom {
