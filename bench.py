@@ -577,6 +577,8 @@ def main():
     ap.add_argument("--threshold", type=float, default=0.05)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of the cube size (counter calibration)")
+    ap.add_argument("--smooth-only", action="store_true",
+                    help="only time the box / Gaussian smoothing set on the 512^3 cube (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -597,6 +599,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes_read": a.numel() * 4, "calib_copy_bytes_written": a.numel() * 4}))
+        return
+    if args.smooth_only:
+        x = torch.from_numpy(igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])).to(dev)
+        print(json.dumps({"smoothing_512": bench_smooth(x)}))
         return
     if args.workload == "surrogate":
         bench_surrogate(args)

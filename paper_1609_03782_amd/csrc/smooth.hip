@@ -364,6 +364,10 @@ k_sep3_t(const float* __restrict__ src, float* __restrict__ dst, Sep3Geom g) {
     __shared__ float xs[NR * kF3X];
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const long nx = g.nx, ny = g.ny, nz = g.nz;
+    // blockIdx.x runs fastest, and workgroups are dealt to the 8 XCDs in turn:
+    // with 8 tiles across (512 voxels) a column of tiles shares an XCD and its
+    // L2, so y-halo rows are mostly rows a neighbour tile read recently.
+    // (Handing each XCD a contiguous run of tiles instead measured slower.)
     const long x0 = (long)blockIdx.x * kF3X, y0 = (long)blockIdx.y * kF3Y;
     for (int k = tid; k < 3 * W; k += kF3Threads) {
         const int a = k / W, d = k % W - R;
@@ -413,8 +417,11 @@ k_sep3_t(const float* __restrict__ src, float* __restrict__ dst, Sep3Geom g) {
     const long plane = nx * ny;
     const long z0 = (long)blockIdx.z * g.tz, z1 = min(z0 + g.tz, nz);
     const long zb = z0 - R, ze = z1 + R;
-    float pf[NL];
-    auto load = [&](long zi) {
+    // input planes are loaded two steps ahead, into two register sets used in
+    // turn (the loop runs an even number of steps: a step past the last input
+    // plane loads nothing and stores nothing)
+    float pa[NL], pb[NL];
+    auto load = [&](long zi, float (&pf)[NL]) {
         const bool on = zi >= 0 && zi < nz && zi < ze;
         const auto rs = __builtin_amdgcn_make_buffer_rsrc((void*)(src + (on ? zi : 0) * plane + yb * nx), 0,
                                                           on ? in_bytes : 0, kSmBufWord3);
@@ -427,9 +434,9 @@ k_sep3_t(const float* __restrict__ src, float* __restrict__ dst, Sep3Geom g) {
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int k = 0; k < W; ++k) ring[j][k] = 0.0f;
-    // the outputs of plane zi - R are stored one iteration later, after the
-    // next plane's loads are issued, so waiting for those loads never waits
-    // for the stores
+    // the outputs of plane zi - R are stored one step later, after the loads
+    // of that step are issued, so waiting for a plane's loads never waits for
+    // stores issued after them
     float ob[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     long zs = zb - R - 1;   // plane held in ob (none yet)
     auto store = [&]() {
@@ -440,11 +447,10 @@ k_sep3_t(const float* __restrict__ src, float* __restrict__ dst, Sep3Geom g) {
         for (int j = 0; j < 4; ++j)
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, ob[j]), rd, soff[j], 0, 0);
     };
-    load(zb);
-    for (long zi = zb; zi < ze; ++zi) {
+    auto step = [&](long zi, float (&pf)[NL]) {
 #pragma unroll
         for (int m = 0; m < NL; ++m) raw[lidx[m]] = pf[m];
-        load(zi + 1);
+        load(zi + 2, pf);
         store();
         __syncthreads();
         // x: outputs 4c .. 4c + 3 of tile row `row`, from 4 + 2R values
@@ -492,6 +498,16 @@ k_sep3_t(const float* __restrict__ src, float* __restrict__ dst, Sep3Geom g) {
             for (int k = 0; k < W; ++k) acc = __builtin_fmaf(wz[k], ring[j][k], acc);
             ob[j] = acc * zsc;
         }
+    };
+    // the stores here write nothing (no plane held yet); they give the loop's
+    // entry the same order of outstanding loads and stores as its back edge
+    load(zb, pa);
+    store();
+    load(zb + 1, pb);
+    store();
+    for (long zi = zb; zi < ze; zi += 2) {
+        step(zi, pa);
+        step(zi + 1, pb);
     }
     store();
 }
@@ -723,29 +739,37 @@ bool fused_applies(int rmax, long nx) {
     return g_smooth_path == 0 && rmax <= kF3MaxR && (long)(kF3Y + 2 * kF3MaxR) * nx * 4 <= (1L << 30);
 }
 
+// One round of workgroups: as many z chunks per (x, y) tile as fill every
+// compute unit to the kernel's occupancy once (each chunk at least 8
+// planes), so no compute unit runs a second, partial round alone.
 template <int R>
-hipError_t launch_sep3(dim3 grid, hipStream_t st, const float* in, float* out, const Sep3Geom& g) {
+hipError_t launch_sep3(hipStream_t st, const float* in, float* out, Sep3Geom g) {
+    int dev = 0, ncu = 0, occ = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sep3_t<R>, kF3Threads, 0);
+    if (e != hipSuccess) return e;
+    const long gx = (g.nx + kF3X - 1) / kF3X, gy = (g.ny + kF3Y - 1) / kF3Y;
+    const long slots = (long)std::max(ncu, 1) * std::max(occ, 1);
+    const long chunks = std::max(1L, std::min(slots / (gx * gy), (g.nz + 7) / 8));
+    const long tz = (g.nz + chunks - 1) / chunks;
+    g.tz = (int)tz;
+    const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)((g.nz + tz - 1) / tz));
     hipLaunchKernelGGL(k_sep3_t<R>, grid, dim3(kF3Threads), 0, st, in, out, g);
     return hipGetLastError();
 }
 
-hipError_t run_sep3(int rmax, const float* in, float* out, const Sep3Geom& g0, hipStream_t st) {
-    Sep3Geom g = g0;
-    const long gx = (g.nx + kF3X - 1) / kF3X, gy = (g.ny + kF3Y - 1) / kF3Y;
-    // about 1024 workgroups (four per compute unit), at least 8 planes each
-    const long tz = std::min(g.nz, std::max(8L, (g.nz * gx * gy + 1023) / 1024));
-    g.tz = (int)tz;
-    const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)((g.nz + tz - 1) / tz));
+hipError_t run_sep3(int rmax, const float* in, float* out, const Sep3Geom& g, hipStream_t st) {
     switch (rmax) {
-        case 0: return launch_sep3<0>(grid, st, in, out, g);
-        case 1: return launch_sep3<1>(grid, st, in, out, g);
-        case 2: return launch_sep3<2>(grid, st, in, out, g);
-        case 3: return launch_sep3<3>(grid, st, in, out, g);
-        case 4: return launch_sep3<4>(grid, st, in, out, g);
-        case 5: return launch_sep3<5>(grid, st, in, out, g);
-        case 6: return launch_sep3<6>(grid, st, in, out, g);
-        case 7: return launch_sep3<7>(grid, st, in, out, g);
-        case 8: return launch_sep3<8>(grid, st, in, out, g);
+        case 0: return launch_sep3<0>(st, in, out, g);
+        case 1: return launch_sep3<1>(st, in, out, g);
+        case 2: return launch_sep3<2>(st, in, out, g);
+        case 3: return launch_sep3<3>(st, in, out, g);
+        case 4: return launch_sep3<4>(st, in, out, g);
+        case 5: return launch_sep3<5>(st, in, out, g);
+        case 6: return launch_sep3<6>(st, in, out, g);
+        case 7: return launch_sep3<7>(st, in, out, g);
+        case 8: return launch_sep3<8>(st, in, out, g);
         default: return hipErrorInvalidValue;
     }
 }
