@@ -132,3 +132,26 @@ def test_fused_pass_matches_oracle_across_chunks(dev):
         ref = Sm.smooth(cube, _kernel(kind, size))
         assert np.abs(y - ref).max() <= _tol(cube, kind, (0, 0, 0)), (kind, size)
 
+
+
+def test_long_rows_take_the_three_pass_route(dev):
+    """Rows up to 5,592,405 voxels run the fused pass, longer ones the three
+    passes (a tile's rows must stay below 2^30 bytes); both sides of the limit
+    against the oracle's renormalised moving mean along x, and the fused pass
+    at the limit against the three passes."""
+    import torch
+    import paper_1609_03782_amd as ig
+    for nx in (5_592_405, 5_592_406):
+        cube = igsynth.random_cube((1, 1, nx), seed=nx % 97)
+        x = torch.from_numpy(cube).to(dev)
+        y = ig.smooth(x, "box", (3, 1, 1)).cpu().numpy()
+        ref = Sm.smooth(cube, _kernel("box", (3, 1, 1)))
+        assert np.abs(y - ref).max() <= _tol(cube, "box", (0, 0, 0)), nx
+        if nx == 5_592_405:
+            try:
+                ig.smooth_set_path(1)
+                a = ig.smooth(x, "gauss", (2.0, 1.0, 1.0))
+            finally:
+                ig.smooth_set_path(0)
+            b = ig.smooth(x, "gauss", (2.0, 1.0, 1.0))
+            assert torch.equal(a, b)
