@@ -29,7 +29,19 @@ constexpr int kMaxLineYZ = 2560;
 struct LiftGeom {
     long nx, ny;      // cube strides
     long bx, by, bz;  // current box
+    // denoiser only, on the first inverse pass of level 1: a coefficient
+    // outside the box [0, ax) x [0, ay) x [0, az) (a detail of level 1, not
+    // touched since the forward transform) is set to 0 as it is loaded when
+    // |c| < athr, the threshold pass's rule for that level
+    long ax, ay, az;
+    double athr;
+    int thr_on;
 };
+
+__device__ __forceinline__ float thr_load(float v, long x, long y, long z, const LiftGeom& g) {
+    const bool detail1 = x >= g.ax || y >= g.ay || z >= g.az;
+    return (detail1 && !(fabs((double)v) >= g.athr)) ? 0.0f : v;
+}
 
 // One lifting direction over the LDS line X (element i at X[i * es]), n >= 2;
 // this thread handles elements e0, e0 + step, ...  Ends every step with a
@@ -111,6 +123,9 @@ k_lift_x(const float* __restrict__ src, float* __restrict__ dst, LiftGeom g) {
             const int j = j0 + 64 * u;
             v[u] = (active && j < n) ? src[base + j] : 0.0f;
         }
+        if (!FWD && g.thr_on)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = thr_load(v[u], j0 + 64 * u, y, z, g);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int j = j0 + 64 * u;
@@ -146,6 +161,12 @@ k_lift_yz(const float* __restrict__ src, float* __restrict__ dst, LiftGeom g, in
             const int j = j0 + rows * u;
             v[u] = (active && j < n) ? src[base + j * es] : 0.0f;
         }
+        if (!FWD && g.thr_on)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const long j = j0 + rows * u;
+                v[u] = AXIS == 1 ? thr_load(v[u], x, j, other, g) : thr_load(v[u], x, other, j, g);
+            }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int j = j0 + rows * u;
@@ -280,8 +301,10 @@ ig_status forward_impl(const ig_wavelet_params* p, const float* d_in, float* d_c
     return IG_OK;
 }
 
+// athr >= 0: the denoiser's level-1 detail threshold, applied as the first
+// pass of level 1 loads the coefficients (see LiftGeom)
 ig_status inverse_impl(const ig_wavelet_params* p, const float* d_coef, float* d_out, int64_t nx, int64_t ny,
-                       int64_t nz, hipStream_t s) {
+                       int64_t nz, hipStream_t s, double athr = -1.0) {
     if (d_coef != d_out) {
         hipError_t e = hipMemcpyAsync(d_out, d_coef, (size_t)(nx * ny * nz) * sizeof(float), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return fail(IG_ERR_DEVICE, "copy: %s", hipGetErrorString(e));
@@ -289,11 +312,13 @@ ig_status inverse_impl(const ig_wavelet_params* p, const float* d_coef, float* d
     long sz[IG_WAVELET_MAX_LEVELS + 1][3];
     box_sizes(nx, ny, nz, p->levels, sz);
     for (int l = p->levels - 1; l >= 0; --l) {
-        LiftGeom g{nx, ny, sz[l][0], sz[l][1], sz[l][2]};
+        LiftGeom g{nx, ny, sz[l][0], sz[l][1], sz[l][2], sz[1][0], sz[1][1], sz[1][2], athr, 0};
+        g.thr_on = l == 0 && athr >= 0.0;
         for (int axis = 2; axis >= 0; --axis) {
             if (sz[l][axis] < 2) continue;
             hipError_t e = run_pass<false>(p->kind, axis, d_out, d_out, g, s);
             if (e != hipSuccess) return fail(IG_ERR_DEVICE, "inverse lifting: %s", hipGetErrorString(e));
+            g.thr_on = 0;
         }
     }
     return IG_OK;
@@ -348,10 +373,15 @@ extern "C" ig_status ig_wavelet_denoise(const ig_wavelet_params* p, const float*
     }
     for (int l = 0; l < p->levels; ++l) g.thr[l] = p->t[l] * rms;
     g.thr[p->levels] = p->t[p->levels - 1] * rms;
-    // ny, nz <= kMaxLineYZ and nx <= kMaxLineX keep the grid within its limits
-    hipLaunchKernelGGL(k_wthresh, dim3((unsigned)((nx + 255) / 256), (unsigned)ny, (unsigned)nz), dim3(256), 0, s,
-                       d_out, g);
+    // The threshold pass covers the level-1 approximation box only (the
+    // coefficients of levels 2 and up and the final approximation); the
+    // level-1 details around it are thresholded by the inverse transform's
+    // first level-1 pass as it loads them, so that pass reads the cube once
+    // for both.  ny, nz <= kMaxLineYZ and nx <= kMaxLineX keep the grid within
+    // its limits.
+    hipLaunchKernelGGL(k_wthresh, dim3((unsigned)((sz[1][0] + 255) / 256), (unsigned)sz[1][1], (unsigned)sz[1][2]),
+                       dim3(256), 0, s, d_out, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(IG_ERR_DEVICE, "threshold: %s", hipGetErrorString(e));
-    return inverse_impl(p, d_out, d_out, nx, ny, nz, s);
+    return inverse_impl(p, d_out, d_out, nx, ny, nz, s, g.thr[0]);
 }

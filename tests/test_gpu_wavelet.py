@@ -93,3 +93,20 @@ def test_fullsize_round_trip_and_paper_pipeline(dev):
     torch.cuda.synchronize()
     assert torch.equal(y, y_ref)
     assert float((y == 0).float().mean()) >= 0.5
+
+
+@pytest.mark.parametrize("shape", [(13, 9, 21), (1, 37, 50), (1, 1, 77), (6, 1, 5), (2, 2, 2)])
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_denoise_levels_and_thin_cubes_bitwise(dev, shape, levels):
+    """Odd sizes and axes of length 1 (the first level-1 inverse pass then runs
+    along y or x), 1-3 levels: every threshold decision and reconstruction as
+    the FP32 oracle's."""
+    import torch
+    import paper_1609_03782_amd as ig
+    cube = igsynth.random_cube(shape, seed=sum(shape) + levels)
+    t = (0.4, 0.9, 1.2)[:levels]
+    for name, kind in KINDS:
+        rms = Wv.plain_rms(cube)
+        y, _ = ig.wavelet_denoise(torch.from_numpy(cube).to(dev), name, levels, t, rms=rms)
+        ref = Wv.denoise(cube, kind, levels, t, rms=rms, dtype=np.float32)
+        assert np.array_equal(y.cpu().numpy(), ref), (name, shape, levels)
