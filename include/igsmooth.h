@@ -48,7 +48,8 @@ typedef struct {
 } ig_smooth_params;
 
 /* Kernel half-widths (r_x, r_y, r_z) that s implies, and whether it runs as
- * three separable passes (1) or one dense pass (0).  Host only. */
+ * separable 1-D sums (1: the fused pass or three passes) or one dense pass
+ * (0).  Host only. */
 ig_status ig_smooth_geometry(const ig_smooth_params* s, int32_t* radius, int32_t* separable);
 
 /* Smooth d_in (FP32, nx*ny*nz voxels, x fastest) into d_out on hip_stream;

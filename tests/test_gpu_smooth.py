@@ -1,5 +1,5 @@
 """GPU machine / Gaussian smoothing (ig_smooth) against the FP64 oracle: ragged
-cubes, kernels larger than the cube, axis-aligned (three separable passes) and
+cubes, kernels larger than the cube, axis-aligned (separable: the fused pass and three passes) and
 rotated (dense) Gaussians, and sampled voxels of the 512^3 cube."""
 import numpy as np
 import pytest
