@@ -115,13 +115,16 @@ k_lift_x(const float* __restrict__ src, float* __restrict__ dst, LiftGeom g) {
     const long y = active ? L % g.by : 0, z = active ? L / g.by : 0;
     const long base = g.nx * (y + g.ny * z);
     float* line = X + ty * n;
-    // loads in groups of 8, each group in flight together before its LDS writes
+    // loads in groups of 8, each group in flight together before its LDS
+    // writes: every lane loads, at an index clamped into the line (a lane past
+    // the line or the box does not write the value), since loads under a
+    // branch made the compiler wait for each pair before issuing the next
     for (int j0 = tx; j0 < n; j0 += 64 * 8) {
         float v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int j = j0 + 64 * u;
-            v[u] = (active && j < n) ? src[base + j] : 0.0f;
+            v[u] = src[base + min(j, n - 1)];
         }
         if (!FWD && g.thr_on)
 #pragma unroll
@@ -152,14 +155,18 @@ k_lift_yz(const float* __restrict__ src, float* __restrict__ dst, LiftGeom g, in
     const long other = blockIdx.y;   // z for lines along y, y for lines along z
     const long es = AXIS == 1 ? g.nx : g.nx * g.ny;
     const long base = x + (AXIS == 1 ? other * g.nx * g.ny : other * g.nx);
+    const long basec = base - x + (active ? x : g.bx - 1);   // an in-box column for lanes past the box
     float* col = X + tx;
-    // loads in groups of 8, each group in flight together before its LDS writes
+    // loads in groups of 8, each group in flight together before its LDS
+    // writes: every lane loads, at indices clamped into the box (a lane past
+    // the line or the box does not write the value), since loads under a
+    // branch made the compiler wait for each pair before issuing the next
     for (int j0 = ty; j0 < n; j0 += rows * 8) {
         float v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int j = j0 + rows * u;
-            v[u] = (active && j < n) ? src[base + j * es] : 0.0f;
+            v[u] = src[basec + (long)min(j, n - 1) * es];
         }
         if (!FWD && g.thr_on)
 #pragma unroll
