@@ -70,8 +70,11 @@ k_quality_vox(const float* __restrict__ orig, const float* __restrict__ filt, co
     const double thr_o = g.thr[63];
     // workgroup b takes a contiguous range of ROI rows (sequential memory),
     // (y, z) carried from row to row; within a row, thread t takes voxels
-    // t, t + kQSeg, ... (kQUnroll loads in flight)
+    // t, t + kQSeg, ... (kQUnroll loads of each cube in flight: every lane
+    // loads, at x clamped into the row, and lanes past the row skip the sums;
+    // loads under a branch made the compiler wait for each one in turn)
     constexpr int kQUnroll = 4;
+    const float* mp = g.has_model ? model : orig;   // any readable cube when there is no model
     const long per = (g.nrows + gridDim.x - 1) / gridDim.x;
     const long r0 = (long)blockIdx.x * per, r1 = min(g.nrows, r0 + per);
     long y = r0 % g.ry, z = r0 / g.ry;
@@ -83,15 +86,16 @@ k_quality_vox(const float* __restrict__ orig, const float* __restrict__ filt, co
 #pragma unroll
             for (int u = 0; u < kQUnroll; ++u) {
                 const long x = x0 + u * kQSeg + threadIdx.x;
+                const long xc = min(x, g.rx - 1);
                 in[u] = x < g.rx;
-                fo[u] = in[u] ? orig[base + x] : 0.0f;
-                ff[u] = in[u] ? filt[base + x] : 0.0f;
-                fm[u] = (in[u] && g.has_model) ? model[base + x] : 0.0f;
+                fo[u] = orig[base + xc];
+                ff[u] = filt[base + xc];
+                fm[u] = mp[base + xc];
             }
 #pragma unroll
             for (int u = 0; u < kQUnroll; ++u) {
                 if (!in[u]) continue;
-                const double o = (double)fo[u], f = (double)ff[u], m = (double)fm[u];
+                const double o = (double)fo[u], f = (double)ff[u], m = g.has_model ? (double)fm[u] : 0.0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const bool p = f >= thr[k];
