@@ -64,12 +64,25 @@ k_batch_sum(const BatchCube* __restrict__ cubes, const SumChunk* __restrict__ ch
     const SumChunk ch = chunks[blockIdx.x];
     const float* x = from_out ? cubes[ch.cube].out : cubes[ch.cube].in;
     double s1 = 0.0, s2 = 0.0, bad = 0.0;
-    for (long i = threadIdx.x; i < ch.len; i += 256) {
-        const float f = x[ch.off + i];
-        if (!isfinite(f)) { bad += 1.0; continue; }
+    auto add = [&](float f) {
+        if (!isfinite(f)) {
+            bad += 1.0;
+            return;
+        }
         s1 += (double)f;
         s2 += (double)f * (double)f;
+    };
+    // groups of 8 loads in flight together, summed in the same order as one
+    // at a time
+    long i = threadIdx.x;
+    for (; i + 7 * 256 < ch.len; i += 8 * 256) {
+        float f[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) f[u] = x[ch.off + i + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) add(f[u]);
     }
+    for (; i < ch.len; i += 256) add(x[ch.off + i]);
     __shared__ double sh[3][4];
     for (int o = 32; o > 0; o >>= 1) {
         s1 += __shfl_xor(s1, o, 64);
