@@ -49,7 +49,7 @@ typedef enum {
     IG_ERR_INVALID_ARG = 1,    /* bad size, parameter, enum, pointer or overlap */
     IG_ERR_OUT_OF_MEMORY = 2,  /* device allocation failed */
     IG_ERR_DEVICE = 3,         /* a HIP call failed */
-    IG_ERR_NONFINITE = 4,      /* the input holds NaN or Inf; output untouched */
+    IG_ERR_NONFINITE = 4,      /* the input holds NaN or Inf; the output is set to NaN */
     IG_ERR_UNSUPPORTED = 5     /* valid request this build cannot serve */
 } ig_status;
 
@@ -133,9 +133,12 @@ ig_status ig_filter_create(const ig_params* p, int device, ig_filter** out);
  * is allowed (2 cubes of device memory in total, the paper's two-buffer GPU
  * model of Section 5); any other overlap is IG_ERR_INVALID_ARG.  d_in is not
  * modified unless it equals d_out.  If stats != NULL the call waits for the
- * stream and fills it.  A non-finite input voxel leaves d_out untouched; it is
- * reported as IG_ERR_NONFINITE when stats != NULL (the scan runs whenever the
- * rms is estimated or stats are requested). */
+ * stream and fills it.  The scan of the input runs whenever the rms is
+ * estimated or stats are requested; if it finds a NaN or Inf voxel, no step
+ * runs and every voxel of d_out is set to NaN (in place, the input is
+ * overwritten), and with stats != NULL the call returns IG_ERR_NONFINITE.
+ * (With rms given and no stats there is no scan: a non-finite voxel then
+ * spreads through the steps as IEEE arithmetic carries it.) */
 ig_status ig_filter_run(ig_filter* f, const void* d_in, void* d_out, void* hip_stream,
                         ig_stats* stats);
 
@@ -201,25 +204,35 @@ typedef struct {
  * graph launch (all items: FP32 storage, same device).  The graph holds the
  * per-cube noise-level scans, one launch for the LDS-resident cubes (below)
  * and one kernel launch per pass round (round r: pass r of every other cube
- * that has one); it is built once per batch signature (item shapes,
- * parameters, buffer addresses and the batch settings), with its work
- * descriptors uploaded at that time, and replayed on later calls with the
- * same signature.  Scratch cubes for the ping-pong are owned by that cached
- * plan (ig_batch_cache_clear frees them).  A cube of at most the resident
- * limit of voxels (ig_batch_set_resident; default 32768, 128 KiB) with
- * n_iter > 0 runs LDS-resident: one workgroup loads it into LDS, runs all
- * n_iter steps there and writes the result, bitwise what the passes give;
- * its stats report passes = 1, schedule.t_block = n_iter and schedule.waves
- * = the wavefronts of its workgroup (sized to the cube: 1 to 16).  per_item
- * (nullable, `count` entries) receives each item's stats; latency_ms
+ * that has one).  It is built once per batch signature (item shapes and
+ * parameters, whether each item runs in place, the buffers' alignment within
+ * 16 bytes, and the batch settings) and replayed on later calls with the same
+ * signature; a call with other buffers of the same signature rewrites the
+ * plan's table of buffer addresses (an asynchronous copy on the stream, after
+ * the plan's previous launch has finished) before the launch.  At most 8
+ * plans are cached; building a ninth drops the least recently used one (after
+ * its last launch has finished).  Scratch cubes for the ping-pong are owned by
+ * the cached plan (ig_batch_cache_clear frees them).  A cube of at most the
+ * resident limit of voxels (ig_batch_set_resident; default 32768, 128 KiB)
+ * with n_iter > 0 runs LDS-resident: one workgroup loads it into LDS, runs all
+ * n_iter steps there and writes the result, bitwise what the passes give; its
+ * stats report passes = 1, schedule.t_block = n_iter and schedule.waves = the
+ * wavefronts of its workgroup (sized to the cube: 1 to 16).  An item whose
+ * input holds NaN or Inf runs no step and its output is set to NaN; the call
+ * then returns IG_ERR_NONFINITE if it waits (per_item or latency_ms given).
+ * per_item (nullable, `count` entries) receives each item's stats; latency_ms
  * (nullable, `count` entries) receives each cube's completion time measured
  * on the GPU clock from the start of the launch.  Either makes the call wait
  * for the stream. */
 ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
                           ig_stats* per_item, double* latency_ms);
 
-/* Free every cached batch plan (graphs and scratch) on every device. */
+/* Free every cached batch plan (graphs and scratch) on every device, after
+ * each plan's last launch has finished. */
 void ig_batch_cache_clear(void);
+
+/* Number of batch plans cached (at most 8). */
+int32_t ig_batch_cache_size(void);
 
 /* Schedule of later ig_filter_batch plans: steps per pass t_block (1..4; 0 =
  * library default), wavefronts per workgroup (1..16, > 2 t_block) and planes

@@ -106,6 +106,7 @@ SIGNATURES = {
     "ig_filter_batch": (ctypes.c_int, [ctypes.POINTER(IgBatchItem), ctypes.c_int32, ctypes.c_int, _P,
                                        ctypes.POINTER(IgStats), ctypes.POINTER(ctypes.c_double)]),
     "ig_batch_cache_clear": (None, []),
+    "ig_batch_cache_size": (ctypes.c_int32, []),
     "ig_batch_set_schedule": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "ig_batch_set_resident": (ctypes.c_int, [ctypes.c_int32]),
     "ig_batch_get_resident": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32)]),
@@ -411,6 +412,10 @@ def batch_autotune(items, device=0):
 
 def batch_cache_clear():
     lib().ig_batch_cache_clear()
+
+
+def batch_cache_size():
+    return int(lib().ig_batch_cache_size())
 
 
 def batch_set_schedule(t_block=0, waves=16, zchunk=32):

@@ -266,7 +266,7 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
 }
 
 // Heuristic schedule when no tuned entry exists.
-static ig_schedule auto_schedule(const ig_params* p) {
+ig_schedule igk_auto_schedule(const ig_params* p) {
     ig_schedule s{};
     s.kind = IG_SCHED_BLOCKED;
     auto_vec_rows(p->nx, &s.vec, &s.rows);
@@ -305,7 +305,7 @@ struct ig_filter {
     size_t ev_used = 0;          // events recorded since the last reset
 };
 
-// Timing hooks used by enqueue_run (null when timing is off).
+// Timing hook of igk_enqueue_run (unused when timing is off).
 struct TimingHook {
     ig_filter* f;
     hipStream_t s;
@@ -376,7 +376,7 @@ extern "C" void ig_filter_destroy(ig_filter* f) {
 }
 
 static ig_schedule resolve_schedule(const ig_filter* f) {
-    if (f->sched.kind == IG_SCHED_AUTO) return auto_schedule(&f->p);
+    if (f->sched.kind == IG_SCHED_AUTO) return igk_auto_schedule(&f->p);
     ig_schedule s = f->sched;
     if (s.kind == IG_SCHED_BLOCKED) {
         if (s.vec == 0) {
@@ -483,10 +483,18 @@ static ig_status get_plan(ig_filter* f, const ig_schedule& sched, int T, const P
     return IG_OK;
 }
 
-// Enqueue the whole filter: parameters (+ scan), then the passes.
-static ig_status enqueue_run(ig_filter* f, const ig_schedule& sched, const void* d_in, void* d_out, bool scan,
-                             hipStream_t stream, int* passes_out, TimingHook* hook) {
-    const ig_params& p = f->p;
+static ig_status handle_plan(void* self, const ig_schedule& sched, int T, const PassPlan** out, const Piece** dev) {
+    return get_plan(static_cast<ig_filter*>(self), sched, T, out, dev);
+}
+
+static hipError_t hook_record(void* self, hipStream_t s) { return static_cast<TimingHook*>(self)->record(); }
+
+// Enqueue the whole filter: parameters (+ scan), then the passes, then (when
+// the scan ran) the kernel that turns the output into NaN if the input held a
+// non-finite voxel.
+ig_status igk_enqueue_run(const RunCtx& c, const ig_schedule& sched, const void* d_in, void* d_out, bool scan,
+                          hipStream_t stream, int* passes_out) {
+    const ig_params& p = *c.p;
     const long n = (long)(p.nx * p.ny * p.nz);
     ParamIn in{};
     in.K = p.K; in.tau = p.tau;
@@ -495,13 +503,14 @@ static ig_status enqueue_run(ig_filter* f, const ig_schedule& sched, const void*
     in.abort_on_nonfinite = 1;
     in.rms = p.rms;
     if (scan) {
-        HIP_TRY(launch_sum_partial(p.dtype, d_in, n, f->parts, kPartBlocks, stream));
-        HIP_TRY(launch_params_final(f->parts, kPartBlocks, n, in, f->dparams, stream));
+        HIP_TRY(launch_sum_partial(p.dtype, d_in, n, c.parts, kPartBlocks, stream));
+        HIP_TRY(launch_params_final(c.parts, kPartBlocks, n, in, c.dparams, stream));
     } else {
-        HIP_TRY(launch_params_final(nullptr, 0, n, in, f->dparams, stream));
+        HIP_TRY(launch_params_final(nullptr, 0, n, in, c.dparams, stream));
     }
     const StencilLaunch* L = stencil_table(p.cond, p.dtype);
     if (!L) return fail(IG_ERR_UNSUPPORTED, "no kernels for cond %d dtype %d", p.cond, p.dtype);
+    auto record = [&]() -> hipError_t { return c.hook ? c.hook(c.hook_self, stream) : hipSuccess; };
 
     // pass depths
     std::vector<int> depths;
@@ -511,53 +520,87 @@ static ig_status enqueue_run(ig_filter* f, const ig_schedule& sched, const void*
         depths.assign(full, T);
         if (rem) depths.push_back(rem);
     }
-    void* scratch = f->scratch;
+    void* scratch = c.scratch;
     const void* src = d_in;
+    int P = 0;
     if (depths.empty()) {
-        if (d_in != d_out) HIP_TRY(launch_copy(p.dtype, d_in, d_out, n, f->dparams, stream));
-        if (passes_out) *passes_out = 0;
-        return IG_OK;
-    }
-    // pass k (1-based) of P writes d_out if (P - k) is even, else scratch, so
-    // the last pass writes d_out.  In place, pass 1 must not write d_in.
-    if (d_in == d_out && depths.size() % 2 == 1) {
-        int k = -1;
-        for (size_t j = 0; j < depths.size(); ++j)
-            if (depths[j] >= 2) { k = (int)j; break; }
-        if (k >= 0) {   // split one pass in two: results do not depend on the split
-            const int d = depths[k];
-            depths[k] = d / 2;
-            depths.insert(depths.begin() + k + 1, d - d / 2);
-        } else {        // all passes are single steps: stage the input through scratch
-            HIP_TRY(launch_copy(p.dtype, d_in, scratch, n, f->dparams, stream));
-            src = scratch;
+        if (d_in != d_out) HIP_TRY(launch_copy(p.dtype, d_in, d_out, n, c.dparams, stream));
+    } else {
+        // pass k (1-based) of P writes d_out if (P - k) is even, else scratch,
+        // so the last pass writes d_out.  In place, pass 1 must not write d_in.
+        if (d_in == d_out && depths.size() % 2 == 1) {
+            int k = -1;
+            for (size_t j = 0; j < depths.size(); ++j)
+                if (depths[j] >= 2) { k = (int)j; break; }
+            if (k >= 0) {   // split one pass in two: results do not depend on the split
+                const int d = depths[k];
+                depths[k] = d / 2;
+                depths.insert(depths.begin() + k + 1, d - d / 2);
+            } else {        // all passes are single steps: stage the input through scratch
+                HIP_TRY(launch_copy(p.dtype, d_in, scratch, n, c.dparams, stream));
+                src = scratch;
+            }
+        }
+        P = (int)depths.size();
+        for (int k = 1; k <= P; ++k) {
+            void* dst = ((P - k) % 2 == 0) ? d_out : scratch;
+            const int D = depths[k - 1];
+            hipError_t e;
+            if (sched.kind == IG_SCHED_NAIVE) {
+                HIP_TRY(record());
+                e = L->naive(src, dst, (int)p.nx, (int)p.ny, (int)p.nz, c.dparams, stream);
+            } else {
+                const PassPlan* pp;
+                const Piece* dev;
+                ig_status st = c.plan(c.plan_self, sched, D, &pp, &dev);
+                if (st != IG_OK) return st;
+                BlockGeom g = pp->g;
+                // vector I/O also needs both buffers aligned to a lane chunk
+                const size_t al = (size_t)pp->V * dtype_size(p.dtype);
+                if (((uintptr_t)src % al) || ((uintptr_t)dst % al)) g.vec = 0;
+                HIP_TRY(record());
+                e = L->blocked(src, dst, g, pp->V, D, dev, (int)pp->pieces.size(), c.dparams, stream);
+            }
+            if (e != hipSuccess) return fail(IG_ERR_DEVICE, "stencil launch: %s", hipGetErrorString(e));
+            HIP_TRY(record());
+            src = dst;
         }
     }
-    const int P = (int)depths.size();
-    for (int k = 1; k <= P; ++k) {
-        void* dst = ((P - k) % 2 == 0) ? d_out : scratch;
-        const int D = depths[k - 1];
-        hipError_t e;
-        if (sched.kind == IG_SCHED_NAIVE) {
-            if (hook) HIP_TRY(hook->record());
-            e = L->naive(src, dst, (int)p.nx, (int)p.ny, (int)p.nz, f->dparams, stream);
-        } else {
-            const PassPlan* pp;
-            const Piece* dev;
-            ig_status st = get_plan(f, sched, D, &pp, &dev);
-            if (st != IG_OK) return st;
-            BlockGeom g = pp->g;
-            // vector I/O also needs both buffers aligned to a lane chunk
-            const size_t al = (size_t)pp->V * dtype_size(p.dtype);
-            if (((uintptr_t)src % al) || ((uintptr_t)dst % al)) g.vec = 0;
-            if (hook) HIP_TRY(hook->record());
-            e = L->blocked(src, dst, g, pp->V, D, dev, (int)pp->pieces.size(), f->dparams, stream);
-        }
-        if (e != hipSuccess) return fail(IG_ERR_DEVICE, "stencil launch: %s", hipGetErrorString(e));
-        if (hook) HIP_TRY(hook->record());
-        src = dst;
-    }
+    // a non-finite input voxel (found by the scan) turns the whole output into
+    // NaN, so a caller that asked for no statistics still sees the failure
+    if (scan) HIP_TRY(launch_nan_if_abort(p.dtype, d_out, n, c.dparams, stream));
     if (passes_out) *passes_out = P;
+    return IG_OK;
+}
+
+// Statistics of a finished run (waits for the stream): rho, the sums, the
+// non-finite count; IG_ERR_NONFINITE if the input held NaN or Inf.
+ig_status igk_finish_stats(const RunCtx& c, const ig_schedule& sched, int passes, const void* d_out,
+                           hipStream_t s, ig_stats* stats) {
+    const ig_params& p = *c.p;
+    DevParams hp;
+    HIP_TRY(hipMemcpyAsync(&hp, c.dparams, sizeof hp, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stats->passes = passes;
+    stats->rms_used = hp.rho;
+    stats->sum_in = hp.sum;
+    stats->nonfinite = hp.nonfinite;
+    stats->monotone = (2.0 * (double)p.tau * ((double)p.C[0] + p.C[1] + p.C[2]) <= 1.0) ? 1 : 0;
+    stats->schedule = sched;
+    stats->sum_out = 0.0;
+    if (hp.abort) return fail(IG_ERR_NONFINITE, "input holds %lld non-finite voxels", (long long)hp.nonfinite);
+    const long n = (long)(p.nx * p.ny * p.nz);
+    HIP_TRY(launch_sum_partial(p.dtype, d_out, n, c.parts, kPartBlocks, s));
+    ParamIn dummy{};
+    dummy.K = 1.0f; dummy.rms = 1.0; dummy.cond = p.cond;
+    // fold the output partials with the same fixed-order kernel, into a scratch DevParams slot
+    DevParams* tmp = reinterpret_cast<DevParams*>(c.results);
+    static_assert(sizeof(DevParams) <= 8 * sizeof(double), "results buffer too small");
+    HIP_TRY(launch_params_final(c.parts, kPartBlocks, n, dummy, tmp, s));
+    DevParams ho;
+    HIP_TRY(hipMemcpyAsync(&ho, tmp, sizeof ho, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    stats->sum_out = ho.sum;
     return IG_OK;
 }
 
@@ -619,34 +662,12 @@ extern "C" ig_status ig_filter_run(ig_filter* f, const void* d_in, void* d_out, 
     const bool scan = p.rms <= 0.0 || stats != nullptr;
     int passes = 0;
     TimingHook hook{f, s};
-    ig_status st = enqueue_run(f, sched, d_in, d_out, scan, s, &passes, f->timing ? &hook : nullptr);
+    RunCtx c{&f->p, f->scratch, f->dparams, f->parts, f->results, handle_plan, f,
+             f->timing ? hook_record : nullptr, &hook};
+    ig_status st = igk_enqueue_run(c, sched, d_in, d_out, scan, s, &passes);
     if (st != IG_OK) return st;
     if (!stats) return IG_OK;
-
-    DevParams hp;
-    HIP_TRY(hipMemcpyAsync(&hp, f->dparams, sizeof hp, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    stats->passes = passes;
-    stats->rms_used = hp.rho;
-    stats->sum_in = hp.sum;
-    stats->nonfinite = hp.nonfinite;
-    stats->monotone = (2.0 * (double)p.tau * ((double)p.C[0] + p.C[1] + p.C[2]) <= 1.0) ? 1 : 0;
-    stats->schedule = sched;
-    stats->sum_out = 0.0;
-    if (hp.abort) return fail(IG_ERR_NONFINITE, "input holds %lld non-finite voxels", (long long)hp.nonfinite);
-    const long n = (long)(p.nx * p.ny * p.nz);
-    HIP_TRY(launch_sum_partial(p.dtype, d_out, n, f->parts, kPartBlocks, s));
-    ParamIn dummy{};
-    dummy.K = 1.0f; dummy.rms = 1.0; dummy.cond = p.cond;
-    // fold the output partials with the same fixed-order kernel, into a scratch DevParams slot
-    DevParams* tmp = reinterpret_cast<DevParams*>(f->results);
-    static_assert(sizeof(DevParams) <= 8 * sizeof(double), "results buffer too small");
-    HIP_TRY(launch_params_final(f->parts, kPartBlocks, n, dummy, tmp, s));
-    DevParams ho;
-    HIP_TRY(hipMemcpyAsync(&ho, tmp, sizeof ho, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    stats->sum_out = ho.sum;
-    return IG_OK;
+    return igk_finish_stats(c, sched, passes, d_out, s, stats);
 }
 
 extern "C" ig_status ig_filter_set_timing(ig_filter* f, int enable) {

@@ -156,6 +156,17 @@ k_batch_stage(const BatchCube* __restrict__ cubes, const SumChunk* __restrict__ 
     for (long i = threadIdx.x; i < ch.len; i += 256) to[ch.off + i] = cb.in[ch.off + i];
 }
 
+// A cube whose input held NaN or Inf ran no step: its output becomes NaN, so
+// the failure is visible without the statistics.  A no-op for other cubes.
+__global__ void __launch_bounds__(256)
+k_batch_nan(const BatchCube* __restrict__ cubes, const SumChunk* __restrict__ chunks, const DevParams* __restrict__ prm) {
+    const SumChunk ch = chunks[blockIdx.x];
+    if (!prm[ch.cube].abort) return;
+    float* out = cubes[ch.cube].out;
+    const float q = __builtin_nanf("");
+    for (long i = threadIdx.x; i < ch.len; i += 256) out[ch.off + i] = q;
+}
+
 // Batch cubes have nx <= 256, so the automatic layout is 4 voxels per lane
 // with 1, 2 or 4 rows per wavefront, or 1 or 2 voxels per lane when nx < 4.
 template <int COND, int T, int D>
@@ -387,15 +398,32 @@ struct BatchPlan {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // the descriptor table as last uploaded (pinned, so the upload of a later
+    // call's buffer addresses is a plain asynchronous copy) and its addresses
+    BatchCube* h_cubes = nullptr;
+    std::vector<std::pair<const void*, void*>> bufs;
+    hipEvent_t done = nullptr;    // recorded after every launch of the graph
+    uint64_t last_use = 0;        // for least-recently-used eviction
     ~BatchPlan() {
+        if (done) {   // the graph may still run on the caller's stream
+            (void)hipEventSynchronize(done);
+            (void)hipEventDestroy(done);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
+        if (h_cubes) (void)hipHostFree(h_cubes);
     }
 };
 
 std::mutex g_mu;
+// Plans keyed by shapes, parameters and settings (not buffer addresses): a
+// call with other tensors of the same shapes reuses the plan and rewrites its
+// descriptor table.  At most kMaxPlans are kept; the least recently used one
+// is dropped (after its last launch has finished) to make room.
+constexpr size_t kMaxPlans = 8;
 std::map<std::vector<uint64_t>, std::unique_ptr<BatchPlan>> g_cache;
+uint64_t g_use = 0;
 // The last call's items (validated) and plan: a call with byte-identical items
 // and the same settings reuses it without validating or hashing again.
 struct LastCall {
@@ -421,10 +449,32 @@ std::vector<uint64_t> signature(const ig_batch_item* items, int count, int devic
         uint64_t w[(sizeof(ig_params) + 7) / 8] = {};
         std::memcpy(w, &items[i].p, sizeof(ig_params));
         for (uint64_t v : w) key.push_back(v);
-        key.push_back((uint64_t)(uintptr_t)items[i].d_in);
-        key.push_back((uint64_t)(uintptr_t)items[i].d_out);
+        // what the plan depends on besides shapes: in place or not (staging)
+        // and the buffers' alignment within 16 bytes (vector access)
+        const uintptr_t a = (uintptr_t)items[i].d_in, b = (uintptr_t)items[i].d_out;
+        key.push_back((uint64_t)((a % 16) << 8 | (b % 16) << 1 | (a == b ? 1 : 0)));
     }
     return key;
+}
+
+// Point the plan's descriptor table at this call's buffers (same shapes,
+// alignment and in-place pattern as when it was built).  Enqueued on the
+// caller's stream before the graph launch; the pinned table is rewritten only
+// once the previous launch of the plan (and so its upload) has finished.
+ig_status rebind(BatchPlan* bp, const ig_batch_item* items, int count, hipStream_t s) {
+    bool same = (int)bp->bufs.size() == count;
+    for (int c = 0; same && c < count; ++c)
+        same = bp->bufs[c].first == items[c].d_in && bp->bufs[c].second == items[c].d_out;
+    if (same) return IG_OK;
+    HIP_TRY(hipEventSynchronize(bp->done));
+    bp->bufs.resize(count);
+    for (int c = 0; c < count; ++c) {
+        bp->h_cubes[c].in = (const float*)items[c].d_in;
+        bp->h_cubes[c].out = (float*)items[c].d_out;
+        bp->bufs[c] = {items[c].d_in, items[c].d_out};
+    }
+    HIP_TRY(hipMemcpyAsync(bp->d_cubes.p, bp->h_cubes, count * sizeof(BatchCube), hipMemcpyHostToDevice, s));
+    return IG_OK;
 }
 
 ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPlan* bp) {
@@ -579,6 +629,11 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         HIP_TRY(hipMemcpy(bp->d_res.p, res_all.data(), res_all.size() * sizeof(int), hipMemcpyHostToDevice));
     // descriptor tables: fixed for the plan's signature, uploaded once
     HIP_TRY(hipMemcpy(bp->d_cubes.p, cubes.data(), count * sizeof(BatchCube), hipMemcpyHostToDevice));
+    HIP_TRY(hipHostMalloc((void**)&bp->h_cubes, count * sizeof(BatchCube), hipHostMallocDefault));
+    std::memcpy(bp->h_cubes, cubes.data(), count * sizeof(BatchCube));
+    bp->bufs.resize(count);
+    for (int c = 0; c < count; ++c) bp->bufs[c] = {items[c].d_in, items[c].d_out};
+    HIP_TRY(hipEventCreateWithFlags(&bp->done, hipEventDisableTiming));
     if (!its.empty())
         HIP_TRY(hipMemcpy(bp->d_items.p, its.data(), its.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
     if (!pieces.empty())
@@ -631,6 +686,11 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         if (n <= 0) continue;
         hipLaunchKernelGGL(kern, dim3(n), dim3(64, W), lds, s, bp->d_cubes.p, bp->d_items.p + bp->round_off[r],
                            bp->d_pieces.p, bp->d_params.p, bp->d_ctr.p, bp->d_stamps.p);
+        chk(hipGetLastError());
+    }
+    if (bp->nchunks > 0) {
+        hipLaunchKernelGGL(k_batch_nan, dim3(bp->nchunks), dim3(256), 0, s, bp->d_cubes.p, bp->d_chunks.p,
+                           bp->d_params.p);
         chk(hipGetLastError());
     }
     hipGraph_t g = nullptr;
@@ -697,10 +757,18 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
     if (hipSetDevice(device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice(%d)", device);
     struct Restore { int d; ~Restore() { if (d >= 0) (void)hipSetDevice(d); } } restore{prev};
 
+    hipStream_t s = (hipStream_t)hip_stream;
     if (!bp) {
         auto key = signature(items, count, device);
         auto it = g_cache.find(key);
         if (it == g_cache.end()) {
+            while (g_cache.size() >= kMaxPlans) {   // drop the least recently used plan
+                auto lru = g_cache.begin();
+                for (auto j = g_cache.begin(); j != g_cache.end(); ++j)
+                    if (j->second->last_use < lru->second->last_use) lru = j;
+                if (g_last.plan == lru->second.get()) g_last = LastCall{};
+                g_cache.erase(lru);
+            }
             auto plan = std::make_unique<BatchPlan>();
             ig_status st = build_plan(items, count, device, plan.get());
             if (st != IG_OK) return st;
@@ -708,14 +776,17 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
             g_cache[key] = std::move(plan);
         } else {
             bp = it->second.get();
+            ig_status st = rebind(bp, items, count, s);
+            if (st != IG_OK) return st;
         }
         g_last.items.assign(items, items + count);
         g_last.device = device;
         g_last.T = g_batch_T; g_last.W = g_batch_W; g_last.Z = g_batch_Z; g_last.res = g_batch_res;
         g_last.plan = bp;
     }
-    hipStream_t s = (hipStream_t)hip_stream;
+    bp->last_use = ++g_use;
     HIP_TRY(hipGraphLaunch(bp->exec, s));
+    HIP_TRY(hipEventRecord(bp->done, s));
     if (!per_item && !latency_ms) return IG_OK;
 
     std::vector<unsigned long long> stamps(1 + count);
@@ -753,7 +824,7 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
         }
         if (prm[c].abort) bad = true;
     }
-    if (bad) return fail(IG_ERR_NONFINITE, "a batch item holds non-finite voxels (left untouched)");
+    if (bad) return fail(IG_ERR_NONFINITE, "a batch item holds non-finite voxels (its output is set to NaN)");
     return IG_OK;
 }
 
@@ -761,6 +832,11 @@ extern "C" void ig_batch_cache_clear(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_last = LastCall{};
     g_cache.clear();
+}
+
+extern "C" int32_t ig_batch_cache_size(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return (int32_t)g_cache.size();
 }
 
 extern "C" ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count, int device, void* hip_stream,

@@ -37,6 +37,9 @@ hipError_t launch_params_final(const double* part, int nparts, long n, const Par
 hipError_t launch_compare(int dtype, const void* x, const double* ref, long n, double tol, double* part,
                           int nblk, double* out, hipStream_t s);
 hipError_t launch_copy(int dtype, const void* a, void* b, long n, const DevParams* dp, hipStream_t s);
+// Writes NaN over all n elements of x if dp->abort is set; otherwise every
+// workgroup returns at once.
+hipError_t launch_nan_if_abort(int dtype, void* x, long n, const DevParams* dp, hipStream_t s);
 
 // Stencil launchers; one translation unit per (conductance, storage type).
 // V in {1,2,4,8}, T in {1..4}.
@@ -63,6 +66,31 @@ int resident_per_cu(int W, size_t lds);
 // nullptr on success, else the reason schedule s cannot serve p at depth T
 const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp);
 ig_status igk_validate_params(const ig_params* p);
+// The library's schedule for p when the caller sets none.
+ig_schedule igk_auto_schedule(const ig_params* p);
+
+// What one filter run needs besides its input and output: the ping-pong
+// scratch cube, the run's constants, the reduction partials, and the piece
+// table of each pass depth.  A handle provides its own allocations; the
+// no-allocation entry point provides carved-out parts of a static array.
+struct RunCtx {
+    const ig_params* p;
+    void* scratch;               // nx*ny*nz elements of p->dtype
+    igk::DevParams* dparams;
+    double* parts;               // kPartBlocks * 6 doubles
+    double* results;             // 8 doubles
+    // the plan of the pass of depth T and its piece table on the device
+    ig_status (*plan)(void* self, const ig_schedule& s, int T, const PassPlan** out, const igk::Piece** dev);
+    void* plan_self;
+    hipError_t (*hook)(void* self, hipStream_t s);   // timing event before/after each pass (nullable)
+    void* hook_self;
+};
+// Enqueue rho (scan when `scan`), the passes and the NaN-on-abort fill.
+ig_status igk_enqueue_run(const RunCtx& c, const ig_schedule& sched, const void* d_in, void* d_out, bool scan,
+                          hipStream_t stream, int* passes_out);
+// Wait for the stream and fill *stats (second scan of d_out for sum_out).
+ig_status igk_finish_stats(const RunCtx& c, const ig_schedule& sched, int passes, const void* d_out,
+                           hipStream_t s, ig_stats* stats);
 // A buffer a kernel will touch: device (or managed) memory of `device` whose
 // allocation covers [p, p + bytes).  A host pointer or a short allocation is
 // reported as IG_ERR_INVALID_ARG (naming `what`) instead of faulting on the GPU.

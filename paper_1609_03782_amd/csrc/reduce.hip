@@ -223,6 +223,17 @@ k_copy(const ST* __restrict__ src, ST* __restrict__ dst, long n, const DevParams
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+// The failure of a run whose input held NaN or Inf, made visible in its
+// output: every element becomes a quiet NaN.  Otherwise a no-op.
+template <typename ST>
+__global__ void __launch_bounds__(256)
+k_nan_if_abort(ST* __restrict__ x, long n, const DevParams* __restrict__ dp) {
+    if (!dp->abort) return;
+    const ST q = Store<ST>::store(__builtin_nanf(""));
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = q;
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename ST>
 static hipError_t sum_partial_t(const void* x, long n, double* part, int nblk, hipStream_t s) {
@@ -277,6 +288,23 @@ hipError_t launch_copy(int dtype, const void* a, void* b, long n, const DevParam
         case 0: return copy_t<float>(a, b, n, dp, s);
         case 1: return copy_t<__hip_bfloat16>(a, b, n, dp, s);
         default: return copy_t<__half>(a, b, n, dp, s);
+    }
+}
+
+template <typename ST>
+static hipError_t nan_if_abort_t(void* x, long n, const DevParams* dp, hipStream_t s) {
+    int nblk = (int)((n + 255) / 256);
+    if (nblk > 1024) nblk = 1024;
+    if (nblk < 1) nblk = 1;
+    hipLaunchKernelGGL(k_nan_if_abort<ST>, dim3(nblk), dim3(256), 0, s, (ST*)x, n, dp);
+    return hipGetLastError();
+}
+
+hipError_t launch_nan_if_abort(int dtype, void* x, long n, const DevParams* dp, hipStream_t s) {
+    switch (dtype) {
+        case 0: return nan_if_abort_t<float>(x, n, dp, s);
+        case 1: return nan_if_abort_t<__hip_bfloat16>(x, n, dp, s);
+        default: return nan_if_abort_t<__half>(x, n, dp, s);
     }
 }
 

@@ -100,10 +100,15 @@ def test_batch_nonfinite_item(dev):
         ig.batch([(xa, oa, kw), (xb, ob, kw)], want_stats=True)
     assert ei.value.status == ig.IG_ERR_NONFINITE
     torch.cuda.synchronize()
-    assert bool((ob == 3.0).all())
+    assert bool(torch.isnan(ob).all())
     ref = ig.Filter(a.shape, **kw).run(xa)
     torch.cuda.synchronize()
     assert torch.equal(ref, oa)
+    # without statistics the call does not wait; the NaN output carries the failure
+    oa2, ob2 = torch.empty_like(xa), torch.zeros_like(xb)
+    ig.batch([(xa, oa2, kw), (xb, ob2, kw)])
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(ob2).all()) and torch.equal(oa2, ref)
     ig.batch_cache_clear()
 
 
@@ -234,3 +239,40 @@ def test_batch_changed_parameters_or_settings_rebuild(dev):
         ig.batch_set_resident(32768)
         ig.batch_set_schedule(0, 16, 32)
         ig.batch_cache_clear()
+
+
+def test_batch_fresh_buffers_reuse_plan_and_cache_stays_bounded(dev):
+    """A serving loop that hands in new output (and input) tensors on every
+    call reuses the plan of that shape signature, with its buffer table
+    rewritten; results stay bitwise those of single-cube runs, and the cache
+    never holds more than 8 plans however many signatures pass through."""
+    import torch
+    import paper_1609_03782_amd as ig
+    ig.batch_cache_clear()
+    shapes = [(10, 21, 33), (24, 40, 72)]
+    kw = dict(K=2.0, tau=1 / 16, n_iter=5)
+    cubes = [igsynth.random_cube(s, seed=700 + k, scale=1.5) for k, s in enumerate(shapes)]
+    refs = [ig.Filter(c.shape, **kw).run(torch.from_numpy(c).to(dev)) for c in cubes]
+    torch.cuda.synchronize()
+    keep = []
+    for call in range(6):
+        xs = [torch.from_numpy(c).to(dev) for c in cubes]     # fresh input and output tensors
+        outs = [torch.full_like(x, float(call)) for x in xs]
+        keep.append((xs, outs))                                # distinct addresses every call
+        ig.batch([(x, o, kw) for x, o in zip(xs, outs)])
+        assert ig.batch_cache_size() == 1
+    torch.cuda.synchronize()
+    for xs, outs in keep:
+        for o, r in zip(outs, refs):
+            assert torch.equal(o, r)
+    # eleven signatures (n_iter 1..11) through an 8-plan cache
+    ig.batch_cache_clear()
+    x = torch.from_numpy(cubes[0]).to(dev)
+    for n in range(1, 12):
+        o = torch.empty_like(x)
+        ig.batch([(x, o, dict(K=2.0, tau=1 / 16, n_iter=n))])
+        assert ig.batch_cache_size() == min(n, 8)
+        torch.cuda.synchronize()
+        assert torch.equal(o, ig.Filter(tuple(x.shape), K=2.0, tau=1 / 16, n_iter=n).run(x)), n
+    ig.batch_cache_clear()
+    assert ig.batch_cache_size() == 0

@@ -198,7 +198,24 @@ def test_nonfinite_input_rejected(dev):
         f.run(x, out=out, stats=True)
     assert ei.value.status == ig.IG_ERR_NONFINITE
     torch.cuda.synchronize()
-    assert bool((out == 7.0).all())     # untouched
+    assert bool(torch.isnan(out).all())   # no step ran; the output says so
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+def test_nonfinite_input_visible_without_stats(dev, in_place):
+    """With rho estimated and no statistics the call returns at once, so the
+    failure shows in the output: every voxel NaN, out of place or in place."""
+    import torch
+    import paper_1609_03782_amd as ig
+    cube = igsynth.random_cube((12, 17, 70), seed=14)
+    cube[5, 6, 7] = np.inf
+    x = _gpu(cube, dev)
+    out = x if in_place else torch.zeros_like(x)
+    y = ig.Filter(cube.shape, n_iter=4 if in_place else 3).run(x, out=out)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(y).all())
+    if not in_place:
+        assert bool(torch.isinf(x).any())   # the input is left as it was
 
 
 def test_stats_and_monotone_flag(dev):
