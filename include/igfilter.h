@@ -142,6 +142,33 @@ ig_status ig_filter_create(const ig_params* p, int device, ig_filter** out);
 ig_status ig_filter_run(ig_filter* f, const void* d_in, void* d_out, void* hip_stream,
                         ig_stats* stats);
 
+/* Largest cube, in bytes of its storage type, that ig_filter_run_static
+ * serves: 64 MiB (16,777,216 FP32 or 33,554,432 16-bit voxels, e.g. a
+ * 256^3 FP32 cube). */
+#define IG_STATIC_MAX_CUBE_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the filter
+ * of ig_filter_run without a handle and without any device allocation.  The
+ * ping-pong cube, the noise-level partials and the piece tables live in one
+ * static device array of the library (IG_STATIC_MAX_CUBE_BYTES plus about
+ * 1.1 MiB, held on each GPU the library runs on until the process ends).
+ * Arguments: p as for ig_filter_create (cubes of at most
+ * IG_STATIC_MAX_CUBE_BYTES; larger ones give IG_ERR_INVALID_ARG before any
+ * work), `device` the GPU of d_in and d_out, the rest as for ig_filter_run
+ * (d_in == d_out allowed; stats nullable, when given the call waits).  The
+ * result is bitwise the one ig_filter_run gives for the same parameters.
+ * The schedule is the library's automatic one with z chunks sized to one
+ * round of workgroups.  Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (concurrent streams or threads) race and
+ * must be serialised by the caller; consecutive calls on one stream are
+ * ordered by the stream. */
+ig_status ig_filter_run_static(const ig_params* p, int device, const void* d_in, void* d_out, void* hip_stream,
+                               ig_stats* stats);
+
+/* IG_STATIC_MAX_CUBE_BYTES as the library was built. */
+int64_t ig_filter_static_max_bytes(void);
+
 /* Override the schedule (NULL restores IG_SCHED_AUTO).  Rejects shapes the
  * schedule cannot serve with IG_ERR_INVALID_ARG. */
 ig_status ig_filter_set_schedule(ig_filter* f, const ig_schedule* s);

@@ -89,6 +89,9 @@ _P = ctypes.c_void_p
 SIGNATURES = {
     "ig_filter_create": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.c_int, ctypes.POINTER(_P)]),
     "ig_filter_run": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(IgStats)]),
+    "ig_filter_run_static": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.c_int, _P, _P, _P,
+                                            ctypes.POINTER(IgStats)]),
+    "ig_filter_static_max_bytes": (ctypes.c_int64, []),
     "ig_filter_set_schedule": (ctypes.c_int, [_P, ctypes.POINTER(IgSchedule)]),
     "ig_filter_get_schedule": (ctypes.c_int, [_P, ctypes.POINTER(IgSchedule)]),
     "ig_filter_destroy": (None, [_P]),
@@ -347,6 +350,37 @@ class Filter:
             return out, Stats(st.passes, st.rms_used, st.sum_in, st.sum_out, st.nonfinite, bool(st.monotone),
                               _sched_dict(st.schedule))
         return out
+
+
+def run_static(x, out=None, stats=False, K=2.0, tau=1.0 / 16, n_iter=50, C=(1.0, 1.0, 1.0), rms=None,
+               cond="pm_exp"):
+    """The filter without a handle and without device allocation in the
+    library (ig_filter_run_static): cubes of at most
+    ig_filter_static_max_bytes() bytes.  `out` defaults to a new tensor
+    (allocated by torch here, not by the library)."""
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or not x.is_contiguous() or x.dim() != 3:
+        raise TypeError("x must be a contiguous 3-D CUDA (HIP) tensor")
+    if out is None:
+        out = torch.empty_like(x)
+    if out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must match x in shape, dtype and device")
+    p = make_params(tuple(x.shape), K, tau, n_iter, C, rms, cond, _torch_dtype_name(x))
+    st = None
+    if stats:
+        st = IgStats()
+        st.struct_size = ctypes.sizeof(IgStats)
+    _check(lib().ig_filter_run_static(ctypes.byref(p), x.device.index or 0, ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(x),
+                                      ctypes.byref(st) if st is not None else None), "ig_filter_run_static")
+    if stats:
+        return out, Stats(st.passes, st.rms_used, st.sum_in, st.sum_out, st.nonfinite, bool(st.monotone),
+                          _sched_dict(st.schedule))
+    return out
+
+
+def static_max_bytes():
+    return int(lib().ig_filter_static_max_bytes())
 
 
 class PreparedBatch:

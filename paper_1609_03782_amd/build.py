@@ -27,7 +27,8 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract
 def _units():
     units = [("api", "api.cpp", ["-x", "hip"]), ("reduce", "reduce.hip", []), ("batch", "batch.hip", []),
              ("quality", "quality.hip", []), ("sweep", "sweep.cpp", ["-x", "hip"]),
-             ("smooth", "smooth.hip", []), ("wavelet", "wavelet.hip", [])]
+             ("smooth", "smooth.hip", []), ("wavelet", "wavelet.hip", []),
+             ("noalloc", "noalloc.hip", [])]
     for c in range(3):
         for d in range(3):
             units.append((f"stencil_c{c}_d{d}", "stencil_inst.hip", [f"-DIG_COND={c}", f"-DIG_DTYPE={d}"]))

@@ -87,6 +87,29 @@ def test_null_arguments():
     assert L.ig_version().count(b".") == 2
 
 
+def test_static_entry_point_validates_before_device_work():
+    """ig_filter_run_static checks its arguments on the host: bad parameters,
+    NULL buffers and cubes beyond the static workspace never reach a device."""
+    L = ig.lib()
+    assert L.ig_filter_static_max_bytes() == 64 << 20
+    fake = ctypes.c_void_p(0x1000)
+    assert L.ig_filter_run_static(None, 0, fake, fake, None, None) == ig.IG_ERR_INVALID_ARG
+    p = ig.make_params((8, 8, 8))
+    p.K = -1.0
+    assert L.ig_filter_run_static(ctypes.byref(p), 0, fake, fake, None, None) == ig.IG_ERR_INVALID_ARG
+    p = ig.make_params((8, 8, 8))
+    assert L.ig_filter_run_static(ctypes.byref(p), 0, None, fake, None, None) == ig.IG_ERR_INVALID_ARG
+    p = ig.make_params((257, 256, 256))                       # 1 plane past 64 MiB of FP32
+    assert L.ig_filter_run_static(ctypes.byref(p), 0, fake, fake, None, None) == ig.IG_ERR_INVALID_ARG
+    assert b"static workspace" in L.ig_last_error()
+    p = ig.make_params((513, 256, 256), dtype="bf16")         # the same limit in bytes for 16-bit storage
+    assert L.ig_filter_run_static(ctypes.byref(p), 0, fake, fake, None, None) == ig.IG_ERR_INVALID_ARG
+    st = ig.IgStats()
+    st.struct_size = 3
+    p = ig.make_params((8, 8, 8))
+    assert L.ig_filter_run_static(ctypes.byref(p), 0, fake, fake, None, ctypes.byref(st)) == ig.IG_ERR_INVALID_ARG
+
+
 def test_valid_params_reach_the_device_check():
     # With valid parameters the only failure left on a GPU-less host is the device lookup.
     import torch
