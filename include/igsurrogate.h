@@ -54,6 +54,31 @@ ig_status ig_surrogate_get_weights(const ig_surrogate* s, float* host, int64_t c
 /* Gradient of the last training step's loss (same layout as the weights). */
 ig_status ig_surrogate_get_grads(const ig_surrogate* s, float* host, int64_t count);
 
+/* Checkpoints of the training state: FP32 master weights, Adam m and v, the
+ * step count and the initialisation seed, with the Adam hyper-parameters the
+ * handle was created with recorded beside them.  Layout (little-endian): a
+ * 64-byte header {char magic[8] = "IGSURR\0\1"; uint32 header_bytes = 64;
+ * uint32 version = 1; int32 depth; int32 width; int64 nparam; int64 step;
+ * uint64 seed; float lr, beta1, beta2, eps}, then FP32 params[nparam],
+ * m[nparam], v[nparam], then the 64-bit FNV-1a hash of every byte before it.
+ * save waits for the device and writes `path` through a temporary file
+ * renamed into place.  load checks magic, version, sizes and hash, and that
+ * the network's depth and width match the handle's (else
+ * IG_ERR_INVALID_ARG with nothing changed); it restores weights, m, v, step
+ * and seed (the handle keeps its own lr, betas and eps), so training resumes
+ * exactly where the saved run stood.  checkpoint_info reads and checks a
+ * file on the host only (no device, no handle); outputs are nullable. */
+ig_status ig_surrogate_save(const ig_surrogate* s, const char* path);
+ig_status ig_surrogate_load(ig_surrogate* s, const char* path);
+ig_status ig_surrogate_checkpoint_info(const char* path, int32_t* depth, int32_t* width, int64_t* nparam,
+                                       int64_t* step, uint64_t* seed);
+
+/* Learning rate of later training steps (a schedule is the caller's: e.g.
+ * cosine decay over the planned steps); IG_ERR_INVALID_ARG unless finite > 0.
+ * get_step: Adam steps taken so far (-1 for NULL). */
+ig_status ig_surrogate_set_lr(ig_surrogate* s, float lr);
+int64_t ig_surrogate_get_step(const ig_surrogate* s);
+
 /* One Adam step on the mean squared error over `batch` cubes of one shape:
  * d_x[k], d_t[k] are device FP32 cubes (input, target).  loss (nullable)
  * receives the mean squared error before the step (the call then waits). */
@@ -64,8 +89,9 @@ ig_status ig_surrogate_train_step(ig_surrogate* s, const float* const* d_x, cons
  * halo of `depth` voxels (the network's receptive radius), which gives the
  * same result as one piece; (tile + 2 depth)^3 x 32 must stay below 2^31
  * (32-bit activation offsets).  tile == 0: the whole cube in one piece when
- * voxels x 32 < 2^31, otherwise the smallest number of equal tiles along the
- * longest axis that satisfies that bound (e.g. 256 for a 512^3 cube). */
+ * voxels x 32 < 2^31, otherwise slabs of the whole x-y extent: the fewest
+ * equal runs of planes whose slab with its halo planes satisfies that bound
+ * (three slabs of 171 planes, 187 with halo, for a 512^3 cube). */
 ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float* d_y, int64_t nx, int64_t ny, int64_t nz,
                              int32_t tile, void* hip_stream);
 

@@ -4,8 +4,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <random>
+#include <string>
 #include <vector>
 
 #include "igsurrogate.h"
@@ -25,7 +27,7 @@ using namespace igs;
 
 namespace {
 
-constexpr int kZC = 8;   // planes per workgroup of the weight-gradient kernel
+constexpr long kWgradGroups = 512;   // workgroups of the weight-gradient kernel (at most)
 
 struct Dev {
     void* p = nullptr;
@@ -47,8 +49,46 @@ struct Dev {
 };
 
 dim3 conv_grid(long nx, long ny, long nz) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, nz); }
-dim3 wgrad_grid(long nx, long ny, long nz) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, (nz + kZC - 1) / kZC); }
-long nwg_of(dim3 g) { return (long)g.x * g.y * g.z; }
+long wgrad_units(long nx, long ny, long nz) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * nz; }
+long wgrad_groups(long nx, long ny, long nz) { return std::min(kWgradGroups, wgrad_units(nx, ny, nz)); }
+
+// z-streaming launch for a 32-channel input: the z chunk that minimises the slowest compute unit's share (in planes, counting the
+// two margin planes and the B copy as about two more) with one workgroup per CU.
+template <int NB, int EPI, int MT>
+hipError_t zs_launch(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
+                     long nz, hipStream_t s) {
+    constexpr int XW = 16 * MT;
+    const int ntx = (int)((nx + XW - 1) / XW), nty = (int)((ny + kZsRows - 1) / kZsRows);
+    const long tiles = (long)ntx * nty;
+    int ncu = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    long best_cost = -1, zch = nz;
+    for (long nzc = 1; nzc <= nz; ++nzc) {
+        const long zc = (nz + nzc - 1) / nzc;
+        const long groups = tiles * ((nz + zc - 1) / zc);
+        const long cost = ((groups + ncu - 1) / ncu) * (zc + 4);
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; zch = zc; }
+        if (zc == 1) break;
+    }
+    const long groups = tiles * ((nz + zch - 1) / zch);
+    const size_t lds = zs_lds_bytes<MT, NB>();
+    auto kern = k_conv_zs<NB, EPI, MT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64 * kZsRows), lds, s, x, wp, b, out, aux, (int)nx, (int)ny,
+                       (int)nz, ntx, nty, (int)zch);
+    return hipGetLastError();
+}
+
+template <int NB, int EPI>
+hipError_t zs_launch_mt(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
+                        long nz, hipStream_t s) {
+    // 8 rows of 32 voxels (2 M-tiles) per workgroup: the largest tile whose
+    // three padded planes and the weights fit the 160 KB of LDS
+    static_assert(zs_lds_bytes<2, 2>() <= 160 * 1024, "z-stream tile exceeds LDS");
+    return zs_launch<NB, EPI, 2>(x, wp, b, out, aux, nx, ny, nz, s);
+}
 
 // forward conv launch (packed weights)
 hipError_t launch_conv(int cin, int cout, int epi, const void* in, const bf16x8* wp, const float* b, void* out,
@@ -56,6 +96,15 @@ hipError_t launch_conv(int cin, int cout, int epi, const void* in, const bf16x8*
     const dim3 g = conv_grid(nx, ny, nz), blk(256);
     const int NB = cout > 16 ? 2 : 1;
     const u16* x = static_cast<const u16*>(in);
+    if (cin == 32) {
+#define Z(NBV, EPIV) return zs_launch_mt<NBV, EPIV>(x, wp, b, out, aux, nx, ny, nz, s)
+        if (NB == 2) {
+            if (epi == EPI_RAW) Z(2, EPI_RAW); else if (epi == EPI_GELU) Z(2, EPI_GELU); else if (epi == EPI_BACK_GELU) Z(2, EPI_BACK_GELU); else Z(2, EPI_RESID);
+        } else {
+            if (epi == EPI_RAW) Z(1, EPI_RAW); else if (epi == EPI_GELU) Z(1, EPI_GELU); else if (epi == EPI_BACK_GELU) Z(1, EPI_BACK_GELU); else Z(1, EPI_RESID);
+        }
+#undef Z
+    }
 #define L(CIN, NBV, EPIV) hipLaunchKernelGGL((k_conv<CIN, NBV, EPIV>), g, blk, 0, s, x, wp, b, out, aux, (int)nx, (int)ny, (int)nz)
     if (cin == 1) {
         if (NB == 2) {
@@ -90,22 +139,24 @@ size_t packed_count(int cin, int cout, int mode) {
 // and db [COUTP] (COUTP = 32, or 16 for one output: column 0 is the gradient)
 hipError_t launch_wgrad(int cin, int cout, const void* a, const void* dz, Dev& part, Dev& partb, float* dW, float* db,
                         int accumulate, long nx, long ny, long nz, hipStream_t s) {
-    const dim3 g = wgrad_grid(nx, ny, nz);
-    const long nwg = nwg_of(g);
+    const long units = wgrad_units(nx, ny, nz);
+    const long nwg = wgrad_groups(nx, ny, nz);
+    const int ntx = (int)((nx + TX - 1) / TX), nty = (int)((ny + TY - 1) / TY);
+    const dim3 g((unsigned)nwg);
     const int NB = cout > 16 ? 2 : 1, COUTP = 16 * NB;
     hipError_t e = part.ensure((size_t)nwg * 27 * cin * COUTP * sizeof(float));
     if (e == hipSuccess) e = partb.ensure((size_t)nwg * COUTP * sizeof(float));
     if (e != hipSuccess) return e;
     const u16* A = static_cast<const u16*>(a);
     const u16* D = static_cast<const u16*>(dz);
-    if (cin == 32 && NB == 2) hipLaunchKernelGGL((k_wgrad<32, 2, kZC>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz);
-    else if (cin == 32) hipLaunchKernelGGL((k_wgrad<32, 1, kZC>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz);
-    else if (NB == 2) hipLaunchKernelGGL((k_wgrad<1, 2, kZC>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz);
-    else hipLaunchKernelGGL((k_wgrad<1, 1, kZC>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz);
+    if (cin == 32 && NB == 2) hipLaunchKernelGGL((k_wgrad<32, 2>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz, ntx, nty, units);
+    else if (cin == 32) hipLaunchKernelGGL((k_wgrad<32, 1>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz, ntx, nty, units);
+    else if (NB == 2) hipLaunchKernelGGL((k_wgrad<1, 2>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz, ntx, nty, units);
+    else hipLaunchKernelGGL((k_wgrad<1, 1>), g, dim3(256), 0, s, A, D, cout, part.as<float>(), partb.as<float>(), (int)nx, (int)ny, (int)nz, ntx, nty, units);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long len = 27L * cin * COUTP;
-    hipLaunchKernelGGL(k_wgrad_fold, dim3((len + 255) / 256), dim3(256), 0, s, part.as<float>(), nwg, len, dW, accumulate);
+    hipLaunchKernelGGL(k_wgrad_fold, dim3((len + 63) / 64), dim3(256), 0, s, part.as<float>(), nwg, len, dW, accumulate);
     hipLaunchKernelGGL(k_wgrad_fold, dim3(1), dim3(256), 0, s, partb.as<float>(), nwg, (long)COUTP, db, accumulate);
     return hipGetLastError();
 }
@@ -330,7 +381,7 @@ extern "C" ig_status ig_surrogate_train_step(ig_surrogate* s, const float* const
     ig_status rc = ensure_acts(s, n);
     if (rc != IG_OK) return rc;
     {   // weight-gradient partials for the largest layer, sized before any launch
-        const long nwg = nwg_of(wgrad_grid(nx, ny, nz));
+        const long nwg = wgrad_groups(nx, ny, nz);
         HIP_TRY(s->part.ensure((size_t)nwg * 27 * 32 * 32 * sizeof(float)));
         HIP_TRY(s->partb.ensure((size_t)nwg * 32 * sizeof(float)));
     }
@@ -408,38 +459,44 @@ extern "C" ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float
     }
     const int H = s->L;   // receptive radius
     // activations are addressed with 32-bit offsets: voxels x 32 channels < 2^31
+    constexpr long kMaxVox = (1LL << 31) / 32;
     auto fits = [&](long t) {
         const long d = t + 2 * H;
-        return std::min(nx, d) * std::min(ny, d) * std::min(nz, d) < (1LL << 31) / 32;
+        return std::min(nx, d) * std::min(ny, d) * std::min(nz, d) < kMaxVox;
     };
-    if (tile == 0 && n >= (1LL << 31) / 32) {
-        // the smallest number of equal tiles along the longest axis that fits
-        const long big = std::max(nx, std::max(ny, nz));
-        for (long k = 2; k <= big; ++k) {
-            const long t = (big + k - 1) / k;
-            if (fits(t)) { tile = (int)t; break; }
-        }
-        if (tile == 0) return fail(IG_ERR_UNSUPPORTED, "no tile size fits");
-    }
     if (tile > 0 && !(tile >= nx && tile >= ny && tile >= nz) && !fits(tile))
         return fail(IG_ERR_INVALID_ARG, "tile %d too large (tile + 2 depth)^3 x 32 must stay below 2^31", tile);
-    if (tile == 0 || (tile >= nx && tile >= ny && tile >= nz)) {
-        if (n >= (1LL << 31) / 32) return fail(IG_ERR_INVALID_ARG, "cube too large for one piece; use tiles");
+    // piece extents per axis: the whole cube; cubes of `tile`; or (tile == 0
+    // and a cube too large for one piece) slabs of the whole x-y extent and
+    // the fewest equal runs of planes whose piece with its halo fits
+    long tx = nx, ty = ny, tz = nz;
+    if (tile > 0 && !(tile >= nx && tile >= ny && tile >= nz)) {
+        tx = ty = tz = tile;
+    } else if (tile == 0 && n >= kMaxVox) {
+        tz = 0;
+        for (long k = 2; k <= nz; ++k) {
+            const long t = (nz + k - 1) / k;
+            if (nx * ny * std::min(nz, t + 2 * H) < kMaxVox) { tz = t; break; }
+        }
+        if (tz == 0) return fail(IG_ERR_UNSUPPORTED, "one plane of %lld x %lld voxels is too large for a piece",
+                                 (long long)nx, (long long)ny);
+    }
+    if (tx >= nx && ty >= ny && tz >= nz) {
         ig_status rc = ensure_acts(s, n);
         if (rc != IG_OK) return rc;
         rc = to_bf16(d_x, s->act[0].p, n, st);
         if (rc != IG_OK) return rc;
         return forward(s, d_x, d_y, nx, ny, nz, false, st);
     }
-    const long dmax = (long)tile + 2 * H;
-    ig_status rc = ensure_acts(s, dmax * dmax * dmax);
+    const long pmax = std::min(nx, tx + 2 * H) * std::min(ny, ty + 2 * H) * std::min(nz, tz + 2 * H);
+    ig_status rc = ensure_acts(s, pmax);
     if (rc != IG_OK) return rc;
-    HIP_TRY(s->sub_x.ensure(dmax * dmax * dmax * 4));
-    HIP_TRY(s->sub_y.ensure(dmax * dmax * dmax * 4));
-    for (long oz = 0; oz < nz; oz += tile)
-        for (long oy = 0; oy < ny; oy += tile)
-            for (long ox = 0; ox < nx; ox += tile) {
-                const long ex = std::min<long>(tile, nx - ox), ey = std::min<long>(tile, ny - oy), ez = std::min<long>(tile, nz - oz);
+    HIP_TRY(s->sub_x.ensure(pmax * 4));
+    HIP_TRY(s->sub_y.ensure(pmax * 4));
+    for (long oz = 0; oz < nz; oz += tz)
+        for (long oy = 0; oy < ny; oy += ty)
+            for (long ox = 0; ox < nx; ox += tx) {
+                const long ex = std::min<long>(tx, nx - ox), ey = std::min<long>(ty, ny - oy), ez = std::min<long>(tz, nz - oz);
                 const long bx = std::max<long>(0, ox - H), by = std::max<long>(0, oy - H), bz = std::max<long>(0, oz - H);
                 const long dx = std::min<long>(nx, ox + ex + H) - bx, dy = std::min<long>(ny, oy + ey + H) - by,
                            dz = std::min<long>(nz, oz + ez + H) - bz;
@@ -521,6 +578,144 @@ extern "C" ig_status ig_surrogate_infer_checked(ig_surrogate* s, const ig_params
     }
     return IG_OK;
 }
+
+// ------------------------------------------------------------ checkpoints
+// File layout (little-endian): a 64-byte header
+//   char magic[8] = "IGSURR\0\1"; uint32 header_bytes = 64; uint32 version = 1;
+//   int32 depth; int32 width; int64 nparam; int64 step; uint64 seed;
+//   float lr, beta1, beta2, eps;
+// then FP32 params[nparam], Adam m[nparam], Adam v[nparam], then the 64-bit
+// FNV-1a hash of every preceding byte.
+namespace {
+struct CkptHeader {
+    char magic[8];
+    uint32_t header_bytes, version;
+    int32_t depth, width;
+    int64_t nparam, step;
+    uint64_t seed;
+    float lr, beta1, beta2, eps;
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header must be 64 bytes");
+constexpr char kCkptMagic[8] = {'I', 'G', 'S', 'U', 'R', 'R', '\0', '\1'};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+constexpr uint64_t kFnvBasis = 14695981039346656037ull;
+
+// Read and check a whole checkpoint file (host only): header, sizes, hash.
+ig_status read_checkpoint(const char* path, CkptHeader* hd, std::vector<float>* body) {
+    if (!path || !hd) return fail(IG_ERR_INVALID_ARG, "NULL argument");
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(IG_ERR_INVALID_ARG, "cannot open %s", path);
+    std::vector<unsigned char> buf;
+    unsigned char chunk[1 << 16];
+    size_t got;
+    while ((got = fread(chunk, 1, sizeof chunk, f)) > 0) buf.insert(buf.end(), chunk, chunk + got);
+    fclose(f);
+    if (buf.size() < sizeof(CkptHeader) + 8) return fail(IG_ERR_INVALID_ARG, "%s: too short for a checkpoint", path);
+    std::memcpy(hd, buf.data(), sizeof(CkptHeader));
+    if (std::memcmp(hd->magic, kCkptMagic, 8) != 0) return fail(IG_ERR_INVALID_ARG, "%s: not a surrogate checkpoint", path);
+    if (hd->header_bytes != sizeof(CkptHeader) || hd->version != 1)
+        return fail(IG_ERR_INVALID_ARG, "%s: unsupported checkpoint version %u", path, hd->version);
+    if (hd->nparam < 1 || hd->nparam > (1LL << 32) || hd->depth < 2 || hd->depth > 64 || hd->width != 32 || hd->step < 0)
+        return fail(IG_ERR_INVALID_ARG, "%s: bad checkpoint header", path);
+    const size_t want = sizeof(CkptHeader) + (size_t)hd->nparam * 12 + 8;
+    if (buf.size() != want) return fail(IG_ERR_INVALID_ARG, "%s: %zu bytes, the header implies %zu", path, buf.size(), want);
+    uint64_t stored;
+    std::memcpy(&stored, buf.data() + want - 8, 8);
+    if (fnv1a(kFnvBasis, buf.data(), want - 8) != stored)
+        return fail(IG_ERR_INVALID_ARG, "%s: checksum mismatch (corrupt or truncated)", path);
+    if (body) {
+        body->resize((size_t)hd->nparam * 3);
+        std::memcpy(body->data(), buf.data() + sizeof(CkptHeader), (size_t)hd->nparam * 12);
+    }
+    return IG_OK;
+}
+}  // namespace
+
+extern "C" ig_status ig_surrogate_save(const ig_surrogate* s, const char* path) {
+    if (!s || !path) return fail(IG_ERR_INVALID_ARG, "NULL argument");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize());
+    const size_t n = s->nparam;
+    std::vector<float> body(3 * n);
+    HIP_TRY(hipMemcpy(body.data(), s->params.p, n * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(body.data() + n, s->m.p, n * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(body.data() + 2 * n, s->v.p, n * 4, hipMemcpyDeviceToHost));
+    CkptHeader hd{};
+    std::memcpy(hd.magic, kCkptMagic, 8);
+    hd.header_bytes = sizeof(CkptHeader);
+    hd.version = 1;
+    hd.depth = s->p.depth;
+    hd.width = s->p.width;
+    hd.nparam = (int64_t)n;
+    hd.step = s->step;
+    hd.seed = s->p.seed;
+    hd.lr = s->p.lr; hd.beta1 = s->p.beta1; hd.beta2 = s->p.beta2; hd.eps = s->p.eps;
+    uint64_t h = fnv1a(kFnvBasis, &hd, sizeof hd);
+    h = fnv1a(h, body.data(), body.size() * 4);
+    // write beside the target, then rename: a reader never sees a partial file
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    if (!f) return fail(IG_ERR_INVALID_ARG, "cannot write %s", tmp.c_str());
+    bool ok = fwrite(&hd, sizeof hd, 1, f) == 1 && fwrite(body.data(), 4, body.size(), f) == body.size() &&
+              fwrite(&h, 8, 1, f) == 1;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(IG_ERR_DEVICE, "writing %s failed", path);
+    }
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_load(ig_surrogate* s, const char* path) {
+    if (!s || !path) return fail(IG_ERR_INVALID_ARG, "NULL argument");
+    CkptHeader hd;
+    std::vector<float> body;
+    ig_status st = read_checkpoint(path, &hd, &body);
+    if (st != IG_OK) return st;
+    if (hd.depth != s->p.depth || hd.width != s->p.width || hd.nparam != (int64_t)s->nparam)
+        return fail(IG_ERR_INVALID_ARG, "%s: network of depth %d, the handle has depth %d", path, hd.depth, s->p.depth);
+    if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize());
+    const size_t n = s->nparam;
+    HIP_TRY(hipMemcpy(s->params.p, body.data(), n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->m.p, body.data() + n, n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->v.p, body.data() + 2 * n, n * 4, hipMemcpyHostToDevice));
+    s->step = hd.step;
+    s->p.seed = hd.seed;
+    st = repack(s, 0);
+    if (st != IG_OK) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_checkpoint_info(const char* path, int32_t* depth, int32_t* width, int64_t* nparam,
+                                                  int64_t* step, uint64_t* seed) {
+    CkptHeader hd;
+    ig_status st = read_checkpoint(path, &hd, nullptr);
+    if (st != IG_OK) return st;
+    if (depth) *depth = hd.depth;
+    if (width) *width = hd.width;
+    if (nparam) *nparam = hd.nparam;
+    if (step) *step = hd.step;
+    if (seed) *seed = hd.seed;
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_set_lr(ig_surrogate* s, float lr) {
+    if (!s || !(lr > 0) || !std::isfinite(lr)) return fail(IG_ERR_INVALID_ARG, "lr must be finite and > 0");
+    s->p.lr = lr;
+    return IG_OK;
+}
+
+extern "C" int64_t ig_surrogate_get_step(const ig_surrogate* s) { return s ? (int64_t)s->step : -1; }
 
 // ------------------------------------------------------------ building blocks
 extern "C" ig_status ig_conv3d_forward(const void* d_in, int32_t c_in, const float* d_w, const float* d_b, int32_t c_out,

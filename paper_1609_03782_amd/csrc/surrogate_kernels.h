@@ -35,6 +35,12 @@ enum { EPI_RAW = 0, EPI_GELU = 1, EPI_BACK_GELU = 2, EPI_RESID = 3 };
 constexpr int TX = 32;   // output tile: 32 voxels in x (two 16-row MFMA tiles) ...
 constexpr int TY = 4;    // ... by 4 rows in y (one per wavefront), one plane in z
 
+// LDS stride of one voxel's channels: 32 channels padded to 40 (80 bytes), so
+// the 16 lanes of one pass of a 16-byte LDS read (16 consecutive voxels, one
+// 8-channel group) start 20 banks apart and cover all 64 banks once; at 64
+// bytes they would meet on the same 4 banks (4-way conflicts).
+template <int C> constexpr int lds_stride() { return C == 32 ? 40 : C; }
+
 __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((unsigned)h << 16); }
 __device__ __forceinline__ u16 f2bf(float f) {   // round to nearest, ties to even (finite inputs)
     unsigned u = __float_as_uint(f);
@@ -57,7 +63,8 @@ k_conv(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* _
        void* __restrict__ out, const void* __restrict__ aux, int nx, int ny, int nz) {
     constexpr int COUTP = 16 * NB;
     constexpr int LX = TX + 2, LY = TY + 2;
-    __shared__ __attribute__((aligned(16))) u16 tile[3 * LY * LX * CIN];
+    constexpr int CS = lds_stride<CIN>();
+    __shared__ __attribute__((aligned(16))) u16 tile[3 * LY * LX * CS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z;
 
@@ -71,7 +78,7 @@ k_conv(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* _
             uint4 v = make_uint4(0, 0, 0, 0);
             if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz)
                 v = *reinterpret_cast<const uint4*>(in + ((long)(z * ny + y) * nx + x) * CIN + 8 * c);
-            *reinterpret_cast<uint4*>(tile + vox * CIN + 8 * c) = v;
+            *reinterpret_cast<uint4*>(tile + vox * CS + 8 * c) = v;
         }
     } else {
         for (int vox = threadIdx.x; vox < 3 * LY * LX; vox += 256) {
@@ -121,7 +128,7 @@ k_conv(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* _
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int vox = (dz * LY + (w + dy)) * LX + (16 * s + i + dx);
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(tile + vox * 32 + 8 * kg);
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(tile + vox * CS + 8 * kg);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[s][nb], 0, 0, 0);
@@ -159,26 +166,209 @@ k_conv(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* _
         }
 }
 
+// ------------------------------------------------ conv, z-streaming, 32 in
+// Error function by Abramowitz & Stegun, Handbook of Mathematical Functions,
+// formula 7.1.26: erf(x) = 1 - (a1 t + ... + a5 t^5) e^{-x^2}, t = 1/(1 + p x)
+// for x >= 0, |error| <= 1.5e-7 (far below the bf16 rounding of every value
+// it feeds).  e2 returns e^{-x^2}, which GELU' reuses.
+__device__ __forceinline__ float erf_as(float x, float* e2) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, ax, 1.0f));
+    const float ex = __builtin_amdgcn_exp2f(-(ax * ax) * 1.4426950408889634f);
+    float pl = __builtin_fmaf(1.061405429f, t, -1.453152027f);
+    pl = __builtin_fmaf(pl, t, 1.421413741f);
+    pl = __builtin_fmaf(pl, t, -0.284496736f);
+    pl = __builtin_fmaf(pl, t, 0.254829592f);
+    const float y = 1.0f - (pl * t) * ex;
+    *e2 = ex;
+    return x < 0.0f ? -y : y;
+}
+// gelu(z) = z/2 (1 + erf(z/sqrt2)); gelu'(z) = (1 + erf(z/sqrt2))/2 + z e^{-z^2/2}/sqrt(2 pi)
+__device__ __forceinline__ float gelu_fast(float z) {
+    float e;
+    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f, &e));
+}
+__device__ __forceinline__ float gelu_grad_fast(float z) {
+    float e;
+    const float er = erf_as(z * 0.70710678118654752f, &e);
+    return 0.5f * (1.0f + er) + z * (0.39894228040143268f * e);
+}
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+// four FP32 values to four bf16 (round to nearest, ties to even; the gfx950
+// conversion instruction packs two per operation)
+__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
+    const bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+    return __builtin_bit_cast(uint2, v);
+}
+
+// The convolution of a 32-channel input as a z-stream: a workgroup of 8
+// wavefronts owns an output tile of 16*MT voxels in x by 8 rows in y (one
+// row per wavefront, MT 16-voxel tiles each) and a chunk of planes [z0, z1).
+// The packed weight fragments of all 27 taps are copied to LDS once; input
+// planes z-1, z, z+1 (tile plus a one-voxel margin, zeros outside the cube)
+// sit in a ring of three LDS slots, and while plane z is computed the global
+// loads of plane z+2 are in flight in registers.  The weights are the MFMA's
+// A operand and the activations its B operand (the same register fragments
+// as the other way round), so each lane ends with four consecutive output
+// channels of one voxel and stores them with one 8-byte write.  Per output the
+// taps are accumulated in the order 0..26, then the bias is added.
+constexpr int kZsRows = 8;
+
+template <int MT>
+constexpr int zs_plane_u16() { return (16 * MT + 2) * (kZsRows + 2) * lds_stride<32>(); }
+template <int MT, int NB>
+constexpr size_t zs_lds_bytes() { return (size_t)27 * NB * 64 * 16 + (size_t)3 * zs_plane_u16<MT>() * 2; }
+
+template <int NB, int EPI, int MT>
+__global__ void __launch_bounds__(512)
+k_conv_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* __restrict__ bias,
+          void* __restrict__ out, const void* __restrict__ aux, int nx, int ny, int nz, int ntx, int nty, int zch) {
+    constexpr int COUTP = 16 * NB;
+    constexpr int XW = 16 * MT, LX = XW + 2, LY = kZsRows + 2;
+    constexpr int CS = lds_stride<32>();
+    constexpr int PLU = zs_plane_u16<MT>();
+    constexpr int NT = 64 * kZsRows;                // threads
+    constexpr int NCH = LX * LY * 4;               // 16-byte chunks of one staged plane
+    constexpr int PER = (NCH + NT - 1) / NT;
+    extern __shared__ uint4 zs_smem[];
+    bf16x8* Bs = reinterpret_cast<bf16x8*>(zs_smem);
+    u16* ring = reinterpret_cast<u16*>(zs_smem + 27 * NB * 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kg = lane >> 4;
+    const int bt = blockIdx.x;
+    const int tx = bt % ntx, ty = (bt / ntx) % nty, tz = bt / (ntx * nty);
+    const int x0 = tx * XW, y0 = ty * kZsRows;
+    const int z0 = tz * zch, z1 = min(nz, z0 + zch);
+
+    for (int q = threadIdx.x; q < 27 * NB * 64; q += NT) Bs[q] = wp[q];
+
+    uint4 st[PER];
+    auto fetch = [&](int z) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int q = threadIdx.x + NT * k;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            const int c = q & 3, vox = q >> 2;
+            const int x = x0 + vox % LX - 1, y = y0 + vox / LX - 1;
+            if (q < NCH && z >= 0 && z < nz && x >= 0 && x < nx && y >= 0 && y < ny)
+                v = *reinterpret_cast<const uint4*>(in + ((long)(z * ny + y) * nx + x) * 32 + 8 * c);
+            st[k] = v;
+        }
+    };
+    auto put = [&](int z) {
+        u16* slot = ring + ((z + 3) % 3) * PLU;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int q = threadIdx.x + NT * k;
+            if (q < NCH) *reinterpret_cast<uint4*>(slot + (q >> 2) * CS + 8 * (q & 3)) = st[k];
+        }
+    };
+    fetch(z0 - 1);
+    put(z0 - 1);
+    fetch(z0);
+    put(z0);
+    fetch(z0 + 1);
+
+    const int y = y0 + w;
+    for (int z = z0; z < z1; ++z) {
+        put(z + 1);
+        __syncthreads();
+        if (z + 1 < z1) fetch(z + 2);
+
+        f32x4 acc[MT][NB];
+#pragma unroll
+        for (int s = 0; s < MT; ++s)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) {
+            const u16* slot = ring + ((z - 1 + dz + 3) % 3) * PLU;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int t = dz * 9 + dy * 3 + dx;
+                    bf16x8 wf[NB];
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) wf[nb] = Bs[(t * NB + nb) * 64 + lane];
+#pragma unroll
+                    for (int s = 0; s < MT; ++s) {
+                        const int vox = (w + dy) * LX + (16 * s + i + dx);
+                        const bf16x8 a = *reinterpret_cast<const bf16x8*>(slot + vox * CS + 8 * kg);
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], a, acc[s][nb], 0, 0, 0);
+                    }
+                }
+        }
+        // epilogue: lane holds D[m = 4*kg + e][n = i], output channel 16*nb + 4*kg + e of voxel 16*s + i
+        if (y < ny) {
+#pragma unroll
+            for (int s = 0; s < MT; ++s) {
+                const int x = x0 + 16 * s + i;
+                if (x >= nx) continue;
+                const long v = (long)(z * ny + y) * nx + x;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int n0 = 16 * nb + 4 * kg;
+                    const f32x4 d = acc[s][nb];
+                    if constexpr (EPI == EPI_RAW) {
+                        float4 r;
+                        r.x = d[0] + (bias ? bias[n0] : 0.0f);
+                        r.y = d[1] + (bias ? bias[n0 + 1] : 0.0f);
+                        r.z = d[2] + (bias ? bias[n0 + 2] : 0.0f);
+                        r.w = d[3] + (bias ? bias[n0 + 3] : 0.0f);
+                        *reinterpret_cast<float4*>(static_cast<float*>(out) + v * COUTP + n0) = r;
+                    } else if constexpr (EPI == EPI_GELU) {
+                        const float z0p = d[0] + bias[n0], z1p = d[1] + bias[n0 + 1];
+                        const float z2p = d[2] + bias[n0 + 2], z3p = d[3] + bias[n0 + 3];
+                        if (aux)
+                            *reinterpret_cast<uint2*>(const_cast<u16*>(static_cast<const u16*>(aux)) + v * COUTP + n0) =
+                                pack_bf16x4(z0p, z1p, z2p, z3p);
+                        *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
+                            pack_bf16x4(gelu_fast(z0p), gelu_fast(z1p), gelu_fast(z2p), gelu_fast(z3p));
+                    } else if constexpr (EPI == EPI_BACK_GELU) {
+                        const uint2 pb = *reinterpret_cast<const uint2*>(static_cast<const u16*>(aux) + v * COUTP + n0);
+                        const float g0 = gelu_grad_fast(__uint_as_float(pb.x << 16));
+                        const float g1 = gelu_grad_fast(__uint_as_float(pb.x & 0xffff0000u));
+                        const float g2 = gelu_grad_fast(__uint_as_float(pb.y << 16));
+                        const float g3 = gelu_grad_fast(__uint_as_float(pb.y & 0xffff0000u));
+                        *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
+                            pack_bf16x4(d[0] * g0, d[1] * g1, d[2] * g2, d[3] * g3);
+                    } else {   // EPI_RESID: output channel 0 only
+                        if (n0 == 0) static_cast<float*>(out)[v] = static_cast<const float*>(aux)[v] + (d[0] + bias[0]);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // every wavefront is done with slot (z - 1) before it takes plane z + 2
+    }
+}
+
 // ---------------------------------------------------------- weight grad
-// Partial dW of one workgroup: voxels of a 32 x 4 tile over ZC planes.
+// Partial dW of one workgroup: a contiguous range of "tile-planes" (32 x 4
+// voxels of one plane; unit u = (z * nty + ty) * ntx + tx), the same fixed
+// split of the units for every call, so the partials and their fold are
+// deterministic.  Few workgroups (a couple per CU), each over many units, keep
+// the partials (and the fold that reads them) small.
 // CIN == 32: rows = input channels, each wavefront owns taps t = w, w+4, ...
 // CIN == 1:  rows = taps (27, padded to 32), one set of accumulators.
 // COUT = 32 (NB = 2) or 1 (NB = 1, only column 0 non-zero).
 // part[wg][27*CIN][COUTP] in FP32; bias partials in part_b[wg][COUTP].
-template <int CIN, int NB, int ZC>
+template <int CIN, int NB>
 __global__ void __launch_bounds__(256)
 k_wgrad(const u16* __restrict__ a, const u16* __restrict__ dz, int cout, float* __restrict__ part,
-        float* __restrict__ part_b, int nx, int ny, int nz) {
+        float* __restrict__ part_b, int nx, int ny, int nz, int ntx, int nty, long units) {
     constexpr int COUTP = 16 * NB;
     constexpr int LX = TX + 2, LY = TY + 2;
     constexpr int NT = CIN == 32 ? 7 : 1;           // taps per wavefront (CIN == 32)
-    __shared__ __attribute__((aligned(16))) u16 at[3 * LY * LX * CIN];
+    constexpr int CS = lds_stride<CIN>();
+    __shared__ __attribute__((aligned(16))) u16 at[3 * LY * LX * CS];
     __shared__ __attribute__((aligned(16))) u16 gt[TY * TX * COUTP];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, kg = lane >> 4;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int zb0 = blockIdx.z * ZC;
-    const long wg = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const long wg = blockIdx.x;
+    const long u0 = wg * units / gridDim.x, u1 = (wg + 1) * units / gridDim.x;
 
     // accumulators: CIN == 32 -> [tap slot][channel subtile][nb]; CIN == 1 -> [tap subtile][nb]
     constexpr int MS = 2;
@@ -191,9 +381,8 @@ k_wgrad(const u16* __restrict__ a, const u16* __restrict__ dz, int cout, float* 
             for (int nb = 0; nb < NB; ++nb) acc[q][ms][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.0f;   // bias gradient of channel threadIdx.x (< COUTP), this workgroup
 
-    for (int zi = 0; zi < ZC; ++zi) {
-        const int z0 = zb0 + zi;
-        if (z0 >= nz) break;
+    for (long u = u0; u < u1; ++u) {
+        const int x0 = (int)(u % ntx) * TX, y0 = (int)((u / ntx) % nty) * TY, z0 = (int)(u / ((long)ntx * nty));
         __syncthreads();
         // stage activations (with margin, zero outside) and the output gradient tile
         if constexpr (CIN % 8 == 0) {
@@ -205,7 +394,7 @@ k_wgrad(const u16* __restrict__ a, const u16* __restrict__ dz, int cout, float* 
                 uint4 v = make_uint4(0, 0, 0, 0);
                 if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz)
                     v = *reinterpret_cast<const uint4*>(a + ((long)(z * ny + y) * nx + x) * CIN + 8 * c);
-                *reinterpret_cast<uint4*>(at + vox * CIN + 8 * c) = v;
+                *reinterpret_cast<uint4*>(at + vox * CS + 8 * c) = v;
             }
         } else {
             for (int vox = threadIdx.x; vox < 3 * LY * LX; vox += 256) {
@@ -248,7 +437,7 @@ k_wgrad(const u16* __restrict__ a, const u16* __restrict__ dz, int cout, float* 
 #pragma unroll
                             for (int e = 0; e < 8; ++e) {
                                 const int vox = (dz_ * LY + (yy + dy)) * LX + (8 * kg + e + dx);
-                                av[e] = __builtin_bit_cast(__bf16, at[vox * 32 + 16 * ms + i]);
+                                av[e] = __builtin_bit_cast(__bf16, at[vox * CS + 16 * ms + i]);
                             }
 #pragma unroll
                             for (int nb = 0; nb < NB; ++nb)
@@ -312,14 +501,34 @@ k_wgrad(const u16* __restrict__ a, const u16* __restrict__ dz, int cout, float* 
     if (threadIdx.x < COUTP) part_b[wg * COUTP + threadIdx.x] = bsum;
 }
 
-// dW[j] (+)= sum over workgroups of part[wg][j], in workgroup order.
+// dW[j] (+)= sum over workgroups of part[wg][j] in a fixed order: wavefront
+// q of the block sums the workgroups [q nwg/4, (q+1) nwg/4) in order for 64
+// consecutive j (eight loads in flight), then the four sums are added in
+// order q = 0..3.
 __global__ void __launch_bounds__(256)
 k_wgrad_fold(const float* __restrict__ part, long nwg, long len, float* __restrict__ dst, int accumulate) {
-    const long j = (long)blockIdx.x * 256 + threadIdx.x;
-    if (j >= len) return;
+    __shared__ float sh[4][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const long j = (long)blockIdx.x * 64 + lane;
+    const long k0 = q * nwg / 4, k1 = (q + 1) * nwg / 4;
     float s = 0.0f;
-    for (long k = 0; k < nwg; ++k) s += part[k * len + j];
-    dst[j] = accumulate ? dst[j] + s : s;
+    if (j < len) {
+        long k = k0;
+        for (; k + 8 <= k1; k += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(k + u) * len + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; k < k1; ++k) s += part[k * len + j];
+    }
+    sh[q][lane] = s;
+    __syncthreads();
+    if (q == 0 && j < len) {
+        const float t = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+        dst[j] = accumulate ? dst[j] + t : t;
+    }
 }
 
 // ---------------------------------------------------------- loss, inputs

@@ -40,6 +40,13 @@ SIGNATURES = {
     "ig_surrogate_infer_checked": (ctypes.c_int, [_P, ctypes.POINTER(IgParams), _P, _P, ctypes.c_int32,
                                                   ctypes.c_double, ctypes.c_double, _P,
                                                   ctypes.POINTER(IgSurrogateReport)]),
+    "ig_surrogate_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "ig_surrogate_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "ig_surrogate_checkpoint_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64),
+                                                    ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_uint64)]),
+    "ig_surrogate_set_lr": (ctypes.c_int, [_P, ctypes.c_float]),
+    "ig_surrogate_get_step": (_I64, [_P]),
     "ig_conv3d_forward": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _I64,
                                          _I64, _I64, _P]),
     "ig_conv3d_input_grad": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _I64, _I64, _I64, _P]),
@@ -100,6 +107,21 @@ class Surrogate:
         a = np.ascontiguousarray(w, np.float32)
         _check(slib().ig_surrogate_set_weights(self._h, a.ctypes.data_as(_F), a.size), "ig_surrogate_set_weights")
 
+    def save(self, path):
+        """Checkpoint weights, Adam state, step and seed (ig_surrogate_save)."""
+        _check(slib().ig_surrogate_save(self._h, str(path).encode()), "ig_surrogate_save")
+
+    def load(self, path):
+        """Restore a checkpoint of a network of the same depth (ig_surrogate_load)."""
+        _check(slib().ig_surrogate_load(self._h, str(path).encode()), "ig_surrogate_load")
+
+    def set_lr(self, lr):
+        _check(slib().ig_surrogate_set_lr(self._h, float(lr)), "ig_surrogate_set_lr")
+
+    @property
+    def step(self):
+        return int(slib().ig_surrogate_get_step(self._h))
+
     def train_step(self, xs, ts, want_loss=True):
         n = len(xs)
         shape = tuple(xs[0].shape)
@@ -129,6 +151,16 @@ class Surrogate:
                "ig_surrogate_infer_checked")
         return out, {"residual": rep.residual, "predicted_rmse": rep.predicted_rmse, "rho": rep.rho,
                      "fell_back": bool(rep.fell_back)}
+
+
+def checkpoint_info(path):
+    """Header of a checkpoint file, checked on the host (no GPU needed):
+    dict with depth, width, nparam, step, seed."""
+    d, w = ctypes.c_int32(), ctypes.c_int32()
+    n, st, sd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
+    _check(slib().ig_surrogate_checkpoint_info(str(path).encode(), ctypes.byref(d), ctypes.byref(w), ctypes.byref(n),
+                                               ctypes.byref(st), ctypes.byref(sd)), "ig_surrogate_checkpoint_info")
+    return {"depth": d.value, "width": w.value, "nparam": n.value, "step": st.value, "seed": sd.value}
 
 
 def param_layout(depth=8, width=32):

@@ -167,12 +167,25 @@ def test_large_cube_auto_tiles(dev):
     import torch
     from paper_1609_03782_amd import surrogate as sg
     net = sg.Surrogate(depth=8, seed=5)
+    # random weights in every layer (the initial last layer is zero, which
+    # would make y = x whatever the tiling)
+    rng = np.random.default_rng(15)
+    Ws, bs = sg.split_params(net.get_weights(), 8)
+    Ws = [(rng.standard_normal(W.shape) * np.sqrt(1.0 / (27 * W.shape[1]))).astype(np.float32) for W in Ws]
+    bs = [(0.1 * rng.standard_normal(b.shape)).astype(np.float32) for b in bs]
+    net.set_weights(sg.join_params(Ws, bs))
     x = torch.randn(257, 512, 512, device=dev)       # 6.74e7 voxels: 32 x voxels > 2^31
-    y0 = net.infer(x)                                # library-picked tiles (256)
-    y1 = net.infer(x, tile=200)
+    y0 = net.infer(x)                                # library-picked slabs (2 x 129 planes)
+    y1 = net.infer(x, tile=200)                      # cubes of 200^3
     torch.cuda.synchronize()
     assert torch.equal(y0, y1)
     assert bool(torch.isfinite(y0).all())
+    assert float((y0 - x).abs().max()) > 1e-2       # the network changes its input
+    # a piece of the interior equals the network on that piece with its halo
+    sub = x[100:140, 200:260, 300:380].contiguous()
+    ys = net.infer(sub)
+    torch.cuda.synchronize()
+    assert torch.equal(ys[8:-8, 8:-8, 8:-8], y0[108:132, 208:252, 308:372])
     with pytest.raises(Exception):
         net.infer(x, tile=500)                       # (500 + 16)^2 x 257 x 32 >= 2^31
 
@@ -215,6 +228,49 @@ def test_training_lowers_the_loss(dev):
     for _ in range(40):
         last = net.train_step(xs, ts)
     assert last < 0.5 * first, (first, last)
+
+
+def test_checkpoint_resume_is_bitwise(dev, tmp_path):
+    """Save after 3 steps, load into a fresh handle (other seed), take 2 more
+    steps on both: the losses and the weights of the resumed run equal the
+    uninterrupted run's bit for bit (weights, Adam m and v, and the step count
+    are restored; every kernel sums in a fixed order)."""
+    import torch
+    import paper_1609_03782_amd as ig
+    from paper_1609_03782_amd import surrogate as sg
+    import igsynth
+    xs, ts = [], []
+    for k in range(4):
+        c = igsynth.batch_cube(igsynth.BatchItem((20, 22, 24), 2.0, 10, 800 + k))
+        x = torch.from_numpy(c).to(dev)
+        xs.append(x)
+        ts.append(ig.Filter(c.shape, K=2.0, tau=1 / 16, n_iter=10).run(x))
+    torch.cuda.synchronize()
+    a = sg.Surrogate(depth=3, seed=11, lr=2e-3)
+    for k in range(3):
+        a.train_step(xs[k % 2 * 2:k % 2 * 2 + 2], ts[k % 2 * 2:k % 2 * 2 + 2])
+    path = tmp_path / "s.ckpt"
+    a.save(path)
+    info = sg.checkpoint_info(path)
+    assert info["step"] == 3 and info["seed"] == 11 and info["depth"] == 3 and info["nparam"] == a.param_count
+    b = sg.Surrogate(depth=3, seed=12, lr=2e-3)
+    assert not np.array_equal(a.get_weights(), b.get_weights())
+    b.load(path)
+    assert b.step == 3 and np.array_equal(a.get_weights(), b.get_weights())
+    for k in range(3, 5):
+        la = a.train_step(xs[k % 2 * 2:k % 2 * 2 + 2], ts[k % 2 * 2:k % 2 * 2 + 2])
+        lb = b.train_step(xs[k % 2 * 2:k % 2 * 2 + 2], ts[k % 2 * 2:k % 2 * 2 + 2])
+        assert la == lb, (k, la, lb)
+    assert np.array_equal(a.get_weights(), b.get_weights())
+    ya, yb = a.infer(xs[0]), b.infer(xs[0])
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yb)
+    # a checkpoint of another depth is refused and leaves the handle as it was
+    c = sg.Surrogate(depth=4, seed=13)
+    w0 = c.get_weights()
+    with pytest.raises(ig.IgError):
+        c.load(path)
+    assert np.array_equal(w0, c.get_weights()) and c.step == 0
 
 
 def test_checked_inference_and_fallback(dev):
