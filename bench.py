@@ -8,7 +8,8 @@ storage runs of that cube, the paper's default parameters on it, and the
 96-cube batched launch, each measured the same way.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
-  python bench.py --workload surrogate [--train N] [--epochs E]
+  python bench.py --workload surrogate [--train N] [--budget SECONDS]
+  python bench.py --workload conv      (the surrogate's kernels alone, for profiling)
   python bench.py --calib-copy          (plain copy of the cube size, for counter calibration)
 """
 from __future__ import annotations
@@ -470,93 +471,198 @@ def bench_wavelet(x):
     return res
 
 
-def bench_surrogate(args):
-    """Learned surrogate: train on filter-generated pairs, calibrate the
-    residual check, then time checked inference on the 512^3 cube against
-    the plain filter."""
+def train_with_budget(net, xs, ts, budget_s, batch, lr0, lr_end_frac=0.02, warm_steps=300, seed=0, log=None,
+                      curve_every=100):
+    """Minibatch Adam over (x, t) pairs for about budget_s seconds: the step
+    time of the first 20 steps fixes the number of steps; the learning rate
+    rises linearly from 0.05 lr0 to lr0 over warm_steps, then follows a cosine
+    down to lr_end_frac * lr0.  Returns (steps, loss curve [(step, mean loss
+    of the last curve_every steps)], all losses)."""
+    import math
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    order, pos = rng.permutation(len(xs)), 0
+    losses, curve = [], []
+
+    def one(k, total):
+        nonlocal order, pos
+        if pos + batch > len(order):
+            order, pos = rng.permutation(len(xs)), 0
+        idx = order[pos:pos + batch]
+        pos += batch
+        if k < warm_steps:
+            lr = lr0 * (0.05 + 0.95 * k / warm_steps)
+        else:
+            q = min(1.0, (k - warm_steps) / max(1, total - warm_steps))
+            lr = lr0 * (lr_end_frac + (1 - lr_end_frac) * 0.5 * (1 + math.cos(math.pi * q)))
+        net.set_lr(lr)
+        losses.append(net.train_step([xs[i] for i in idx], [ts[i] for i in idx]))
+        if len(losses) % curve_every == 0:
+            curve.append((len(losses), float(np.mean(losses[-curve_every:]))))
+            if log:
+                log(f"step {len(losses)} lr {lr:.2e} loss {curve[-1][1]:.5f}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    warm = 20
+    for k in range(warm):
+        one(k, 10 ** 9)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / warm
+    total = max(warm + 1, int(budget_s / per))
+    for k in range(warm, total):
+        one(k, total)
+    torch.cuda.synchronize()
+    return total, curve, losses
+
+
+def surrogate_c5(x, ms_plain, ref=None, rho=None, budget_s=90.0, n_train=4000, n_val=50, cube=96, batch=4,
+                 lr=4e-4, threshold=0.05, log=None):
+    """The learned surrogate on the 512^3 workload: train the 8-layer 32-channel
+    network on n_train synthetic 96^3 cubes paired with their 50-step filter
+    outputs (made by the library's filter) for about budget_s seconds,
+    calibrate the residual check on n_val held-out cubes, then on the 512^3
+    cube time the forward pass and the checked path (forward + two plain steps
+    + fallback to the filter when the predicted RMSE exceeds the threshold)
+    and score both outputs against `ref`, the FP64 oracle's 50-step output of
+    that cube (the GPU filter's output when no oracle output is given)."""
     import numpy as np
     import torch
     import igsynth
     import paper_1609_03782_amd as ig
     from paper_1609_03782_amd import surrogate as sg
-    dev = torch.device("cuda:0")
+    dev = x.device
     params = dict(K=2.0, tau=1 / 16, n_iter=N_ITER, cond="pm_exp")
     t0 = time.perf_counter()
-    xs_np = igsynth.train_set(range(100000, 100000 + args.train), n=args.cube, workers=16)
-    log = lambda m: print(m, file=sys.stderr, flush=True)
-    log(f"generated {len(xs_np)} training cubes in {time.perf_counter() - t0:.1f} s")
-    xs = [torch.from_numpy(c).to(dev) for c in xs_np]
-    del xs_np
+    xs = [torch.from_numpy(c).to(dev) for c in igsynth.train_set(range(100000, 100000 + n_train), n=cube, workers=16)]
     ts = sg.filter_targets(xs, n_iter=N_ITER)
-    torch.cuda.synchronize()
-    log(f"filtered targets ready at {time.perf_counter() - t0:.1f} s")
-    vx_np = igsynth.train_set(range(200000, 200000 + args.val), n=args.cube, workers=16)
-    vxs = [torch.from_numpy(c).to(dev) for c in vx_np]
+    vxs = [torch.from_numpy(c).to(dev) for c in igsynth.train_set(range(200000, 200000 + n_val), n=cube, workers=16)]
     vts = sg.filter_targets(vxs, n_iter=N_ITER)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    net = sg.Surrogate(depth=8, lr=args.lr, seed=0)
+    if log:
+        log(f"surrogate data: {n_train} + {n_val} cubes of {cube}^3 with targets in {t_data:.1f} s")
+    net = sg.Surrogate(depth=8, lr=lr, seed=0)
     t0 = time.perf_counter()
-    losses = sg.train(net, xs, ts, epochs=args.epochs, batch=args.batch, log=log)
-    torch.cuda.synchronize()
+    steps, curve, losses = train_with_budget(net, xs, ts, budget_s, batch, lr, log=log)
     t_train = time.perf_counter() - t0
-    log(f"trained {len(losses)} steps in {t_train:.1f} s")
     slope, pairs = sg.calibrate(net, vxs, vts, params)
-    log(f"calibrated slope {slope:.4g} on {len(pairs)} validation cubes")
-    val_rmse = float(np.mean([e for _, e in pairs]))
-    del xs, ts
-    cube = igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])
-    x = torch.from_numpy(cube).to(dev)
-    f = ig.Filter(cube.shape, **params)
-    plain = torch.empty_like(x)
-    ms_plain, _ = time_runs(f, x, plain, 5, 2)
-    y, rep = net.infer_checked(x, params, slope=slope, threshold=args.threshold)
+    val_rmse = float(np.sqrt(np.mean([e * e for _, e in pairs])))
+    del xs, ts, vxs, vts
+    torch.cuda.empty_cache()
+    # the 512^3 cube: forward alone, then the checked path
+    ysur = net.infer(x)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        y, rep = net.infer_checked(x, params, slope=slope, threshold=args.threshold)
-    torch.cuda.synchronize()
-    ms_checked = (time.perf_counter() - t0) / 3 * 1e3
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    ysur = net.infer(x)
+    for _ in range(3):
+        ysur = net.infer(x)
     e1.record()
     torch.cuda.synchronize()
-    ms_infer = e0.elapsed_time(e1)
-    # break-even iteration count: the plain filter costs about a + b n; the
-    # surrogate path one forward pass plus the two-step residual check
+    ms_fwd = e0.elapsed_time(e1) / 3
+    f2 = ig.Filter(tuple(x.shape), **dict(params, n_iter=2))
     tmp = torch.empty_like(x)
-    f10 = ig.Filter(cube.shape, **dict(params, n_iter=10))
-    ms10, _ = time_runs(f10, x, tmp, 5, 2)
-    f2 = ig.Filter(cube.shape, **dict(params, n_iter=2))
     ms2, _ = time_runs(f2, x, tmp, 5, 2)
     del tmp
-    slope_ms = (ms_plain - ms10) / (params["n_iter"] - 10)
-    icpt_ms = ms10 - 10 * slope_ms
-    ms_sur_path = ms_infer + ms2
-    n_break = (ms_sur_path - icpt_ms) / slope_ms
-    rmse_sur = float(torch.sqrt(torch.mean((ysur.double() - plain.double()) ** 2)).item()) / rep["rho"]
-    rmse_out = float(torch.sqrt(torch.mean((y.double() - plain.double()) ** 2)).item()) / rep["rho"]
-    flops = 335232.0 * cube.size
-    res = {"metric": "surrogate speedup vs plain GPU filter at RMSE <= 0.05 sigma", "value": round(ms_plain / ms_checked, 4),
-           "unit": "x", "higher_is_better": True, "n_gpus": 1, "dtype": "bf16", "data": "synthetic",
-           "config": {"workload": "8-layer 32-channel 3x3x3 CNN, bf16 MFMA, trained on filter-generated pairs, "
-                                  "checked inference on the 512^3 cube",
-                      "train_cubes": args.train, "val_cubes": args.val, "cube": args.cube, "epochs": args.epochs,
-                      "batch": args.batch, "lr": args.lr},
-           "ms_plain_filter": round(ms_plain, 3), "ms_checked_inference": round(ms_checked, 3),
-           "ms_surrogate_forward": round(ms_infer, 3),
-           "forward_TFLOPs": round(flops / ms_infer / 1e9, 2),
-           "rmse_surrogate_vs_filter_sigma": rmse_sur, "rmse_output_vs_filter_sigma": rmse_out,
-           "fell_back": rep["fell_back"], "residual": rep["residual"], "slope": slope,
-           "threshold": args.threshold, "val_rmse_mean_sigma": val_rmse,
-           "loss_first": losses[0] if losses else None, "loss_last": float(np.mean(losses[-20:])) if losses else None,
-           "s_data": round(t_data, 1), "s_train": round(t_train, 1),
-           "plain_ms_per_iteration": round(slope_ms, 4), "plain_ms_fixed": round(icpt_ms, 4),
-           "ms_surrogate_path": round(ms_sur_path, 3),
-           "breakeven_n": round(n_break, 1),
-           "breakeven_note": "iterations at which the plain filter (fixed + per-iteration cost, fitted from 10 and "
-                             "the configured n) costs as much as one forward pass plus the 2-step residual check"}
+    y, rep = net.infer_checked(x, params, slope=slope, threshold=threshold)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(2):
+        y, rep = net.infer_checked(x, params, slope=slope, threshold=threshold)
+    torch.cuda.synchronize()
+    ms_checked = (time.perf_counter() - t1) / 2 * 1e3
+    against = "FP64 oracle"
+    if ref is None:
+        fpl = ig.Filter(tuple(x.shape), **params)
+        ref = fpl.run(x).double().cpu().numpy()
+        rho = rep["rho"]
+        against = "GPU FP32 filter (no oracle output in this run)"
+    ysn = ysur.cpu().numpy().astype(np.float64)
+    rmse_sur = float(np.sqrt(np.mean((ysn - ref) ** 2))) / rho
+    del ysn
+    yn = y.cpu().numpy().astype(np.float64)
+    rmse_out = float(np.sqrt(np.mean((yn - ref) ** 2))) / rho
+    del yn
+    gate = rmse_sur <= threshold
+    flops = 335232.0 * x.numel()
+    return {
+        "value": round(ms_plain / ms_checked, 4) if gate else None,
+        "unit": "x (plain GPU filter time / checked surrogate time)",
+        "gate_rmse_sigma": threshold, "gate_met": gate,
+        "rmse_surrogate_sigma": rmse_sur, "rmse_checked_output_sigma": rmse_out, "rmse_against": against,
+        "fell_back": bool(rep["fell_back"]), "residual_sigma": rep["residual"],
+        "predicted_rmse_sigma": rep["predicted_rmse"], "calibration_slope": slope,
+        "val_rmse_sigma": val_rmse, "val_cubes": n_val,
+        "ms_plain_filter": round(ms_plain, 4), "ms_checked_path": round(ms_checked, 3),
+        "ms_forward": round(ms_fwd, 3), "ms_two_plain_steps": round(ms2, 4),
+        "speedup_checked_path": round(ms_plain / ms_checked, 4),
+        "speedup_forward_plus_check": round(ms_plain / (ms_fwd + ms2), 4),
+        "forward_TFLOPs_bf16": round(flops / ms_fwd / 1e9, 1),
+        "training": {"cubes": n_train, "cube": cube, "batch": batch, "steps": steps, "budget_s": budget_s,
+                     "s_train": round(t_train, 1), "s_data": round(t_data, 1), "lr": lr,
+                     "schedule": "linear warm-up over 300 steps, then cosine to 0.02 lr", "loss_first": losses[0],
+                     "loss_last100": float(np.mean(losses[-100:])), "curve": curve[::max(1, len(curve) // 12)]},
+        "network": "8 conv3d 3x3x3 layers (1-32-...-32-1), GELU, residual to input, bf16 weights/activations, "
+                   "FP32 accumulate on MFMA",
+    }
+
+
+def bench_conv(args):
+    """--workload conv: the surrogate's kernels alone, for profiling: 20
+    training steps (batch 4) on 96^3 cubes and 2 forward passes over the
+    512^3 cube, untrained network; prints their times."""
+    import torch
+    import igsynth
+    import paper_1609_03782_amd as ig
+    from paper_1609_03782_amd import surrogate as sg
+    dev = torch.device("cuda:0")
+    xs = [torch.from_numpy(igsynth.train_cube(100000 + k, 96)).to(dev) for k in range(8)]
+    ts = sg.filter_targets(xs, n_iter=N_ITER)
+    net = sg.Surrogate(depth=8, lr=4e-4, seed=0)
+    for k in range(3):
+        net.train_step(xs[4 * (k % 2):4 * (k % 2) + 4], ts[4 * (k % 2):4 * (k % 2) + 4], want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(20):
+        net.train_step(xs[4 * (k % 2):4 * (k % 2) + 4], ts[4 * (k % 2):4 * (k % 2) + 4], want_loss=False)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / 20 * 1e3
+    x = torch.from_numpy(igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])).to(dev)
+    y = net.infer(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        y = net.infer(x)
+    torch.cuda.synchronize()
+    ms_fwd = (time.perf_counter() - t0) / 2 * 1e3
+    step_flop = 3 * 335232.0 * 4 * 96 ** 3
+    print(json.dumps({"workload": "surrogate kernels: 20 training steps (4 x 96^3) + 2 forward passes (512^3)",
+                      "ms_train_step": round(ms_step, 3), "train_TFLOPs": round(step_flop / ms_step / 1e9, 1),
+                      "ms_forward_512": round(ms_fwd, 3),
+                      "forward_TFLOPs": round(335232.0 * x.numel() / ms_fwd / 1e9, 1)}), flush=True)
+
+
+def bench_surrogate(args):
+    """--workload surrogate: the C5 leg alone, with its own budget, printed
+    as its own JSON line (scored against the FP64 oracle unless --no-cpu)."""
+    import torch
+    import igsynth
+    import paper_1609_03782_amd as ig
+    dev = torch.device("cuda:0")
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    cube = igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])
+    x = torch.from_numpy(cube).to(dev)
+    f = ig.Filter(cube.shape, K=2.0, tau=1 / 16, n_iter=N_ITER, cond="pm_exp")
+    ms_plain, _ = time_runs(f, x, torch.empty_like(x), 10, 3)
+    ref = rho = None
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        ref, rho = oracle.run(cube, "pm_exp", K=2.0, tau=1 / 16, n_iter=N_ITER)
+    res = surrogate_c5(x, ms_plain, ref, rho, budget_s=args.budget, n_train=args.train, n_val=args.val,
+                       cube=args.cube, batch=args.batch, lr=args.lr, threshold=args.threshold, log=log)
+    res["metric"] = "surrogate speedup vs plain GPU filter at RMSE <= 0.05 sigma (512^3 cube)"
     print(json.dumps(res), flush=True)
 
 
@@ -567,13 +673,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
-    ap.add_argument("--workload", default="filter", choices=["filter", "surrogate"])
+    ap.add_argument("--workload", default="filter", choices=["filter", "surrogate", "conv"])
     ap.add_argument("--train", type=int, default=4000)
-    ap.add_argument("--val", type=int, default=200)
+    ap.add_argument("--val", type=int, default=50)
     ap.add_argument("--cube", type=int, default=96)
-    ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--budget", type=float, default=90.0, help="surrogate training seconds")
     ap.add_argument("--batch", type=int, default=4)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=4e-4)
     ap.add_argument("--threshold", type=float, default=0.05)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of the cube size (counter calibration)")
@@ -606,6 +712,9 @@ def main():
         return
     if args.workload == "surrogate":
         bench_surrogate(args)
+        return
+    if args.workload == "conv":
+        bench_conv(args)
         return
 
     cube = igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])
@@ -691,13 +800,19 @@ def main():
         extras["smoothing_512"] = bench_smooth(x)
         extras["wavelet_512"] = bench_wavelet(x)
         res["extras"] = extras
+    ref = rho = None
     if not args.no_cpu:
         y32 = out.cpu().numpy()
         res["cpu_baseline"], ref, rho = cpu_baseline(cube, N_ITER, K, tau)
         outs16["f32"] = (y32, ms_step)
         res["errors_vs_fp64_oracle"] = errors_vs_oracle(outs16, ref, rho, ms_step)
         res["errors_vs_fp64_oracle"]["f32_storage_floor"] = storage_floor(cube, ref, rho, N_ITER, K, tau)
-        del ref
+    if not args.no_extras and args.budget > 0:
+        log = lambda m: print(m, file=sys.stderr, flush=True)
+        res["extras"]["surrogate_c5"] = surrogate_c5(x, ms_step, ref, rho, budget_s=args.budget, n_train=args.train,
+                                                     n_val=args.val, cube=args.cube, batch=args.batch, lr=args.lr,
+                                                     threshold=args.threshold, log=log)
+    del ref
     print(json.dumps(res), flush=True)
 
 
