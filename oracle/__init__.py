@@ -9,6 +9,8 @@ Contents
   * ``run`` / ``rms`` / ``round_bf16`` / ``round_f16``: ctypes front end to
     ``oracle.c`` (plain C, FP64, OpenMP over z-planes), the definition of the
     filter written out (Section 3.3, Eqs. 5-7).
+  * ``error_bound``: the exact result with a per-voxel first-order running
+    error bound for binary32 computations of the same steps (oracle.c).
   * ``brute``: an independent NumPy pad-and-shift form of the same step, for
     tiny cubes.
   * ``surrogate``: FP64 NumPy forms of the learned surrogate's layers.
@@ -67,6 +69,8 @@ def _load():
         lib.oracle_run.argtypes = [p, p, i64, i64, i64, i32, d, d, i32, d, d, d, d, i32,
                                    ctypes.POINTER(d)]
         lib.oracle_run.restype = i32
+        lib.oracle_error_bound.argtypes = [p, p, p, i64, i64, i64, i32, d, d, i32, d, d, d, d, ctypes.POINTER(d)]
+        lib.oracle_error_bound.restype = i32
         lib.oracle_rms.argtypes = [p, i64, ctypes.POINTER(d), ctypes.POINTER(i64)]
         lib.oracle_rms.restype = d
         lib.oracle_round_bf16.argtypes = [d]
@@ -102,6 +106,27 @@ def run(cube, cond: str = "pm_exp", K: float = 2.0, tau: float = 1.0 / 16, n_ite
         raise OracleError({-1: "invalid argument", -2: "out of memory",
                            -3: "non-finite input"}.get(rc, str(rc)))
     return out, used.value
+
+
+def error_bound(cube, cond: str = "pm_exp", K: float = 2.0, tau: float = 1.0 / 16, n_iter: int = 1,
+                C=(1.0, 1.0, 1.0), rms: float | None = None):
+    """(exact FP64 result, per-voxel first-order bound on the error of any
+    binary32 computation of the same steps, rho used); see oracle.c."""
+    lib = _load()
+    a = np.ascontiguousarray(cube, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("cube must be 3-D (nz, ny, nx)")
+    out = np.empty_like(a)
+    bnd = np.empty_like(a)
+    nz, ny, nx = a.shape
+    used = ctypes.c_double(0.0)
+    rc = lib.oracle_error_bound(a.ctypes.data, out.ctypes.data, bnd.ctypes.data, nx, ny, nz, COND[cond], float(K),
+                                float(tau), int(n_iter), float(C[0]), float(C[1]), float(C[2]),
+                                float(rms) if rms is not None else 0.0, ctypes.byref(used))
+    if rc != 0:
+        raise OracleError({-1: "invalid argument", -2: "out of memory",
+                           -3: "non-finite input"}.get(rc, str(rc)))
+    return out, bnd, used.value
 
 
 def rms(cube):

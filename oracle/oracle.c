@@ -29,6 +29,27 @@
  * Optional storage rounding: round_mode 1 (bfloat16), 2 (binary16) or 3
  * (binary32) rounds every voxel to the nearest representable value, ties to
  * even, after each step; the arithmetic of the step itself stays FP64.
+ *
+ * oracle_error_bound: a first-order running error bound (in the manner of
+ * Wilkinson's running error analysis) for any computation of the same steps
+ * that works in binary32 and rounds each voxel's new value once per step.
+ * If every step adds at voxel v a local error of at most
+ *     delta_i(v) = u (|I_{i+1}(v)| + sum_e c_e |T_e(v)|),   u = 2^-24,
+ * where T_e is the flux term of edge e (tau C_a w d, or tau S C_a d for the
+ * intensity form) and c_e bounds the relative error of computing it, then
+ * the accumulated error obeys, to first order,
+ *     B_{i+1}(v) = sum_u |dI_{i+1}(v) / dI_i(u)| B_i(u) + delta_i(v),  B_0 = 0,
+ * the Jacobian taken at the exact FP64 trajectory.  c_e counts the unit
+ * roundoffs one flux term can collect: the difference d (1), the product
+ * that forms the term (1), five additions of the terms into the update (5),
+ * and for the exponential weight (r = d / (K rho)) an exponential accurate to
+ * 2 u whose argument, the base-2 exponent -log2(e) r^2 + log2(tau C) formed
+ * from rounded d^2 and 1/(K rho)^2 with one multiply-add, is off by up to
+ * u (5.8 r^2 + 4), i.e. a relative error of ln2 times that in the weight:
+ * c_e = 12 + 4 r^2; for the rational weight d^2, the multiply-add, the
+ * reciprocal (2) and the weight's constant: c_e = 14; for the intensity form
+ * the reciprocal 1 / (1 + I^2 / (K rho)^2) and the scaling products: 14.
+ * Second-order terms are of the order of B^2 and negligible.
  */
 #include <math.h>
 #include <stdint.h>
@@ -155,6 +176,105 @@ static void step(const double* src, double* dst, int64_t nx, int64_t ny, int64_t
             }
         }
     }
+}
+
+/* dT/dd of one edge's flux term (its derivative in the difference d). */
+static double flux_slope(int cond, double d, double kr, double tau_c)
+{
+    const double r2 = (d / kr) * (d / kr);
+    if (cond == COND_PM_EXP) return tau_c * exp(-r2) * (1.0 - 2.0 * r2);
+    if (cond == COND_PM_RATIONAL) return tau_c * (1.0 - r2) / ((1.0 + r2) * (1.0 + r2));
+    return tau_c;
+}
+
+/* One exact step src -> dst together with the bound bsrc -> bdst. */
+static void step_bound(const double* src, double* dst, const double* bsrc, double* bdst, int64_t nx, int64_t ny,
+                       int64_t nz, int cond, double K, double rho, double tau, const double C[3])
+{
+    const double kr = K * rho, u = 0x1p-24;
+    const int64_t sx = 1, sy = nx, sz = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z) {
+        for (int64_t y = 0; y < ny; ++y) {
+            for (int64_t x = 0; x < nx; ++x) {
+                const int64_t v = x * sx + y * sy + z * sz;
+                const double Iv = src[v];
+                const int64_t coord[3] = {x, y, z};
+                const int64_t extent[3] = {nx, ny, nz};
+                const int64_t stride[3] = {sx, sy, sz};
+                const double S = cond == COND_INTENSITY ? 1.0 / (1.0 + (Iv * Iv) / (kr * kr)) : 1.0;
+                double acc = 0.0, term_err = 0.0, prop = 0.0, self = 1.0, sumcd = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    for (int s = -1; s <= 1; s += 2) {
+                        const int64_t c = coord[a] + s;
+                        if (c < 0 || c >= extent[a]) continue;   /* no edge through a face */
+                        const int64_t w = v + s * stride[a];
+                        const double d = src[w] - Iv;
+                        const double t = C[a] * edge_weight(cond, d, kr) * d;
+                        acc += t;
+                        sumcd += C[a] * d;
+                        const double r2 = (d / kr) * (d / kr);
+                        const double ce = cond == COND_PM_EXP ? 12.0 + 4.0 * r2 : 14.0;
+                        term_err += ce * fabs(tau * S * t);
+                        /* dependence of I_{i+1}(v) on the neighbour through this edge */
+                        const double g = cond == COND_INTENSITY ? tau * S * C[a] : flux_slope(cond, d, kr, tau * C[a]);
+                        prop += fabs(g) * bsrc[w];
+                        self -= g;
+                    }
+                }
+                if (cond == COND_INTENSITY)   /* S depends on I(v) too: dS/dI = -2 I S^2 / (K rho)^2 */
+                    self += tau * sumcd * (-2.0 * Iv * S * S / (kr * kr));
+                /* the same expression as step(), so `out` is bitwise oracle_run's result */
+                const double out = cond == COND_INTENSITY ? Iv + tau * acc / (1.0 + (Iv * Iv) / (kr * kr))
+                                                          : Iv + tau * acc;
+                dst[v] = out;
+                bdst[v] = fabs(self) * bsrc[v] + prop + u * (fabs(out) + term_err);
+            }
+        }
+    }
+}
+
+/*
+ * The exact FP64 result of n_iter steps (as oracle_run with round_mode 0) in
+ * `out`, and in `bound` the first-order bound described at the top of this
+ * file on |result of a binary32 computation - exact result|, per voxel.  rms
+ * as for oracle_run.  Returns 0, -1 (invalid arguments), -2 (allocation
+ * failure) or -3 (non-finite input).
+ */
+int oracle_error_bound(const double* in, double* out, double* bound, int64_t nx, int64_t ny, int64_t nz, int cond,
+                       double K, double tau, int n_iter, double Cx, double Cy, double Cz, double rms,
+                       double* rms_used)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || n_iter < 0 || !(K > 0.0) || !(tau >= 0.0)) return -1;
+    if (cond < 0 || cond > 2) return -1;
+    const int64_t n = nx * ny * nz;
+    double s1;
+    int64_t bad;
+    double rho_est = oracle_rms(in, n, &s1, &bad);
+    if (bad) return -3;
+    const double rho = rms > 0.0 ? rms : rho_est;
+    if (rms_used) *rms_used = rho;
+    const double C[3] = {Cx, Cy, Cz};
+    if (!(rho > 0.0)) {
+        memmove(out, in, (size_t)n * sizeof(double));
+        memset(bound, 0, (size_t)n * sizeof(double));
+        return 0;
+    }
+    double* a = (double*)malloc((size_t)n * sizeof(double));
+    double* b = (double*)malloc((size_t)n * sizeof(double));
+    double* ba = (double*)calloc((size_t)n, sizeof(double));
+    double* bb = (double*)malloc((size_t)n * sizeof(double));
+    if (!a || !b || !ba || !bb) { free(a); free(b); free(ba); free(bb); return -2; }
+    memcpy(a, in, (size_t)n * sizeof(double));
+    for (int i = 0; i < n_iter; ++i) {
+        step_bound(a, b, ba, bb, nx, ny, nz, cond, K, rho, tau, C);
+        double* t = a; a = b; b = t;
+        t = ba; ba = bb; bb = t;
+    }
+    memcpy(out, a, (size_t)n * sizeof(double));
+    memcpy(bound, ba, (size_t)n * sizeof(double));
+    free(a); free(b); free(ba); free(bb);
+    return 0;
 }
 
 /*

@@ -28,74 +28,110 @@ def field(dev):
     return cube, torch.from_numpy(cube).to(dev)
 
 
-def _points(cube, rng, extra=()):
+CONFIGS = [("pm_exp", 2.0, 1 / 16, 50, 1.0), ("intensity", 1.5, 0.0325, 20, 5.0)]
+_cache = {}
+
+
+def _whole_cube(dev, field, oracle_lib, cond, K, tau, n, C):
+    """GPU output of the 512^3 workload in the launch configuration bench.py
+    times, and on the CPU: the FP64 oracle's result, its per-voxel
+    first-order error bound for any binary32 computation of the same steps,
+    and the binary32-storage run (FP64 arithmetic, state rounded to binary32
+    after every step).  Computed once per configuration."""
+    key = (cond, K, tau, n, C)
+    if key not in _cache:
+        import torch
+        import paper_1609_03782_amd as ig
+        cube, x = field
+        f = ig.Filter(cube.shape, K=K, tau=tau, n_iter=n, C=(C, C, C), cond=cond)
+        y, st = f.run(x, stats=True)
+        torch.cuda.synchronize()
+        rho = st.rms_used
+        got = y.cpu().numpy().astype(np.float64)
+        ymax, ymin = float(y.max()), float(y.min())
+        del y
+        ref, B, _ = oracle_lib.error_bound(cube, cond, K=K, tau=tau, n_iter=n, C=(C, C, C), rms=rho)
+        r32, _ = oracle_lib.run(cube, cond, K=K, tau=tau, n_iter=n, C=(C, C, C), rms=rho, round_to="f32")
+        _cache[key] = dict(st=st, rho=rho, got=got, ref=ref, B=B, r32=r32, ymax=ymax, ymin=ymin)
+    return _cache[key]
+
+
+def _seams_and_extremes(cube, rng):
     nz, ny, nx = cube.shape
     pts = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (0, ny - 1, 0), (nz - 1, 0, nx - 1), (nz // 2, 0, nx // 2),
            (0, ny // 2, nx - 1), (nz - 1, ny // 2, 7)]
     pts += [tuple(int(v) for v in np.unravel_index(int(np.argmax(cube)), cube.shape))]
-    pts += [tuple(int(rng.integers(0, e)) for e in cube.shape) for _ in range(10)]
+    pts += [tuple(int(rng.integers(0, e)) for e in cube.shape) for _ in range(16)]
     # tile and piece seams of the streaming kernel (rows 11/12, planes near piece ends)
     pts += [(85, 11, 100), (86, 12, 511), (171, 23, 0), (255, 24, 256)]
-    return pts + list(extra)
+    return pts
 
 
-@pytest.mark.parametrize("cond,K,tau,n,C", [("pm_exp", 2.0, 1 / 16, 50, 1.0), ("intensity", 1.5, 0.0325, 20, 5.0)])
-def test_fullsize_sampled_parity(dev, field, oracle_lib, cond, K, tau, n, C):
-    import torch
-    import paper_1609_03782_amd as ig
-    cube, x = field
-    f = ig.Filter(cube.shape, K=K, tau=tau, n_iter=n, C=(C, C, C), cond=cond)
-    y, st = f.run(x, stats=True)
-    torch.cuda.synchronize()
-    rho = st.rms_used
-    r_or, s_or, _ = oracle_lib.rms(cube)
-    # the oracle sums the 1.3e8 squares one after another: recursive summation
-    # in FP64 is exact to (N-1) u sum|x^2| (u = 2^-53), so rho to half of that
-    assert rho == pytest.approx(r_or, rel=0.5 * cube.size * 2.0 ** -53 + 1e-15)
-    rng = np.random.default_rng(n)
-    pts = _points(cube, rng)
-    ref = oracle_lib.run_points(cube, pts, cond, K=K, tau=tau, n_iter=n, C=(C, C, C), rms=rho)
-    yh = y.cpu().numpy()
-    got = np.array([yh[p] for p in pts], dtype=np.float64)
-    err = np.abs(got - ref).max()
-    print(f"512^3 {cond} n={n}: sampled max-abs {err:.3e} = {err / rho:.3e} rms over {len(pts)} voxels")
-    assert err <= TOL * rho
-    if cond == "pm_exp":   # per-edge flux form conserves the sum
-        assert abs(st.sum_out - st.sum_in) <= 1e-9 * np.abs(cube).astype(np.float64).sum()
-    # maximum principle (2 tau sum C <= 1 for both settings)
-    assert float(y.max()) <= float(x.max()) and float(y.min()) >= float(x.min())
-
-
-@pytest.mark.parametrize("cond,K,tau,n,C", [("pm_exp", 2.0, 1 / 16, 50, 1.0), ("intensity", 1.5, 0.0325, 20, 5.0)])
-def test_fullsize_whole_cube_vs_fp64_oracle(dev, field, oracle_lib, cond, K, tau, n, C):
-    """Every voxel of the 512^3 result against the FP64 oracle.  Where the
-    conductance falls faster than the difference grows (|difference| above
-    K rho / sqrt 2 for the exponential form) the equation amplifies any
-    perturbation step after step, so the bound is 1e-5 rho or, where that is
-    larger, twice what rounding the oracle's state to binary32 after every
-    step (FP64 arithmetic otherwise) already costs."""
-    import torch
-    import paper_1609_03782_amd as ig
-    cube, x = field
-    f = ig.Filter(cube.shape, K=K, tau=tau, n_iter=n, C=(C, C, C), cond=cond)
-    y, st = f.run(x, stats=True)
-    torch.cuda.synchronize()
-    rho = st.rms_used
-    got = y.cpu().numpy()
-    del y
-    ref, _ = oracle_lib.run(cube, cond, K=K, tau=tau, n_iter=n, C=(C, C, C), rms=rho)
-    d = np.abs(got.astype(np.float64) - ref)
-    del got
-    r32, _ = oracle_lib.run(cube, cond, K=K, tau=tau, n_iter=n, C=(C, C, C), rms=rho, round_to="f32")
+@pytest.mark.parametrize("cond,K,tau,n,C", CONFIGS)
+def test_fullsize_whole_cube_within_error_bound(dev, field, oracle_lib, cond, K, tau, n, C):
+    """Every voxel of the 512^3 result against the FP64 oracle, bounded per
+    voxel by the first-order running error bound of a binary32 computation of
+    the same steps (derived from the arithmetic; it grows only where the
+    equation itself amplifies perturbations: for the exponential conductance
+    along edges with |difference| above K rho / sqrt 2, where the flux falls
+    as the difference grows).  Beside it, the error distribution is that of
+    the binary32-storage run, another binary32 computation of the same steps
+    (a GPU step's local error has the spread of one binary32 rounding of the
+    new value, because the flux terms it rounds are at most |d| / 16)."""
+    r = _whole_cube(dev, field, oracle_lib, cond, K, tau, n, C)
+    rho, got, ref, B, r32 = r["rho"], r["got"], r["ref"], r["B"], r["r32"]
+    d = np.abs(got - ref)
     fl = np.abs(r32 - ref)
-    del r32, ref
+    ratio = d / B
+    worst = int(np.argmax(ratio))
     e_max, e_rms, e_cnt = d.max() / rho, np.sqrt(np.mean(d * d)) / rho, int((d > TOL * rho).sum())
     f_max, f_rms, f_cnt = fl.max() / rho, np.sqrt(np.mean(fl * fl)) / rho, int((fl > TOL * rho).sum())
     print(f"512^3 {cond} n={n} whole cube, in rms: GPU max {e_max:.3e} rmse {e_rms:.3e} over-1e-5 {e_cnt}; "
-          f"binary32-storage floor max {f_max:.3e} rmse {f_rms:.3e} over-1e-5 {f_cnt}")
-    assert e_max <= max(TOL, 2 * f_max)
-    assert e_rms <= 2 * f_rms
-    assert e_cnt <= 2 * f_cnt
+          f"binary32-storage run max {f_max:.3e} rmse {f_rms:.3e} over-1e-5 {f_cnt}; "
+          f"largest error / bound {ratio.max():.3f} (bound there {B.flat[worst] / rho:.3e}); "
+          f"bound median {np.median(B) / rho:.3e}, voxels with bound > 1e-5: {int((B > TOL * rho).sum())}")
+    assert ratio.max() <= 1.0
+    if cond == "pm_exp":
+        # tau C = 1/16: the flux terms a step rounds are at most |d| / 16, so
+        # its local error is one binary32 rounding of the new value, as in the
+        # storage run (the intensity form at C = 5 rounds larger flux terms and
+        # a reciprocal, and is held to the bound alone)
+        assert e_rms <= 1.25 * f_rms
+        assert e_cnt <= 1.5 * f_cnt + 10
+
+
+@pytest.mark.parametrize("cond,K,tau,n,C", CONFIGS)
+def test_fullsize_sampled_parity(dev, field, oracle_lib, cond, K, tau, n, C):
+    """Voxels the oracle computes one by one from their own n-neighbourhood
+    (run_points), at the 48 voxels where the binary32-storage run strays
+    furthest from the exact result (chosen on the CPU: where rounding is
+    amplified most, so where a wrong kernel would show too), at seams and
+    extremes and at random: within the per-voxel bound, which is below
+    1e-5 rho wherever the equation does not amplify."""
+    r = _whole_cube(dev, field, oracle_lib, cond, K, tau, n, C)
+    cube, _ = field
+    rho, got, B, r32, ref = r["rho"], r["got"], r["B"], r["r32"], r["ref"]
+    worst = np.argsort(np.abs(r32 - ref).ravel())[-48:]
+    pts = [tuple(int(v) for v in np.unravel_index(int(k), cube.shape)) for k in worst]
+    pts += _seams_and_extremes(cube, np.random.default_rng(n))
+    vals = oracle_lib.run_points(cube, pts, cond, K=K, tau=tau, n_iter=n, C=(C, C, C), rms=rho)
+    err = np.array([abs(got[p] - v) for p, v in zip(pts, vals)])
+    bnd = np.array([B[p] for p in pts])
+    print(f"512^3 {cond} n={n}: {len(pts)} sampled voxels, max error {err.max() / rho:.3e} rms, "
+          f"max error / bound {np.max(err / bnd):.3f}; at the 48 most amplifying voxels the error reaches "
+          f"{err[:48].max() / rho:.3e} rms")
+    assert np.all(err <= bnd)
+    easy = bnd <= TOL * rho
+    assert np.all(err[easy] <= TOL * rho)
+    # rho of the GPU scan: recursive FP64 summation of the 1.3e8 squares is
+    # exact to (N-1) u sum|x^2| (u = 2^-53), so rho to half of that
+    r_or, _, _ = oracle_lib.rms(cube)
+    assert rho == pytest.approx(r_or, rel=0.5 * cube.size * 2.0 ** -53 + 1e-15)
+    st = r["st"]
+    if cond == "pm_exp":   # per-edge flux form conserves the sum
+        assert abs(st.sum_out - st.sum_in) <= 1e-9 * np.abs(cube).astype(np.float64).sum()
+    # maximum principle (2 tau sum C <= 1 for both settings)
+    assert r["ymax"] <= float(cube.max()) and r["ymin"] >= float(cube.min())
 
 
 def _ulp_at(mag, dtype):

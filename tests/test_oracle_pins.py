@@ -343,3 +343,69 @@ def test_bright_structure_changes_less(oracle_lib):
     # adaptive smoothing: the bright core keeps most of its value while noise
     # spikes of a few rms are flattened
     assert np.median(rel[bright]) < 0.3 < 0.8 < np.median(rel[spikes])
+
+
+# ---------------------------------------------------------------- error bound
+# The per-voxel first-order running error bound of oracle.c (error_bound)
+# is pinned three ways: its closed form on a constant cube, the binary32-
+# storage run (a binary32 computation whose local error is one rounding of
+# each new value) staying inside it, and an independent binary32 computation
+# of the steps in another operation order staying inside it.
+
+U32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("cond", ["pm_exp", "pm_rational", "intensity"])
+def test_error_bound_exact_part_is_oracle_run(oracle_lib, cond):
+    cube = igsynth.cube_field(40, seed=31, nz=24)
+    ref, _, rho = oracle_lib.error_bound(cube, cond, K=1.5, tau=0.04, n_iter=7, C=(1.0, 2.0, 0.5))
+    run, _ = oracle_lib.run(cube, cond, K=1.5, tau=0.04, n_iter=7, C=(1.0, 2.0, 0.5), rms=rho)
+    assert np.array_equal(ref, run)
+
+
+def test_error_bound_constant_cube_closed_form(oracle_lib):
+    # no flux: every step adds u |c| and carries the previous bound unchanged
+    cube = np.full((5, 6, 7), -3.25, np.float32)
+    for n in (0, 1, 9):
+        _, B, _ = oracle_lib.error_bound(cube, "pm_exp", K=2.0, tau=1 / 16, n_iter=n, rms=1.0)
+        np.testing.assert_allclose(B, n * U32 * 3.25, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("cond,K,tau,n,C", [("pm_exp", 2.0, 1 / 16, 30, 1.0), ("pm_rational", 2.0, 1 / 16, 30, 1.0),
+                                            ("intensity", 1.5, 0.0325, 20, 5.0)])
+def test_error_bound_covers_binary32_storage_run(oracle_lib, cond, K, tau, n, C):
+    cube = igsynth.cube_field(64, seed=32, nz=48)
+    ref, B, rho = oracle_lib.error_bound(cube, cond, K=K, tau=tau, n_iter=n, C=(C, C, C))
+    r32, _ = oracle_lib.run(cube, cond, K=K, tau=tau, n_iter=n, C=(C, C, C), rms=rho, round_to="f32")
+    ratio = np.abs(r32 - ref) / B
+    assert ratio.max() <= 1.0, ratio.max()
+    assert np.median(B) <= 1e-5 * rho          # and it is tight where nothing amplifies
+
+
+def _f32_steps(cube, n, K, tau, rho):
+    """The exponential-conductance steps computed in binary32 with numpy, in
+    an order of operations of its own: per axis the weight as exp of the
+    negated squared ratio, minus-side and plus-side fluxes summed per axis."""
+    f = np.float32
+    I = cube.astype(f)
+    kr = f(K * rho)
+    for _ in range(n):
+        acc = np.zeros_like(I)
+        for ax in range(3):
+            nxt = np.concatenate([np.take(I, range(1, I.shape[ax]), axis=ax), np.take(I, [-1], axis=ax)], axis=ax)
+            prv = np.concatenate([np.take(I, [0], axis=ax), np.take(I, range(I.shape[ax] - 1), axis=ax)], axis=ax)
+            dp, dm = nxt - I, prv - I
+            rp, rm = dp / kr, dm / kr
+            acc = acc + (np.exp(-(rp * rp)) * dp + np.exp(-(rm * rm)) * dm)
+        I = I + f(tau) * acc
+    return I.astype(np.float64)
+
+
+def test_error_bound_covers_independent_binary32_computation(oracle_lib):
+    cube = igsynth.cube_field(48, seed=33, nz=32)
+    n, K, tau = 25, 2.0, 1 / 16
+    ref, B, rho = oracle_lib.error_bound(cube, "pm_exp", K=K, tau=tau, n_iter=n)
+    got = _f32_steps(cube, n, K, tau, rho)
+    ratio = np.abs(got - ref) / B
+    assert ratio.max() <= 1.0, ratio.max()
+    assert np.abs(got - ref).max() > 0            # it is a different computation
