@@ -79,6 +79,14 @@ ig_status ig_surrogate_checkpoint_info(const char* path, int32_t* depth, int32_t
 ig_status ig_surrogate_set_lr(ig_surrogate* s, float lr);
 int64_t ig_surrogate_get_step(const ig_surrogate* s);
 
+/* Clipping of later training steps by the global gradient norm: when
+ * ||g||_2 (FP64, over every parameter) exceeds max_norm, the step uses
+ * g * max_norm / ||g||; 0 (the default) turns it off.  The factor is computed
+ * and applied on the device.  last_grad_norm waits and returns ||g|| of the
+ * last step (before clipping); IG_ERR_INVALID_ARG before the first step. */
+ig_status ig_surrogate_set_clip(ig_surrogate* s, float max_norm);
+ig_status ig_surrogate_last_grad_norm(const ig_surrogate* s, double* norm);
+
 /* One Adam step on the mean squared error over `batch` cubes of one shape:
  * d_x[k], d_t[k] are device FP32 cubes (input, target).  loss (nullable)
  * receives the mean squared error before the step (the call then waits). */

@@ -135,6 +135,9 @@ SIGNATURES = {
                                           ctypes.c_int64, _P]),
     "ig_wavelet_denoise": (ctypes.c_int, [ctypes.POINTER(IgWaveletParams), _P, _P, ctypes.c_int64, ctypes.c_int64,
                                           ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_double)]),
+    "ig_debug_fail_alloc": (None, [ctypes.c_int64]),
+    "ig_debug_live_allocations": (ctypes.c_int64, []),
+    "ig_debug_release_caches": (None, []),
     "ig_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ig_last_error": (ctypes.c_char_p, []),
     "ig_version": (ctypes.c_char_p, []),

@@ -25,7 +25,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract
 
 
 def _units():
-    units = [("api", "api.cpp", ["-x", "hip"]), ("reduce", "reduce.hip", []), ("batch", "batch.hip", []),
+    units = [("api", "api.cpp", ["-x", "hip"]), ("plan", "plan.cpp", []), ("reduce", "reduce.hip", []), ("batch", "batch.hip", []),
              ("quality", "quality.hip", []), ("sweep", "sweep.cpp", ["-x", "hip"]),
              ("smooth", "smooth.hip", []), ("wavelet", "wavelet.hip", []),
              ("noalloc", "noalloc.hip", [])]

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -11,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "igdebug.h"
 #include "igfilter.h"
 #include "internal.h"
 #include "stencil_kernels.h"
@@ -39,19 +41,6 @@ const StencilLaunch* stencil_table(int cond, int dtype) {
 }
 }  // namespace igk
 
-// ------------------------------------------------------------------ errors
-static thread_local std::string g_last_error;
-
-ig_status igk_fail(ig_status s, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return s;
-}
-
 #define fail igk_fail
 #define HIP_TRY(expr)                                                                              \
     do {                                                                                           \
@@ -73,8 +62,68 @@ extern "C" const char* ig_status_string(ig_status s) {
     return "unknown status";
 }
 
-extern "C" const char* ig_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char* ig_version(void) { return "0.1.0"; }
+
+// ------------------------------------------------------------------ allocation
+// Every device (and pinned host) allocation of the library goes through
+// igk_malloc / igk_host_malloc: they count live allocations and can be made
+// to fail on purpose (ig_debug_fail_alloc, or IG_FAULT_INJECT=alloc[:N] in the
+// environment: the N-th allocation after the library loads, default the
+// first), so the error paths can be tested for their status and their leaks.
+namespace {
+std::atomic<long long> g_live{0};
+std::atomic<long long> g_fail_in{-1};   // > 0: allocations until the injected failure; -1: none
+
+long long fault_env() {
+    const char* e = getenv("IG_FAULT_INJECT");
+    if (!e || strncmp(e, "alloc", 5) != 0) return -1;
+    long long n = 1;
+    if (e[5] == ':') n = atoll(e + 6);
+    return n > 0 ? n : -1;
+}
+struct FaultInit {
+    FaultInit() { g_fail_in = fault_env(); }
+} g_fault_init;
+
+bool inject_failure() {
+    long long cur = g_fail_in.load();
+    while (cur > 0) {
+        if (g_fail_in.compare_exchange_weak(cur, cur - 1)) {
+            if (cur == 1) { g_fail_in = -1; return true; }
+            return false;
+        }
+    }
+    return false;
+}
+}  // namespace
+
+hipError_t igk_malloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (inject_failure()) return hipErrorOutOfMemory;
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) ++g_live;
+    return e;
+}
+void igk_free(void* p) {
+    if (!p) return;
+    (void)hipFree(p);
+    --g_live;
+}
+hipError_t igk_host_malloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (inject_failure()) return hipErrorOutOfMemory;
+    const hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) ++g_live;
+    return e;
+}
+void igk_host_free(void* p) {
+    if (!p) return;
+    (void)hipHostFree(p);
+    --g_live;
+}
+
+extern "C" void ig_debug_fail_alloc(int64_t nth) { g_fail_in = nth > 0 ? nth : -1; }
+extern "C" int64_t ig_debug_live_allocations(void) { return (int64_t)g_live.load(); }
 
 // ------------------------------------------------------------------ device guard
 namespace {
@@ -90,201 +139,7 @@ struct DeviceGuard {
     }
 };
 
-bool finite_f(float v) { return std::isfinite(v); }
 }  // namespace
-
-size_t dtype_size(int dt) { return dt == IG_F32 ? 4 : 2; }
-
-// ------------------------------------------------------------------ validation
-ig_status igk_validate_params(const ig_params* p) {
-    if (!p) return fail(IG_ERR_INVALID_ARG, "params is NULL");
-    if (p->struct_size != sizeof(ig_params))
-        return fail(IG_ERR_INVALID_ARG, "params.struct_size %u != %zu", p->struct_size, sizeof(ig_params));
-    if (p->dtype < IG_F32 || p->dtype > IG_F16) return fail(IG_ERR_INVALID_ARG, "bad dtype %d", p->dtype);
-    if (p->cond < IG_COND_INTENSITY || p->cond > IG_COND_PM_RATIONAL)
-        return fail(IG_ERR_INVALID_ARG, "bad conductance %d", p->cond);
-    if (p->n_iter < 0) return fail(IG_ERR_INVALID_ARG, "n_iter %d < 0", p->n_iter);
-    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
-        return fail(IG_ERR_INVALID_ARG, "shape %lld x %lld x %lld", (long long)p->nx, (long long)p->ny,
-                    (long long)p->nz);
-    if (p->nx > (1LL << 30) || p->ny > (1LL << 30) || p->nz > (1LL << 30) ||
-        p->nx * p->ny * p->nz >= (1LL << 31))
-        return fail(IG_ERR_INVALID_ARG, "cube too large (nx*ny*nz must be < 2^31)");
-    if (!finite_f(p->K) || !(p->K > 0.0f)) return fail(IG_ERR_INVALID_ARG, "K must be finite and > 0");
-    if (!finite_f(p->tau) || !(p->tau >= 0.0f)) return fail(IG_ERR_INVALID_ARG, "tau must be finite and >= 0");
-    for (int a = 0; a < 3; ++a)
-        if (!finite_f(p->C[a]) || !(p->C[a] >= 0.0f))
-            return fail(IG_ERR_INVALID_ARG, "C[%d] must be finite and >= 0", a);
-    if (p->reserved0 != 0.0f) return fail(IG_ERR_INVALID_ARG, "reserved0 must be 0");
-    if (std::isnan(p->rms) || std::isinf(p->rms)) return fail(IG_ERR_INVALID_ARG, "rms must be finite");
-    return IG_OK;
-}
-
-// ------------------------------------------------------------------ schedule
-// Automatic x layout: 8 voxels per lane for 256 < nx <= 512 (one tile), 4
-// per lane in 256-voxel x tiles above 512; up to 256, 4 voxels per lane and as
-// many rows per wavefront as keep one row's lanes covering nx, so narrow cubes
-// still give every lane 4 voxels.
-void auto_vec_rows(int64_t nx, int* V, int* R) {
-    // 8 voxels per lane while one 512-voxel tile holds the row; wider rows
-    // need x tiles, and 256-voxel tiles waste fewer lanes on the last, partly
-    // filled tile (measured on gfx950: 731 against 495 Gvoxel-iter/s at
-    // nx = 1024, 860 against 648 at 2048, 574 against 344 at 600)
-    if (nx > 512) { *V = 4; *R = 1; return; }
-    if (nx > 256) { *V = 8; *R = 1; return; }
-    if (nx < 4) { *V = nx >= 2 ? 2 : 1; *R = 1; return; }   // a lane's chunk never exceeds the row
-    *V = 4;
-    *R = nx <= 64 ? 4 : nx <= 128 ? 2 : 1;
-}
-
-// Workgroups of the streaming kernel one CU holds at once: 16 wavefronts of
-// at most 128 VGPRs each (launch bound of 1024 threads) and 160 KB of LDS.
-int resident_per_cu(int W, size_t lds) {
-    const int by_waves = 16 / W;
-    const int by_lds = (int)(kMaxLds / std::max<size_t>(lds, 1));
-    return std::max(1, std::min(by_waves, by_lds));
-}
-
-// Plan the pass of depth T for schedule s; returns nullptr or the reason it
-// cannot serve the shape.
-const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp) {
-    const int nx = (int)p.nx, ny = (int)p.ny, nz = (int)p.nz;
-    int V = s.vec, R = s.rows;
-    if (V == 0) {
-        int av, ar;
-        auto_vec_rows(p.nx, &av, &ar);
-        V = av;
-        if (R == 0) R = ar;
-    }
-    if (R == 0) R = 1;
-    const int W = s.waves;
-    if (!(V == 1 || V == 2 || V == 4 || V == 8)) return "vec must be 1, 2, 4 or 8";
-    if (V > nx) return "vec must not exceed nx";
-    // a tile's rows of one plane are addressed with 32-bit byte offsets below 2^30
-    if ((long)s.waves * std::max(R, 1) * nx * (long)dtype_size(p.dtype) >= (1L << 30))
-        return "rows too long for the blocked schedule (use naive)";
-    if (!(R == 1 || R == 2 || R == 4)) return "rows must be 1, 2 or 4";
-    if (R > 1 && (V != 4 || (64 / R) * V < nx)) return "rows > 1 needs vec 4 and nx <= 256 / rows";
-    if (W < 1 || W > 16) return "waves must be in 1..16";
-    if (T < 1 || T > 4) return "t_block must be in 1..4";
-    if (s.zchunk < 0 || s.rounds < 0) return "zchunk and rounds must be >= 0";
-    const size_t lds = stream_lds_bytes(V, T, W);
-    if (lds > kMaxLds) return "tile needs more LDS than a CU has (reduce waves, vec or t_block)";
-    BlockGeom& g = pp->g;
-    g.nx = nx; g.ny = ny; g.nz = nz; g.W = W; g.R = R;
-    const int RX = 64 * V;
-    if (nx <= RX) { g.ntx = 1; g.ox = nx; g.hx = 0; }
-    else {
-        // halo of whole lane chunks, so every tile starts at a multiple of V
-        // and the vector path serves cubes wider than one tile
-        g.hx = (T + V - 1) / V * V;
-        g.ox = RX - 2 * g.hx;
-        if (g.ox < 1) return "x tile too narrow for t_block";
-        g.ntx = (nx + g.ox - 1) / g.ox;
-    }
-    if (ny <= W * R) { g.nty = 1; g.oy = ny; }
-    else {
-        g.oy = W * R - 2 * T;
-        if (g.oy < 1) return "too few rows for t_block (need waves * rows > 2 * t_block)";
-        g.nty = (ny + g.oy - 1) / g.oy;
-    }
-    // vector I/O: whole lane chunks (nx a multiple of V) and a tile's rows of
-    // one plane below 2^30 bytes (the buffer offsets of the 16-bit kernels)
-    g.vec = (nx % V == 0 && (long)W * R * nx * (long)dtype_size(p.dtype) < (1L << 30)) ? 1 : 0;
-    pp->V = V;
-    pp->T = T;
-    auto& pcs = pp->pieces;
-    pcs.clear();
-    const long ntiles = (long)g.ntx * g.nty;
-    if (s.zchunk > 0) {
-        const int nzc = (nz + s.zchunk - 1) / s.zchunk;
-        if (ntiles * nzc > (1L << 30)) return "too many pieces";
-        for (int tz = 0; tz < nzc; ++tz)
-            for (int ty = 0; ty < g.nty; ++ty)
-                for (int tx = 0; tx < g.ntx; ++tx)
-                    pcs.push_back(Piece{tx, ty, tz * s.zchunk, std::min(nz, (tz + 1) * s.zchunk)});
-        return nullptr;
-    }
-    // balanced split: G pieces of (nearly) equal output volume, G a whole
-    // number of rounds of the resident workgroups
-    const long slots = (long)ncu * resident_per_cu(W, lds);
-    long rounds = s.rounds > 0 ? s.rounds : std::max<long>(1, (ntiles + slots - 1) / slots);
-    long G = std::min<long>(slots * rounds, ntiles * (long)nz);
-    if (G > (1L << 24)) return "too many pieces";
-    std::vector<double> area(ntiles);
-    double total = 0.0;
-    for (int ty = 0; ty < g.nty; ++ty)
-        for (int tx = 0; tx < g.ntx; ++tx) {
-            const int ex = std::min(g.ox, nx - tx * g.ox), ey = std::min(g.oy, ny - ty * g.oy);
-            area[(long)ty * g.ntx + tx] = (double)ex * ey;
-            total += (double)ex * ey;
-        }
-    std::vector<int> cnt(ntiles);
-    long used = 0;
-    for (long i = 0; i < ntiles; ++i) {
-        cnt[i] = (int)std::max<double>(1.0, std::min<double>(nz, std::floor(G * area[i] / total)));
-        used += cnt[i];
-    }
-    while (used < G) {   // give the next piece to the tile with the most work per piece
-        long best = -1;
-        double bw = -1.0;
-        for (long i = 0; i < ntiles; ++i)
-            if (cnt[i] < nz && area[i] / cnt[i] > bw) { bw = area[i] / cnt[i]; best = i; }
-        if (best < 0) break;
-        ++cnt[best];
-        ++used;
-    }
-    struct Item { Piece pc; double key; };
-    std::vector<Item> items;
-    items.reserve(used);
-    for (long i = 0; i < ntiles; ++i) {
-        const int tx = (int)(i % g.ntx), ty = (int)(i / g.ntx);
-        for (int k = 0; k < cnt[i]; ++k) {
-            const int z0 = (int)((long)k * nz / cnt[i]), z1 = (int)((long)(k + 1) * nz / cnt[i]);
-            items.push_back(Item{Piece{tx, ty, z0, z1}, 0.5 * (z0 + z1)});
-        }
-    }
-    // neighbouring pieces (same z range, adjacent tiles) next to each other ...
-    std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) {
-        const double qa = std::floor(a.key * 8.0 / nz), qb = std::floor(b.key * 8.0 / nz);
-        if (qa != qb) return qa < qb;
-        if (a.pc.ty != b.pc.ty) return a.pc.ty < b.pc.ty;
-        return a.pc.tx < b.pc.tx;
-    });
-    // ... and each contiguous eighth of that order on one XCD: workgroups are
-    // dispatched to the 8 XCDs round-robin, so XCD j runs workgroups j, j+8, ...
-    const long n = (long)items.size();
-    pcs.resize(n);
-    if (n % 8 == 0) {
-        const long per = n / 8;
-        for (long j = 0; j < 8; ++j)
-            for (long k = 0; k < per; ++k) pcs[8 * k + j] = items[j * per + k].pc;
-    } else {
-        for (long k = 0; k < n; ++k) pcs[k] = items[k].pc;
-    }
-    return nullptr;
-}
-
-// Heuristic schedule when no tuned entry exists.
-ig_schedule igk_auto_schedule(const ig_params* p) {
-    ig_schedule s{};
-    s.kind = IG_SCHED_BLOCKED;
-    auto_vec_rows(p->nx, &s.vec, &s.rows);
-    s.t_block = std::max(1, std::min(2, p->n_iter));
-    // 12 wavefronts and one round of pieces: the fastest on gfx950 for the
-    // 512^3 cube in every conductance and storage type (measured over
-    // T 1..3, 8..16 wavefronts, 0..2 rounds)
-    s.waves = 12;
-    if (stream_lds_bytes(s.vec, s.t_block, s.waves) > kMaxLds) s.waves = 8;
-    s.zchunk = 0;
-    s.rounds = 1;
-    if ((long)s.waves * s.rows * p->nx * (long)dtype_size(p->dtype) >= (1L << 30)) {   // absurdly long rows
-        ig_schedule n{};
-        n.kind = IG_SCHED_NAIVE;
-        return n;
-    }
-    return s;
-}
 
 // ------------------------------------------------------------------ handle
 struct ig_filter {
@@ -334,10 +189,10 @@ extern "C" ig_status ig_filter_create(const ig_params* p, int device, ig_filter*
     f->p = *p;
     f->device = device;
     const size_t bytes = (size_t)(p->nx * p->ny * p->nz) * dtype_size(p->dtype);
-    hipError_t e = hipMalloc(&f->scratch, bytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&f->dparams, sizeof(DevParams));
-    if (e == hipSuccess) e = hipMalloc((void**)&f->parts, sizeof(double) * kPartBlocks * 6);
-    if (e == hipSuccess) e = hipMalloc((void**)&f->results, sizeof(double) * 8);
+    hipError_t e = igk_malloc(&f->scratch, bytes);
+    if (e == hipSuccess) e = igk_malloc((void**)&f->dparams, sizeof(DevParams));
+    if (e == hipSuccess) e = igk_malloc((void**)&f->parts, sizeof(double) * kPartBlocks * 6);
+    if (e == hipSuccess) e = igk_malloc((void**)&f->results, sizeof(double) * 8);
     if (e != hipSuccess) {
         ig_filter_destroy(f);
         return fail(e == hipErrorOutOfMemory ? IG_ERR_OUT_OF_MEMORY : IG_ERR_DEVICE, "allocation: %s",
@@ -365,13 +220,12 @@ extern "C" ig_status ig_filter_set_params(ig_filter* f, const ig_params* p) {
 extern "C" void ig_filter_destroy(ig_filter* f) {
     if (!f) return;
     DeviceGuard dg(f->device);
-    if (f->scratch) (void)hipFree(f->scratch);
-    if (f->dparams) (void)hipFree(f->dparams);
-    if (f->parts) (void)hipFree(f->parts);
-    if (f->results) (void)hipFree(f->results);
+    igk_free(f->scratch);
+    igk_free(f->dparams);
+    igk_free(f->parts);
+    igk_free(f->results);
     for (hipEvent_t e : f->ev) (void)hipEventDestroy(e);
-    for (Piece* d : f->dpieces)
-        if (d) (void)hipFree(d);
+    for (Piece* d : f->dpieces) igk_free(d);
     delete f;
 }
 
@@ -439,7 +293,7 @@ extern "C" ig_status ig_schedule_plan(const ig_params* p, const ig_schedule* s, 
 
 static void drop_plans(ig_filter* f) {
     for (int T = 0; T < 5; ++T) {
-        if (f->dpieces[T]) (void)hipFree(f->dpieces[T]);
+        igk_free(f->dpieces[T]);
         f->dpieces[T] = nullptr;
         f->planned[T] = false;
     }
@@ -472,9 +326,9 @@ static ig_status get_plan(ig_filter* f, const ig_schedule& sched, int T, const P
         const char* why = plan_pass(f->p, sched, T, f->ncu, &f->plans[T]);
         if (why) return fail(IG_ERR_INVALID_ARG, "schedule cannot serve this shape: %s", why);
         const size_t bytes = f->plans[T].pieces.size() * sizeof(Piece);
-        if (f->dpieces[T]) (void)hipFree(f->dpieces[T]);
+        igk_free(f->dpieces[T]);
         f->dpieces[T] = nullptr;
-        HIP_TRY(hipMalloc((void**)&f->dpieces[T], bytes));
+        HIP_TRY(igk_malloc((void**)&f->dpieces[T], bytes));
         HIP_TRY(hipMemcpy(f->dpieces[T], f->plans[T].pieces.data(), bytes, hipMemcpyHostToDevice));
         f->planned[T] = true;
     }
@@ -799,20 +653,39 @@ struct Scratch {
 };
 thread_local Scratch g_scratch;
 
-ig_status util_scratch(int device) {
-    if (g_scratch.device == device && g_scratch.parts) return IG_OK;
-    if (g_scratch.parts) {
+void util_scratch_release() {
+    if (g_scratch.parts || g_scratch.out) {
         DeviceGuard old(g_scratch.device);
-        (void)hipFree(g_scratch.parts);
-        (void)hipFree(g_scratch.out);
-        g_scratch = Scratch{};
+        igk_free(g_scratch.parts);
+        igk_free(g_scratch.out);
     }
-    HIP_TRY(hipMalloc((void**)&g_scratch.parts, sizeof(double) * kPartBlocks * 6));
-    HIP_TRY(hipMalloc((void**)&g_scratch.out, sizeof(double) * 8));
-    g_scratch.device = device;
+    g_scratch = Scratch{};
+}
+
+ig_status util_scratch(int device) {
+    if (g_scratch.device == device && g_scratch.parts && g_scratch.out) return IG_OK;
+    util_scratch_release();
+    Scratch sc;
+    hipError_t e = igk_malloc((void**)&sc.parts, sizeof(double) * kPartBlocks * 6);
+    if (e == hipSuccess) e = igk_malloc((void**)&sc.out, sizeof(double) * 8);
+    if (e != hipSuccess) {
+        igk_free(sc.parts);
+        igk_free(sc.out);
+        return fail(e == hipErrorOutOfMemory ? IG_ERR_OUT_OF_MEMORY : IG_ERR_DEVICE, "reduction scratch: %s",
+                    hipGetErrorString(e));
+    }
+    sc.device = device;
+    g_scratch = sc;
     return IG_OK;
 }
 }  // namespace
+
+void igk_quality_cache_release();
+extern "C" void ig_debug_release_caches(void) {
+    util_scratch_release();
+    igk_quality_cache_release();
+    ig_batch_cache_clear();
+}
 
 extern "C" ig_status ig_compare(const void* d_x, int32_t x_dtype, const double* d_ref, int64_t n, double tol,
                                 int device, void* hip_stream, ig_compare_result* res) {

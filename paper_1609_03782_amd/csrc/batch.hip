@@ -362,10 +362,10 @@ template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
-    ~DevBuf() { if (p) (void)hipFree(p); }
+    ~DevBuf() { igk_free(p); }
     hipError_t alloc(size_t count) {
         n = count;
-        return hipMalloc((void**)&p, std::max<size_t>(1, count) * sizeof(T));
+        return igk_malloc((void**)&p, std::max<size_t>(1, count) * sizeof(T));
     }
 };
 struct BatchPlan {
@@ -412,7 +412,7 @@ struct BatchPlan {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
-        if (h_cubes) (void)hipHostFree(h_cubes);
+        igk_host_free(h_cubes);
     }
 };
 
@@ -629,7 +629,7 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         HIP_TRY(hipMemcpy(bp->d_res.p, res_all.data(), res_all.size() * sizeof(int), hipMemcpyHostToDevice));
     // descriptor tables: fixed for the plan's signature, uploaded once
     HIP_TRY(hipMemcpy(bp->d_cubes.p, cubes.data(), count * sizeof(BatchCube), hipMemcpyHostToDevice));
-    HIP_TRY(hipHostMalloc((void**)&bp->h_cubes, count * sizeof(BatchCube), hipHostMallocDefault));
+    HIP_TRY(igk_host_malloc((void**)&bp->h_cubes, count * sizeof(BatchCube)));
     std::memcpy(bp->h_cubes, cubes.data(), count * sizeof(BatchCube));
     bp->bufs.resize(count);
     for (int c = 0; c < count; ++c) bp->bufs[c] = {items[c].d_in, items[c].d_out};

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "igfilter.h"
+#include "plan.h"
 #include "stencil_common.h"
 #include "stencil_kernels.h"
 
@@ -22,14 +23,7 @@ struct ParamIn {
 };
 
 struct NaiveGeom;
-struct BlockGeom;
-struct Piece;
 
-// LDS bytes of the streaming kernel: current rows and up-edge terms of every
-// level, for every wavefront.
-// two regions of T levels, each level W + 2 row slots of 64 V floats
-inline size_t stream_lds_bytes(int V, int T, int W) { return (size_t)2 * T * (W + 2) * 64 * V * sizeof(float); }
-constexpr size_t kMaxLds = 160 * 1024;
 
 hipError_t launch_sum_partial(int dtype, const void* x, long n, double* part, int nblk, hipStream_t s);
 hipError_t launch_params_final(const double* part, int nparts, long n, const ParamIn& in, DevParams* out,
@@ -54,21 +48,18 @@ constexpr int kPartBlocks = 2048;   // partials of the FP64 reductions
 
 }  // namespace igk
 
-// ------------------------------------------------------------ host planner
-// One pass of the streaming kernel, fully planned: geometry and piece table.
-struct PassPlan {
-    igk::BlockGeom g{};
-    std::vector<igk::Piece> pieces;
-    int V = 0, T = 0;
-};
-void auto_vec_rows(int64_t nx, int* V, int* R);
-int resident_per_cu(int W, size_t lds);
-// nullptr on success, else the reason schedule s cannot serve p at depth T
-const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp);
-ig_status igk_validate_params(const ig_params* p);
-// The library's schedule for p when the caller sets none.
-ig_schedule igk_auto_schedule(const ig_params* p);
-
+// A buffer a kernel will touch: device (or managed) memory of `device` whose
+// allocation covers [p, p + bytes).  A host pointer or a short allocation is
+// reported as IG_ERR_INVALID_ARG (naming `what`) instead of faulting on the GPU.
+ig_status igk_check_buffer(const void* p, size_t bytes, int device, const char* what);
+// The calling thread's current device (0 if it cannot be read).
+int igk_current_device();
+// The library's device / pinned-host allocations (counted, and failed on
+// purpose when a test asks for it; see ig_debug_fail_alloc).  free(NULL) is a no-op.
+hipError_t igk_malloc(void** p, size_t bytes);
+void igk_free(void* p);
+hipError_t igk_host_malloc(void** p, size_t bytes);
+void igk_host_free(void* p);
 // What one filter run needs besides its input and output: the ping-pong
 // scratch cube, the run's constants, the reduction partials, and the piece
 // table of each pass depth.  A handle provides its own allocations; the
@@ -91,11 +82,4 @@ ig_status igk_enqueue_run(const RunCtx& c, const ig_schedule& sched, const void*
 // Wait for the stream and fill *stats (second scan of d_out for sum_out).
 ig_status igk_finish_stats(const RunCtx& c, const ig_schedule& sched, int passes, const void* d_out,
                            hipStream_t s, ig_stats* stats);
-// A buffer a kernel will touch: device (or managed) memory of `device` whose
-// allocation covers [p, p + bytes).  A host pointer or a short allocation is
-// reported as IG_ERR_INVALID_ARG (naming `what`) instead of faulting on the GPU.
-ig_status igk_check_buffer(const void* p, size_t bytes, int device, const char* what);
-// The calling thread's current device (0 if it cannot be read).
-int igk_current_device();
-ig_status igk_fail(ig_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-size_t dtype_size(int dt);
+

@@ -323,10 +323,19 @@ extern "C" ig_status ig_quality(const ig_quality_params* q, const float* d_orig,
     g.nrows = g.ry * (r[5] - r[4]);
     std::lock_guard<std::mutex> lk(g_qmu);
     QScratch& qs = g_qs[device];
-    if (!qs.part) {
-        HIP_TRY(hipMalloc((void**)&qs.part, (size_t)kQMaxBlocks * kQWaves * kQSlots * sizeof(double)));
-        HIP_TRY(hipMalloc((void**)&qs.sums, (size_t)kQSlots * sizeof(double)));
-        HIP_TRY(hipMalloc((void**)&qs.res, sizeof(ig_quality_result)));
+    if (!qs.part) {   // all three or none: a failure leaves the cache empty
+        QScratch fresh{};
+        hipError_t e = igk_malloc((void**)&fresh.part, (size_t)kQMaxBlocks * kQWaves * kQSlots * sizeof(double));
+        if (e == hipSuccess) e = igk_malloc((void**)&fresh.sums, (size_t)kQSlots * sizeof(double));
+        if (e == hipSuccess) e = igk_malloc((void**)&fresh.res, sizeof(ig_quality_result));
+        if (e != hipSuccess) {
+            igk_free(fresh.part);
+            igk_free(fresh.sums);
+            igk_free(fresh.res);
+            return fail(e == hipErrorOutOfMemory ? IG_ERR_OUT_OF_MEMORY : IG_ERR_DEVICE, "quality scratch: %s",
+                        hipGetErrorString(e));
+        }
+        qs = fresh;
     }
     long count;
     if (q->n_thr <= 8) {
@@ -351,4 +360,21 @@ extern "C" ig_status ig_quality(const ig_quality_params* q, const float* d_orig,
     HIP_TRY(hipMemcpyAsync(out, qs.res, sizeof(ig_quality_result), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return IG_OK;
+}
+
+// Free the per-device quality scratch (the next ig_quality allocates it again).
+void igk_quality_cache_release() {
+    std::lock_guard<std::mutex> lk(g_qmu);
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    for (int d = 0; d < 64; ++d) {
+        QScratch& qs = g_qs[d];
+        if (!qs.part && !qs.sums && !qs.res) continue;
+        (void)hipSetDevice(d);
+        igk_free(qs.part);
+        igk_free(qs.sums);
+        igk_free(qs.res);
+        qs = QScratch{};
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
 }

@@ -25,6 +25,7 @@
 #pragma once
 #include <type_traits>
 
+#include "plan.h"
 #include "stencil_common.h"
 
 namespace igk {
@@ -33,15 +34,7 @@ struct NaiveGeom {
     int nx, ny, nz;
 };
 
-struct BlockGeom {
-    int nx, ny, nz;
-    int ntx, nty;         // tile counts in x, y
-    int ox, oy;           // output extent of a tile in x, y
-    int W;                // wavefronts per workgroup (== blockDim.y)
-    int vec;              // 1: lane chunks are whole and aligned (vector I/O)
-    int R;                // rows per wavefront (1, 2 or 4); a tile has W * R rows
-    int hx;               // x halo of a tile when ntx > 1 (t_block rounded up to whole lane chunks)
-};
+
 
 __device__ __forceinline__ float lane_shr1(float v) {  // lane i <- lane i-1, lane 0 <- 0
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
@@ -362,9 +355,7 @@ __device__ __forceinline__ void store_row_f32(__amdgpu_buffer_rsrc_t r, int full
 // between the last lane of one row and the first lane of the next (adjacent
 // lanes, exchanged by the same DPP shifts) has the closed coefficient, since
 // a row's lanes cover the whole row, so no value crosses rows.
-struct Piece {
-    int tx, ty, z0, z1;
-};
+// (Piece: plan.h)
 
 // Which of the two y edge schemes a conductance uses (above).
 template <int COND>

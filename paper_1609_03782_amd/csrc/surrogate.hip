@@ -32,16 +32,16 @@ constexpr long kWgradGroups = 512;   // workgroups of the weight-gradient kernel
 struct Dev {
     void* p = nullptr;
     size_t bytes = 0;
-    ~Dev() { if (p) (void)hipFree(p); }
+    ~Dev() { igk_free(p); }
     hipError_t ensure(size_t b) {
         if (b <= bytes && p) return hipSuccess;
         if (p) {   // queued kernels may still use the old buffer
             (void)hipDeviceSynchronize();
-            (void)hipFree(p);
+            igk_free(p);
             p = nullptr;
             bytes = 0;
         }
-        hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
+        hipError_t e = igk_malloc(&p, std::max<size_t>(b, 256));
         if (e == hipSuccess) bytes = std::max<size_t>(b, 256);
         return e;
     }
@@ -222,6 +222,8 @@ struct ig_surrogate {
     Dev params, grads, m, v;            // FP32
     std::vector<Dev> pk_f, pk_d;        // packed bf16 weights (forward, input gradient)
     long step = 0;
+    float clip = 0.0f;                  // global gradient-norm limit (0: none)
+    Dev clipbuf;                        // [0]: factor (float), [8..]: norm (double), [64..]: partials
     // activations, sized for the largest cube seen
     long cap = 0;
     std::vector<Dev> act, pre;          // act[0] 1 channel, act[1..L-1] 32; pre[1..L-1]
@@ -429,8 +431,17 @@ extern "C" ig_status ig_surrogate_train_step(ig_surrogate* s, const float* const
     ++s->step;
     const float b1 = s->p.beta1, b2 = s->p.beta2;
     const float bc1 = 1.0f - std::pow(b1, (float)s->step), bc2 = 1.0f - std::pow(b2, (float)s->step);
-    hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, st, s->params.as<float>(), s->grads.as<float>(),
-                       s->m.as<float>(), s->v.as<float>(), np, s->p.lr, b1, b2, s->p.eps, bc1, bc2, 1.0f);
+    HIP_TRY(s->clipbuf.ensure(64 + 1024 * sizeof(double)));
+    {
+        float* factor = s->clipbuf.as<float>();
+        double* norm = reinterpret_cast<double*>(s->clipbuf.as<char>() + 8);
+        double* cparts = reinterpret_cast<double*>(s->clipbuf.as<char>() + 64);
+        hipLaunchKernelGGL(k_sumsq, dim3(1024), dim3(256), 0, st, s->grads.as<float>(), np, cparts);
+        hipLaunchKernelGGL(k_clip_factor, dim3(1), dim3(64), 0, st, cparts, 1024, s->clip, factor, norm);
+        hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, st, s->params.as<float>(),
+                           s->grads.as<float>(), s->m.as<float>(), s->v.as<float>(), np, s->p.lr, b1, b2, s->p.eps, bc1,
+                           bc2, (const float*)factor);
+    }
     HIP_TRY(hipGetLastError());
     rc = repack(s, st);
     if (rc != IG_OK) return rc;
@@ -716,6 +727,22 @@ extern "C" ig_status ig_surrogate_set_lr(ig_surrogate* s, float lr) {
 }
 
 extern "C" int64_t ig_surrogate_get_step(const ig_surrogate* s) { return s ? (int64_t)s->step : -1; }
+
+extern "C" ig_status ig_surrogate_set_clip(ig_surrogate* s, float max_norm) {
+    if (!s || !(max_norm >= 0.0f) || !std::isfinite(max_norm))
+        return fail(IG_ERR_INVALID_ARG, "max_norm must be finite and >= 0");
+    s->clip = max_norm;
+    return IG_OK;
+}
+
+extern "C" ig_status ig_surrogate_last_grad_norm(const ig_surrogate* s, double* norm) {
+    if (!s || !norm) return fail(IG_ERR_INVALID_ARG, "NULL argument");
+    if (!s->clipbuf.p || s->step == 0) return fail(IG_ERR_INVALID_ARG, "no training step taken yet");
+    if (hipSetDevice(s->device) != hipSuccess) return fail(IG_ERR_DEVICE, "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(norm, s->clipbuf.as<char>() + 8, sizeof(double), hipMemcpyDeviceToHost));
+    return IG_OK;
+}
 
 // ------------------------------------------------------------ building blocks
 extern "C" ig_status ig_conv3d_forward(const void* d_in, int32_t c_in, const float* d_w, const float* d_b, int32_t c_out,

@@ -559,13 +559,42 @@ k_mse(const float* __restrict__ y, const float* __restrict__ t, long n, double s
 }
 
 // ---------------------------------------------------------- optimiser
-// Adam on FP32 master parameters (bias-corrected), grads scaled by gscale.
+// Gradient clipping by global norm: FP64 sum of squares of the gradient per
+// workgroup, then one workgroup folds the partials in order and writes the
+// factor min(1, max_norm / ||g||) (1 when max_norm <= 0).
+__global__ void __launch_bounds__(256)
+k_sumsq(const float* __restrict__ g, long n, double* __restrict__ part) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+        const double v = g[i];
+        s += v * v;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_clip_factor(const double* __restrict__ part, int nparts, float max_norm, float* __restrict__ factor,
+                              double* __restrict__ norm_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < nparts; ++k) s += part[k];
+    const double nrm = sqrt(s);
+    *norm_out = nrm;
+    *factor = (max_norm > 0.0f && nrm > (double)max_norm) ? (float)((double)max_norm / nrm) : 1.0f;
+}
+
+// Adam on FP32 master parameters (bias-corrected), grads scaled by *gscale.
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, long n, float lr, float b1, float b2, float eps, float bc1, float bc2,
-                       float gscale) {
+                       const float* __restrict__ gscale) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const float gi = g[i] * gscale;
+    const float gi = g[i] * *gscale;
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;

@@ -70,7 +70,7 @@ extern "C" ig_status ig_filter_sweep(const ig_params* base, const ig_sweep_point
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(device);
     float* work = nullptr;
-    hipError_t he = hipMalloc((void**)&work, (size_t)n * sizeof(float));
+    hipError_t he = igk_malloc((void**)&work, (size_t)n * sizeof(float));
     (void)hipSetDevice(prev >= 0 ? prev : device);
     if (he != hipSuccess) {
         ig_filter_destroy(f);
@@ -100,7 +100,7 @@ extern "C" ig_status ig_filter_sweep(const ig_params* base, const ig_sweep_point
         st = fail(IG_ERR_DEVICE, "sync: %s", hipGetErrorString(he));
     (void)hipStreamSynchronize(s);   // the work cube is in use until the stream drains
     (void)hipSetDevice(device);
-    (void)hipFree(work);
+    igk_free(work);
     (void)hipSetDevice(prev >= 0 ? prev : device);
     ig_filter_destroy(f);
     return st;

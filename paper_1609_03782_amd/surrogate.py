@@ -47,6 +47,8 @@ SIGNATURES = {
                                                     ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_uint64)]),
     "ig_surrogate_set_lr": (ctypes.c_int, [_P, ctypes.c_float]),
     "ig_surrogate_get_step": (_I64, [_P]),
+    "ig_surrogate_set_clip": (ctypes.c_int, [_P, ctypes.c_float]),
+    "ig_surrogate_last_grad_norm": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
     "ig_conv3d_forward": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _I64,
                                          _I64, _I64, _P]),
     "ig_conv3d_input_grad": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _I64, _I64, _I64, _P]),
@@ -117,6 +119,15 @@ class Surrogate:
 
     def set_lr(self, lr):
         _check(slib().ig_surrogate_set_lr(self._h, float(lr)), "ig_surrogate_set_lr")
+
+    def set_clip(self, max_norm):
+        """Clip later steps by the global gradient norm (0: off)."""
+        _check(slib().ig_surrogate_set_clip(self._h, float(max_norm)), "ig_surrogate_set_clip")
+
+    def last_grad_norm(self):
+        v = ctypes.c_double()
+        _check(slib().ig_surrogate_last_grad_norm(self._h, ctypes.byref(v)), "ig_surrogate_last_grad_norm")
+        return v.value
 
     @property
     def step(self):

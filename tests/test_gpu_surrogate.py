@@ -273,6 +273,33 @@ def test_checkpoint_resume_is_bitwise(dev, tmp_path):
     assert np.array_equal(w0, c.get_weights()) and c.step == 0
 
 
+def test_gradient_clipping(dev):
+    """The reported gradient norm is the FP64 norm of the step's gradient; a
+    limit above it changes nothing (bitwise), a limit below it changes the
+    later steps (Adam's first step is scale-invariant, its later ones are not)."""
+    import torch
+    import paper_1609_03782_amd as ig
+    from paper_1609_03782_amd import surrogate as sg
+    import igsynth
+    c = igsynth.batch_cube(igsynth.BatchItem((16, 18, 20), 2.0, 8, 900))
+    x = torch.from_numpy(c).to(dev)
+    t = ig.Filter(c.shape, K=2.0, tau=1 / 16, n_iter=8).run(x)
+    torch.cuda.synchronize()
+    nets = [sg.Surrogate(depth=3, seed=21, lr=1e-3) for _ in range(3)]
+    nets[1].set_clip(1e30)
+    for k in range(3):
+        for n in nets:
+            n.train_step([x], [t], want_loss=False)
+        g = nets[0].get_grads().astype(np.float64)
+        assert nets[0].last_grad_norm() == pytest.approx(float(np.sqrt((g * g).sum())), rel=1e-6)
+        if k == 0:
+            nets[2].set_clip(0.01 * nets[0].last_grad_norm())
+    assert np.array_equal(nets[0].get_weights(), nets[1].get_weights())
+    assert not np.array_equal(nets[0].get_weights(), nets[2].get_weights())
+    with pytest.raises(ig.IgError):
+        nets[0].set_clip(-1.0)
+
+
 def test_checked_inference_and_fallback(dev):
     import torch
     import paper_1609_03782_amd as ig

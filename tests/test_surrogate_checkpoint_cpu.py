@@ -87,3 +87,5 @@ def test_missing_file_and_null_arguments(tmp_path):
     assert L.ig_surrogate_load(None, b"x") == ig.IG_ERR_INVALID_ARG
     assert L.ig_surrogate_set_lr(None, ctypes.c_float(1e-3)) == ig.IG_ERR_INVALID_ARG
     assert L.ig_surrogate_get_step(None) == -1
+    assert L.ig_surrogate_set_clip(None, ctypes.c_float(1.0)) == ig.IG_ERR_INVALID_ARG
+    assert L.ig_surrogate_last_grad_norm(None, None) == ig.IG_ERR_INVALID_ARG
