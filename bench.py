@@ -8,7 +8,7 @@ storage runs of that cube, the paper's default parameters on it, and the
 96-cube batched launch, each measured the same way.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
-  python bench.py --workload surrogate [--train N] [--budget SECONDS]
+  python bench.py --workload surrogate [--train N] [--train-steps STEPS]
   python bench.py --workload conv      (the surrogate's kernels alone, for profiling)
   python bench.py --calib-copy          (plain copy of the cube size, for counter calibration)
 """
@@ -120,13 +120,14 @@ def copy_gbps(x, reps=10):
 
 
 # Algorithmic ALU work of one voxel-iteration of the edge-shared exponential
-# update: 3 edges x (difference, square, scaled exponent fma, exp2, flux
-# multiply) + 6 adds for the flux divergence and the update.  Issue slots on
-# gfx950 without packed FP32: 1 per operation, 2 per exp2 -> 24 slots; flops:
-# 1 per operation, 2 per fma -> 24.  Non-packed FP32 issue peak: 256 CUs x
-# 64 lanes x 2.4 GHz = 39.32 T slots/s, so 39.32 TFLOP/s for this mix.
-PM_EXP_FLOP_PER_VOXEL_ITER = 24
-ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+# update, counted in VALU issue slots: 3 edges x (difference, square, scaled
+# exponent fma, exp2, flux multiply) + 6 adds for the flux divergence and the
+# update = 18 single-slot operations + 3 exp2 at 2 slots each (transcendentals
+# issue at half rate) = 24 slots.  Issue ceiling without packed FP32 (not used
+# on this platform): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T
+# lane-slots/s (a wave64 instruction takes 4 cycles on a 16-lane SIMD).
+PM_EXP_SLOTS_PER_VOXEL_ITER = 24
+ALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def code_only(src):
@@ -245,6 +246,44 @@ def storage_floor(cube, ref, rho, n_iter, K, tau):
     d = np.abs(r32 - ref)
     return {"max_abs_in_rms": float(d.max()) / rho, "rmse_in_rms": float(np.sqrt(np.mean(d * d))) / rho,
             "voxels_over_1e-5_rms": int((d > 1e-5 * rho).sum()), "histogram_in_rms": decade_histogram(d / rho)}
+
+
+def run_with_host_io(f, x, reps=3):
+    """One whole run including the host<->device copies the paper's GPU time
+    includes: pinned host cube -> device, the filter, device -> pinned host."""
+    import torch
+    host = x.cpu().pin_memory()
+    back = torch.empty(x.shape, dtype=x.dtype, pin_memory=True)
+    out = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        xd = host.to(x.device, non_blocking=True)
+        f.run(xd, out)
+        back.copy_(out, non_blocking=True)
+        torch.cuda.synchronize()
+    return round((time.perf_counter() - t0) / reps * 1e3, 3)
+
+
+def errors_vs_quantised_oracle(cube, outs, n_iter, K, tau):
+    """Each 16-bit run against the FP64 oracle run on the same input rounded
+    to that storage type (so the input's own quantisation is not counted; what
+    remains is the rounding after every step), in units of the oracle's rho."""
+    import numpy as np
+    import torch
+    import oracle
+    res = {}
+    for name, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        if name not in outs:
+            continue
+        q = torch.from_numpy(cube).to(tdt).to(torch.float32).numpy()
+        t0 = time.perf_counter()
+        ref, rho = oracle.run(q, "pm_exp", K=K, tau=tau, n_iter=n_iter)
+        d = outs[name][0].astype(np.float64) - ref
+        res[name] = {"max_abs_in_rms": float(np.abs(d).max()) / rho, "rmse_in_rms": float(np.sqrt(np.mean(d * d))) / rho,
+                     "voxels_over_1e-5_rms": int((np.abs(d) > 1e-5 * rho).sum()),
+                     "oracle_s": round(time.perf_counter() - t0, 1)}
+    return res
 
 
 def bench_paper_defaults(x, steps):
@@ -471,22 +510,20 @@ def bench_wavelet(x):
     return res
 
 
-def train_with_budget(net, xs, ts, budget_s, batch, lr0, lr_end_frac=0.02, warm_steps=300, seed=0, log=None,
-                      curve_every=100):
-    """Minibatch Adam over (x, t) pairs for about budget_s seconds: the step
-    time of the first 20 steps fixes the number of steps; the learning rate
-    rises linearly from 0.05 lr0 to lr0 over warm_steps, then follows a cosine
-    down to lr_end_frac * lr0.  Returns (steps, loss curve [(step, mean loss
-    of the last curve_every steps)], all losses)."""
+def train_steps(net, xs, ts, steps, batch, lr0, lr_end_frac=0.02, warm_steps=300, seed=0, log=None,
+                curve_every=100):
+    """`steps` minibatch Adam steps over the (x, t) pairs in a seeded order:
+    the learning rate rises linearly from 0.05 lr0 to lr0 over warm_steps,
+    then follows a cosine down to lr_end_frac * lr0.  Every step's kernels sum
+    in a fixed order, so the run is reproducible bit for bit.  Returns (loss
+    curve [(step, mean loss of the last curve_every steps, gradient norm of
+    that step)], all losses)."""
     import math
     import numpy as np
-    import torch
     rng = np.random.default_rng(seed)
     order, pos = rng.permutation(len(xs)), 0
     losses, curve = [], []
-
-    def one(k, total):
-        nonlocal order, pos
+    for k in range(steps):
         if pos + batch > len(order):
             order, pos = rng.permutation(len(xs)), 0
         idx = order[pos:pos + batch]
@@ -494,34 +531,22 @@ def train_with_budget(net, xs, ts, budget_s, batch, lr0, lr_end_frac=0.02, warm_
         if k < warm_steps:
             lr = lr0 * (0.05 + 0.95 * k / warm_steps)
         else:
-            q = min(1.0, (k - warm_steps) / max(1, total - warm_steps))
+            q = min(1.0, (k - warm_steps) / max(1, steps - warm_steps))
             lr = lr0 * (lr_end_frac + (1 - lr_end_frac) * 0.5 * (1 + math.cos(math.pi * q)))
         net.set_lr(lr)
         losses.append(net.train_step([xs[i] for i in idx], [ts[i] for i in idx]))
         if len(losses) % curve_every == 0:
-            curve.append((len(losses), float(np.mean(losses[-curve_every:]))))
+            curve.append((len(losses), float(np.mean(losses[-curve_every:])), round(net.last_grad_norm(), 4)))
             if log:
-                log(f"step {len(losses)} lr {lr:.2e} loss {curve[-1][1]:.5f}")
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    warm = 20
-    for k in range(warm):
-        one(k, 10 ** 9)
-    torch.cuda.synchronize()
-    per = (time.perf_counter() - t0) / warm
-    total = max(warm + 1, int(budget_s / per))
-    for k in range(warm, total):
-        one(k, total)
-    torch.cuda.synchronize()
-    return total, curve, losses
+                log(f"step {len(losses)} lr {lr:.2e} loss {curve[-1][1]:.5f} |g| {curve[-1][2]}")
+    return curve, losses
 
 
-def surrogate_c5(x, ms_plain, ref=None, rho=None, budget_s=90.0, n_train=4000, n_val=50, cube=96, batch=4,
-                 lr=4e-4, threshold=0.05, log=None):
+def surrogate_c5(x, ms_plain, ref=None, rho=None, steps=7000, n_train=4000, n_val=50, cube=96, batch=4,
+                 lr=3e-4, clip=0.0, threshold=0.05, log=None):
     """The learned surrogate on the 512^3 workload: train the 8-layer 32-channel
     network on n_train synthetic 96^3 cubes paired with their 50-step filter
-    outputs (made by the library's filter) for about budget_s seconds,
+    outputs (made by the library's filter) for `steps` Adam steps,
     calibrate the residual check on n_val held-out cubes, then on the 512^3
     cube time the forward pass and the checked path (forward + two plain steps
     + fallback to the filter when the predicted RMSE exceeds the threshold)
@@ -544,8 +569,9 @@ def surrogate_c5(x, ms_plain, ref=None, rho=None, budget_s=90.0, n_train=4000, n
     if log:
         log(f"surrogate data: {n_train} + {n_val} cubes of {cube}^3 with targets in {t_data:.1f} s")
     net = sg.Surrogate(depth=8, lr=lr, seed=0)
+    net.set_clip(clip)
     t0 = time.perf_counter()
-    steps, curve, losses = train_with_budget(net, xs, ts, budget_s, batch, lr, log=log)
+    curve, losses = train_steps(net, xs, ts, steps, batch, lr, log=log)
     t_train = time.perf_counter() - t0
     slope, pairs = sg.calibrate(net, vxs, vts, params)
     val_rmse = float(np.sqrt(np.mean([e * e for _, e in pairs])))
@@ -599,9 +625,9 @@ def surrogate_c5(x, ms_plain, ref=None, rho=None, budget_s=90.0, n_train=4000, n
         "speedup_checked_path": round(ms_plain / ms_checked, 4),
         "speedup_forward_plus_check": round(ms_plain / (ms_fwd + ms2), 4),
         "forward_TFLOPs_bf16": round(flops / ms_fwd / 1e9, 1),
-        "training": {"cubes": n_train, "cube": cube, "batch": batch, "steps": steps, "budget_s": budget_s,
-                     "s_train": round(t_train, 1), "s_data": round(t_data, 1), "lr": lr,
-                     "schedule": "linear warm-up over 300 steps, then cosine to 0.02 lr", "loss_first": losses[0],
+        "training": {"cubes": n_train, "cube": cube, "batch": batch, "steps": steps,
+                     "s_train": round(t_train, 1), "s_data": round(t_data, 1), "lr": lr, "clip_norm": clip,
+                     "schedule": "linear warm-up over 300 steps, then cosine to 0.02 lr; fixed data order (seed 0)", "loss_first": losses[0],
                      "loss_last100": float(np.mean(losses[-100:])), "curve": curve[::max(1, len(curve) // 12)]},
         "network": "8 conv3d 3x3x3 layers (1-32-...-32-1), GELU, residual to input, bf16 weights/activations, "
                    "FP32 accumulate on MFMA",
@@ -644,7 +670,7 @@ def bench_conv(args):
 
 
 def bench_surrogate(args):
-    """--workload surrogate: the C5 leg alone, with its own budget, printed
+    """--workload surrogate: the C5 leg alone, with its own training settings, printed
     as its own JSON line (scored against the FP64 oracle unless --no-cpu)."""
     import torch
     import igsynth
@@ -660,8 +686,9 @@ def bench_surrogate(args):
         import oracle
         oracle.build(force=False)
         ref, rho = oracle.run(cube, "pm_exp", K=2.0, tau=1 / 16, n_iter=N_ITER)
-    res = surrogate_c5(x, ms_plain, ref, rho, budget_s=args.budget, n_train=args.train, n_val=args.val,
-                       cube=args.cube, batch=args.batch, lr=args.lr, threshold=args.threshold, log=log)
+    res = surrogate_c5(x, ms_plain, ref, rho, steps=args.train_steps, n_train=args.train, n_val=args.val,
+                       cube=args.cube, batch=args.batch, lr=args.lr, clip=args.clip, threshold=args.threshold,
+                       log=log)
     res["metric"] = "surrogate speedup vs plain GPU filter at RMSE <= 0.05 sigma (512^3 cube)"
     print(json.dumps(res), flush=True)
 
@@ -677,9 +704,10 @@ def main():
     ap.add_argument("--train", type=int, default=4000)
     ap.add_argument("--val", type=int, default=50)
     ap.add_argument("--cube", type=int, default=96)
-    ap.add_argument("--budget", type=float, default=90.0, help="surrogate training seconds")
+    ap.add_argument("--train-steps", type=int, default=7000, help="surrogate training steps (0: no surrogate leg)")
     ap.add_argument("--batch", type=int, default=4)
-    ap.add_argument("--lr", type=float, default=4e-4)
+    ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--clip", type=float, default=0.0, help="surrogate gradient-norm clip (0: off)")
     ap.add_argument("--threshold", type=float, default=0.05)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of the cube size (counter calibration)")
@@ -731,20 +759,22 @@ def main():
     # dominant kernel: k_stream, T iterations per launch over N voxels.
     # Algorithmic bytes per launch: 8 B per voxel (the cube read once and
     # written once; the T - 1 levels in between stay on chip); algorithmic
-    # flops: 24 per voxel-iteration, N * T per launch.
+    # ALU work: 24 issue slots per voxel-iteration, N * T per launch.
     T = max(1, sched["t_block"]) if sched["kind"] == "blocked" else 1
     avg_ms = k_ms / max(1, k_launches)
     achieved_gbs = 8.0 * N / (avg_ms * 1e-3) / 1e9
-    achieved_tf = PM_EXP_FLOP_PER_VOXEL_ITER * N * T / (avg_ms * 1e-3) / 1e12
+    achieved_ts = PM_EXP_SLOTS_PER_VOXEL_ITER * N * T / (avg_ms * 1e-3) / 1e12
     traffic = counter_traffic()
     hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
-    alu = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
-           "frac": round(achieved_tf / ALU_PEAK_TFLOPS, 4), "traffic": traffic}
+    alu = {"bound": "alu", "achieved": round(achieved_ts, 2), "peak": round(ALU_PEAK_TSLOTS, 2),
+           "unit": "T issue-slots/s", "frac": round(achieved_ts / ALU_PEAK_TSLOTS, 4), "traffic": traffic,
+           "unit_note": "VALU lane issue slots: 24 per voxel-iteration (18 operations + 3 exp2 at 2 slots); "
+                        "ceiling 256 CU x 64 lanes x 2.4 GHz without packed FP32"}
     # the bound is the roofline with the lower ceiling in voxel-iterations/s
-    # for this schedule: HBM gives T * peak / 8 B, the ALU peak / 24 flop
+    # for this schedule: HBM gives T * peak / 8 B, the ALU peak / 24 slots
     hbm_ceiling = HBM_PEAK_GBS * 1e9 * T / 8.0
-    alu_ceiling = ALU_PEAK_TFLOPS * 1e12 / PM_EXP_FLOP_PER_VOXEL_ITER
+    alu_ceiling = ALU_PEAK_TSLOTS * 1e12 / PM_EXP_SLOTS_PER_VOXEL_ITER
     first, second = (hbm, alu) if hbm_ceiling <= alu_ceiling else (alu, hbm)
     roof = dict(first)
     roof["other"] = second
@@ -763,6 +793,7 @@ def main():
     if roof["bound"] == "hbm":
         roof["frac_of_copy"] = hbm["frac_of_copy"]
     runs = per_run_ms(f, x, out)
+    io_ms = run_with_host_io(f, x)
 
     res = {
         "metric": METRIC,
@@ -773,6 +804,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
         "ms_per_step_single_runs": runs,
+        "ms_with_host_io": io_ms,
         "gpu": gpu_info(),
         "higher_is_better": True,
         "scaling": "weak",
@@ -807,11 +839,13 @@ def main():
         outs16["f32"] = (y32, ms_step)
         res["errors_vs_fp64_oracle"] = errors_vs_oracle(outs16, ref, rho, ms_step)
         res["errors_vs_fp64_oracle"]["f32_storage_floor"] = storage_floor(cube, ref, rho, N_ITER, K, tau)
-    if not args.no_extras and args.budget > 0:
+        res["errors_vs_fp64_oracle"]["vs_oracle_on_quantised_input"] = errors_vs_quantised_oracle(
+            cube, outs16, N_ITER, K, tau)
+    if not args.no_extras and args.train_steps > 0:
         log = lambda m: print(m, file=sys.stderr, flush=True)
-        res["extras"]["surrogate_c5"] = surrogate_c5(x, ms_step, ref, rho, budget_s=args.budget, n_train=args.train,
+        res["extras"]["surrogate_c5"] = surrogate_c5(x, ms_step, ref, rho, steps=args.train_steps, n_train=args.train,
                                                      n_val=args.val, cube=args.cube, batch=args.batch, lr=args.lr,
-                                                     threshold=args.threshold, log=log)
+                                                     clip=args.clip, threshold=args.threshold, log=log)
     del ref
     print(json.dumps(res), flush=True)
 
