@@ -10,6 +10,7 @@ storage runs of that cube, the paper's default parameters on it, and the
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
   python bench.py --workload surrogate [--train N] [--train-steps STEPS]
   python bench.py --workload conv      (the surrogate's kernels alone, for profiling)
+  python bench.py --workload batch     (the 96-cube batch alone, for profiling)
   python bench.py --calib-copy          (plain copy of the cube size, for counter calibration)
 """
 from __future__ import annotations
@@ -700,7 +701,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
-    ap.add_argument("--workload", default="filter", choices=["filter", "surrogate", "conv"])
+    ap.add_argument("--workload", default="filter", choices=["filter", "surrogate", "conv", "batch"])
     ap.add_argument("--train", type=int, default=4000)
     ap.add_argument("--val", type=int, default=50)
     ap.add_argument("--cube", type=int, default=96)
@@ -743,6 +744,9 @@ def main():
         return
     if args.workload == "conv":
         bench_conv(args)
+        return
+    if args.workload == "batch":
+        print(json.dumps({"batch_96": bench_batch(max(3, args.steps // 4))}), flush=True)
         return
 
     cube = igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])

@@ -276,7 +276,7 @@ ig_status ig_batch_set_resident(int32_t max_voxels);
 ig_status ig_batch_get_resident(int32_t* max_voxels);
 
 /* Batch autotuner: runs the batch with t_block 1..4, waves 8, 12 and 16 and
- * z-chunks of 32 and 64 planes, and, when some cube is small enough, with the
+ * z-chunks of 16, 32 and 64 planes, and, when some cube is small enough, with the
  * resident limit at 32768 and at 0; keeps the fastest (sets it as by
  * ig_batch_set_schedule and ig_batch_set_resident, and keeps only that plan
  * cached) and returns the schedule (the resident limit through

@@ -875,7 +875,7 @@ extern "C" ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count
     for (int R : res_modes)
         for (int T = 1; T <= std::max(1, std::min(4, maxn)); ++T)
             for (int W : {8, 12, 16})
-                for (int Z : {32, 64}) {
+                for (int Z : {16, 32, 64}) {
                     if (W <= 2 * T) continue;
                     if (ig_batch_set_schedule(T, W, Z) != IG_OK || ig_batch_set_resident(R) != IG_OK) continue;
                     if (ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) != IG_OK) {   // build + warm

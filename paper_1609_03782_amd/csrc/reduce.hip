@@ -1,5 +1,5 @@
 // FP64 reductions on the device: the noise level rho (root mean square of
-// the input, Section 3.3 "rms is the noise level in the data cube"), the sums
+// the input; Section 3.3 takes the cube's rms as its noise level), the sums
 // used for the conservation check, a non-finite scan, and error norms against
 // an FP64 reference cube.
 //
