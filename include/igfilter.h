@@ -203,8 +203,11 @@ ig_status ig_filter_get_timing(ig_filter* f, double* total_ms, int64_t* launches
  * {ntx, nty, ox, oy, waves, vec_io, V, pieces, rows per wavefront}; if
  * pieces != NULL, up to cap
  * pieces as {tile_x, tile_y, z0, z1} (outputs in planes [z0, z1) of tile
- * (tile_x, tile_y), whose outputs are columns [tile_x*ox, +ox) and rows
- * [tile_y*oy, +oy), clipped to the cube).  *count receives the number. */
+ * (tile_x, tile_y)).  Tiles split the cube evenly: tile j outputs rows
+ * [j*ny/nty, (j+1)*ny/nty) and tile i columns [c(i), c(i+1)), where c(i) is
+ * i*nx/ntx rounded up to a multiple of V and c(ntx) = nx (integer division
+ * throughout); no tile exceeds ox columns or oy rows.  *count receives the
+ * number. */
 ig_status ig_schedule_plan(const ig_params* p, const ig_schedule* s, int32_t t_block, int32_t ncu,
                            int32_t* geom, int32_t* pieces, int64_t cap, int64_t* count);
 

@@ -127,6 +127,16 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
         if (g.oy < 1) return "too few rows for t_block (need waves * rows > 2 * t_block)";
         g.nty = (ny + g.oy - 1) / g.oy;
     }
+    for (int k = 0; k < g.ntx; ++k) {
+        int a, b;
+        tile_cols(g, V, k, &a, &b);
+        if (a % V || b <= a || b - a > g.ox) return "x tile split out of range";
+    }
+    for (int k = 0; k < g.nty; ++k) {
+        int a, b;
+        tile_rows(g, k, &a, &b);
+        if (b <= a || b - a > g.oy) return "y tile split out of range";
+    }
     // vector I/O: whole lane chunks (nx a multiple of V) and a tile's rows of
     // one plane below 2^30 bytes (the buffer offsets of the 16-bit kernels)
     g.vec = (nx % V == 0 && (long)W * R * nx * (long)dtype_size(p.dtype) < (1L << 30)) ? 1 : 0;
@@ -144,8 +154,11 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
                     pcs.push_back(Piece{tx, ty, tz * s.zchunk, std::min(nz, (tz + 1) * s.zchunk)});
         return nullptr;
     }
-    // balanced split: G pieces of (nearly) equal output volume, G a whole
-    // number of rounds of the resident workgroups
+    // balanced split: G pieces of (nearly) equal work, G a whole number of
+    // rounds of the resident workgroups.  A tile's work per plane is set by
+    // the rows and columns it computes (its outputs and halo inside the
+    // cube), not by its outputs alone: a plane step costs the same whether
+    // a tile outputs 11 rows or 12.
     const long slots = (long)ncu * resident_per_cu(W, lds);
     long rounds = s.rounds > 0 ? s.rounds : std::max<long>(1, (ntiles + slots - 1) / slots);
     long G = std::min<long>(slots * rounds, ntiles * (long)nz);
@@ -154,7 +167,12 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
     double total = 0.0;
     for (int ty = 0; ty < g.nty; ++ty)
         for (int tx = 0; tx < g.ntx; ++tx) {
-            const int ex = std::min(g.ox, nx - tx * g.ox), ey = std::min(g.oy, ny - ty * g.oy);
+            int x0, x1, y0, y1;
+            tile_cols(g, V, tx, &x0, &x1);
+            tile_rows(g, ty, &y0, &y1);
+            const int rx0 = g.ntx > 1 ? x0 - g.hx : 0, ry0 = g.nty > 1 ? y0 - T : 0;
+            const int ex = std::min(rx0 + RX, nx) - std::max(rx0, 0);
+            const int ey = std::min(ry0 + W * R, ny) - std::max(ry0, 0);
             area[(long)ty * g.ntx + tx] = (double)ex * ey;
             total += (double)ex * ey;
         }

@@ -16,7 +16,7 @@ namespace igk {
 struct BlockGeom {
     int nx, ny, nz;
     int ntx, nty;         // tile counts in x, y
-    int ox, oy;           // output extent of a tile in x, y
+    int ox, oy;           // largest output extent of a tile in x, y (the split below keeps every tile within it)
     int W;                // wavefronts per workgroup (== blockDim.y)
     int vec;              // 1: lane chunks are whole and aligned (vector I/O)
     int R;                // rows per wavefront (1, 2 or 4); a tile has W * R rows
@@ -26,6 +26,19 @@ struct BlockGeom {
 struct Piece {
     int tx, ty, z0, z1;
 };
+
+// Output extent of tile k: rows [k ny / nty, (k+1) ny / nty); columns from
+// k nx / ntx rounded up to a multiple of V to the next tile's start (nx for
+// the last).  The streaming kernel computes the same bounds.
+inline void tile_rows(const BlockGeom& g, int k, int* y0, int* y1) {
+    *y0 = (int)((long)k * g.ny / g.nty);
+    *y1 = (int)((long)(k + 1) * g.ny / g.nty);
+}
+inline void tile_cols(const BlockGeom& g, int V, int k, int* x0, int* x1) {
+    const long q = (long)g.ntx * V;
+    *x0 = V * (int)(((long)k * g.nx + q - 1) / q);
+    *x1 = k + 1 == g.ntx ? g.nx : V * (int)(((long)(k + 1) * g.nx + q - 1) / q);
+}
 
 // LDS bytes of the streaming kernel: two regions of T levels, each level
 // W + 2 row slots of 64 V floats (current rows and up-edge terms).

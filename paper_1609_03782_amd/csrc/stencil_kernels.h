@@ -366,6 +366,18 @@ constexpr bool y_row_shared() {
 // One piece of one pass: the whole per-workgroup algorithm above.  `lds`
 // must hold stream_lds_bytes(V, T, W) bytes.  Called by k_stream (one cube)
 // and by the batch round kernel.
+// Calls f(std::integral_constant<int, 2^k - 1>) for the k in 0..K with
+// vmask == 2^k - 1 (k = 0 when no larger one matches).
+template <int K, typename F>
+__device__ __forceinline__ void level_mask_dispatch(int vmask, F&& f) {
+    if constexpr (K == 0) {
+        f(std::integral_constant<int, 0>{});
+    } else {
+        if (vmask == (1 << K) - 1) f(std::integral_constant<int, (1 << K) - 1>{});
+        else level_mask_dispatch<K - 1>(vmask, f);
+    }
+}
+
 template <int COND, typename ST, int V, int T, bool VEC, int R>
 __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __restrict__ dst, const BlockGeom& g,
                                              const Piece pc, const DevParams& P, float* __restrict__ lds) {
@@ -380,8 +392,14 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     const int rows = W * R;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
 
-    const int ox0 = pc.tx * g.ox, oy0 = pc.ty * g.oy;
-    const int ox1 = min(ox0 + g.ox, nx), oy1 = min(oy0 + g.oy, ny);
+    // tiles share the rows evenly (tile k outputs rows [k ny / nty, (k+1) ny / nty))
+    // and the columns evenly in whole lane chunks (tile k starts at k nx / ntx
+    // rounded up to a multiple of V), so no tile is a thin ragged remainder;
+    // the planner's geometry guarantees each tile's outputs fit ox x oy
+    const int oy0 = (int)((long)pc.ty * ny / g.nty), oy1 = (int)((long)(pc.ty + 1) * ny / g.nty);
+    const long xq = (long)g.ntx * V;
+    const int ox0 = V * (int)(((long)pc.tx * nx + xq - 1) / xq);
+    const int ox1 = pc.tx + 1 == g.ntx ? nx : V * (int)(((long)(pc.tx + 1) * nx + xq - 1) / xq);
     const int oz0 = pc.z0, oz1 = pc.z1;
     const int rx0 = g.ntx > 1 ? ox0 - g.hx : 0;
     const int ry0 = g.nty > 1 ? oy0 - T : 0;
@@ -514,11 +532,28 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     for (int t = 0; t < T; ++t)
         valid[t] = row_in && y >= lo_base + (t + 1) * lo_step && y < hi_base - (t + 1) * hi_step;
 
+    // Levels exact on this wavefront's row(s): bit t for level t.  A row's
+    // validity holds for the whole piece, and level t + 1 valid implies level t
+    // valid, so the mask is 2^k - 1.  In passes of depth 1 and 2 the steady
+    // loop is compiled once per mask, with the mask a compile-time constant: with no skip branch inside
+    // the loop there are no control-flow joins, and the compiler keeps the
+    // register rotation without copies.
+    int vmask = 0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        bool v;
+        if constexpr (R == 1) v = valid[t];
+        else v = __any(valid[t]);
+        vmask |= v ? 1 << t : 0;
+    }
+
     // One step.  STEADY: every level computes and has the plane above (the
     // steps T <= s < nin), so none of the start/end conditions are evaluated.
-    auto step = [&](auto parity, auto steady, int s) {
+    // VM >= 0: the validity mask, known at compile time; -1: test valid[] here.
+    auto step = [&](auto parity, auto steady, auto vm, int s) {
         constexpr int p = decltype(parity)::value, q = p ^ 1;
         constexpr bool STEADY = decltype(steady)::value;
+        constexpr int VM = decltype(vm)::value;
         if (STEADY || s < nin) {
             if constexpr (VEC) {
 #pragma unroll
@@ -543,7 +578,9 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
             // halo rows of a level are never used by a valid row: skip them
             // (with R > 1, when no row of the wavefront is valid)
             if (!compute) continue;
-            if constexpr (R == 1) {
+            if constexpr (VM >= 0) {
+                if (((VM >> t) & 1) == 0) continue;   // a constant once the level loop is unrolled
+            } else if constexpr (R == 1) {
                 if (!valid[t]) continue;
             } else {
                 if (!__any(valid[t])) continue;
@@ -645,24 +682,32 @@ __device__ __forceinline__ void stream_piece(const ST* __restrict__ src, ST* __r
     using PA = std::integral_constant<int, PT>;
     using PB = std::integral_constant<int, PT ^ 1>;
 
+    using VRT = std::integral_constant<int, -1>;   // validity tested at run time
+
     // prologue: steps 0 .. T-1 (parity s & 1)
 #pragma unroll
     for (int s0 = 0; s0 < T; ++s0) {
         if (s0 < nsteps) {
-            if ((s0 & 1) == 0) step(I0{}, GEN{}, s0);
-            else step(I1{}, GEN{}, s0);
+            if ((s0 & 1) == 0) step(I0{}, GEN{}, VRT{}, s0);
+            else step(I1{}, GEN{}, VRT{}, s0);
         }
     }
     // steady state: steps T .. nin-1, two per iteration
     int s = T;
-    for (; s + 1 < nin; s += 2) {
-        step(PA{}, STD{}, s);
-        step(PB{}, STD{}, s + 1);
-    }
+    auto steady_loop = [&](auto vm) {
+        for (; s + 1 < nin; s += 2) {
+            step(PA{}, STD{}, vm, s);
+            step(PB{}, STD{}, vm, s + 1);
+        }
+    };
+    // deeper passes keep one loop: their T + 1 copies would not fit the
+    // register file without spilling
+    if constexpr (T <= 2) level_mask_dispatch<T>(vmask, steady_loop);
+    else steady_loop(VRT{});
     // remaining steps: at most one steady one, then the epilogue
     for (; s < nsteps; ++s) {
-        if (((s - T) & 1) == 0) step(PA{}, GEN{}, s);
-        else step(PB{}, GEN{}, s);
+        if (((s - T) & 1) == 0) step(PA{}, GEN{}, VRT{}, s);
+        else step(PB{}, GEN{}, VRT{}, s);
     }
 }
 

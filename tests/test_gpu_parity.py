@@ -244,7 +244,7 @@ def test_reduce_and_compare(dev):
 # so with nx a multiple of V the vector path serves them (1040, 600), else
 # the scalar one (1037).  Bitwise against the naive schedule, in FP32 and in
 # bfloat16 storage (buffer loads and stores), and FP32 against the oracle.
-WIDE_SHAPES = [(4, 5, 1040), (3, 4, 1037), (6, 9, 600)]
+WIDE_SHAPES = [(4, 5, 1040), (3, 4, 1037), (6, 9, 600), (5, 6, 991)]
 
 
 @pytest.mark.parametrize("cond", CONDS)

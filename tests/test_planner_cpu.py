@@ -14,6 +14,19 @@ SCHEDS = [dict(t_block=2, waves=16), dict(t_block=1, waves=16), dict(t_block=2, 
           dict(t_block=1, waves=3, vec=2, zchunk=1)]
 
 
+def tile_rows(g, ny, k):
+    """Rows [y0, y1) that y tile k outputs (the even split the header states)."""
+    return k * ny // g["nty"], (k + 1) * ny // g["nty"]
+
+
+def tile_cols(g, nx, k):
+    """Columns [x0, x1) that x tile k outputs: starts at k nx / ntx rounded
+    up to whole lane chunks, the last tile ends at nx."""
+    q = g["ntx"] * g["V"]
+    start = lambda i: nx if i == g["ntx"] else g["V"] * -(-(i * nx) // q)
+    return start(k), start(k + 1)
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("sched", SCHEDS)
 def test_pieces_cover_every_output_once(shape, sched):
@@ -27,9 +40,10 @@ def test_pieces_cover_every_output_once(shape, sched):
         cover = np.zeros(shape, np.int32)
         for tx, ty, z0, z1 in pcs:
             assert 0 <= tx < g["ntx"] and 0 <= ty < g["nty"] and 0 <= z0 < z1 <= nz
-            x0, y0 = tx * g["ox"], ty * g["oy"]
-            assert x0 < nx and y0 < ny
-            cover[z0:z1, y0:y0 + g["oy"], x0:x0 + g["ox"]] += 1
+            (x0, x1), (y0, y1) = tile_cols(g, nx, tx), tile_rows(g, ny, ty)
+            assert 0 <= x0 < x1 <= nx and x1 - x0 <= g["ox"] and x0 % g["V"] == 0
+            assert 0 <= y0 < y1 <= ny and y1 - y0 <= g["oy"]
+            cover[z0:z1, y0:y1, x0:x1] += 1
         assert cover.min() == 1 and cover.max() == 1, (shape, sched, T)
         if g["ntx"] == 1:
             assert 64 // g["rows"] * g["V"] >= nx
@@ -38,12 +52,12 @@ def test_pieces_cover_every_output_once(shape, sched):
 
 
 def test_balanced_split_whole_rounds():
-    g, pcs = ig.schedule_plan((512, 512, 512), dict(kind="blocked", t_block=2, waves=16), 2, ncu=256)
+    g, pcs = ig.schedule_plan((512, 512, 512), dict(kind="blocked", t_block=2, waves=12), 2, ncu=256)
     assert len(pcs) % 256 == 0
     vol = []
     for tx, ty, z0, z1 in pcs:
-        rows = min(g["oy"], 512 - ty * g["oy"])
-        vol.append(rows * (z1 - z0))
+        y0, y1 = tile_rows(g, 512, ty)
+        vol.append((y1 - y0) * (z1 - z0))
     vol = np.array(vol)
     assert vol.max() <= 1.1 * vol.mean()          # equal work per piece (within 10 %)
     # each eighth of the table (one XCD) is a contiguous band of z
@@ -91,3 +105,51 @@ def test_rows_too_long_for_blocked_schedule():
     # a tile's rows of one plane must stay below 2^30 bytes (32-bit offsets)
     why = ig.schedule_check((1, 1, 1 << 24), dict(kind="blocked", t_block=1, waves=16, vec=8), n_iter=1)
     assert why is not None and "too long" in why
+
+
+def test_even_tile_split():
+    """Tiles share the rows and columns evenly: y tiles differ by at most one
+    row, x tiles by at most one lane chunk (the last may be shorter by the
+    row's ragged end), none exceeds the tile's output extent, and together
+    they cover the row once; near-worst cases (n just below a multiple of the
+    extent) included."""
+    for nx in (600, 991, 992, 993, 1037, 1480, 1489, 2048, 4095):
+        for V in (2, 4, 8):
+            for T in (1, 2, 4):
+                s = dict(kind="blocked", t_block=T, waves=12, vec=V)
+                if ig.schedule_check((2, 30, nx), s, n_iter=T) is not None:
+                    continue
+                g, _ = ig.schedule_plan((2, 30, nx), s, T)
+                w = [tile_cols(g, nx, i) for i in range(g["ntx"])]
+                assert w[0][0] == 0 and w[-1][1] == nx
+                assert all(a[1] == b[0] for a, b in zip(w, w[1:]))
+                widths = [b - a for a, b in w]
+                assert max(widths) <= g["ox"] and min(widths) > 0, (nx, V, T, g)
+                assert max(widths[:-1] or widths) - min(widths[:-1] or widths) <= V
+    for ny in (13, 100, 499, 500, 511, 512, 513, 1000):
+        for waves, T in ((12, 2), (14, 2), (10, 2), (16, 1), (9, 3)):
+            s = dict(kind="blocked", t_block=T, waves=waves)
+            if ig.schedule_check((2, ny, 64), s, n_iter=T) is not None:
+                continue
+            g, _ = ig.schedule_plan((2, ny, 64), s, T)
+            h = [tile_rows(g, ny, j) for j in range(g["nty"])]
+            assert h[0][0] == 0 and h[-1][1] == ny and all(a[1] == b[0] for a, b in zip(h, h[1:]))
+            rows = [b - a for a, b in h]
+            assert max(rows) <= g["oy"] and max(rows) - min(rows) <= 1, (ny, waves, T, g)
+
+
+def test_ragged_shapes_balance_in_one_round():
+    """A cube whose rows do not divide into whole tiles still gets one round
+    of pieces, and no piece is longer in z than the tile count forces: with
+    k = floor(256 / tiles) pieces per tile at least, the longest piece has at
+    most ceil(nz / k) planes (a thin last tile used to get a single piece of
+    all nz planes that outlasted every other piece)."""
+    for shape, sched in [((512, 512, 512), dict(t_block=2, waves=14)), ((500, 500, 500), dict(t_block=2, waves=12)),
+                         ((512, 512, 512), dict(t_block=1, waves=12)), ((512, 512, 512), dict(t_block=2, waves=10)),
+                         ((512, 500, 512), dict(t_block=2, waves=16))]:
+        g, pcs = ig.schedule_plan(shape, dict(kind="blocked", **sched), sched["t_block"], ncu=256)
+        tiles = g["ntx"] * g["nty"]
+        assert len(pcs) <= 256 and tiles <= 256
+        k = 256 // tiles
+        planes = np.array([z1 - z0 for tx, ty, z0, z1 in pcs])
+        assert planes.max() <= -(-shape[0] // k), (shape, sched, planes.max(), k)
