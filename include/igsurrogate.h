@@ -131,7 +131,10 @@ ig_status ig_surrogate_infer_checked(ig_surrogate* s, const ig_params* p, const 
  * ig_conv3d_weight_grad: FP32 d_dw [27][c_in][c_out] and d_db [c_out] of a
  *   conv with input d_a bf16 [v][c_in] (1 or 32) and output gradient d_dz
  *   bf16 [v][c_out] (1 or 32); partial sums in a fixed order (deterministic).
- * All three allocate temporaries and wait for the stream. */
+ * All three allocate temporaries and wait for the stream, and return
+ * IG_ERR_INVALID_ARG for cubes of 2^31 / 32 voxels or more (one kernel runs
+ * over the whole cube with 32-bit element offsets; the network's own entry
+ * points tile such cubes). */
 ig_status ig_conv3d_forward(const void* d_in, int32_t c_in, const float* d_w, const float* d_b, int32_t c_out,
                             int32_t epilogue, void* d_aux, void* d_out, int64_t nx, int64_t ny, int64_t nz,
                             void* hip_stream);

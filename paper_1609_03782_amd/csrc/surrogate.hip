@@ -745,6 +745,10 @@ extern "C" ig_status ig_surrogate_last_grad_norm(const ig_surrogate* s, double* 
 }
 
 // ------------------------------------------------------------ building blocks
+// The single-layer entry points run one kernel over the whole cube, whose
+// activations are addressed with 32-bit element offsets.
+constexpr int64_t kMaxConvVox = (1LL << 31) / 32;
+
 extern "C" ig_status ig_conv3d_forward(const void* d_in, int32_t c_in, const float* d_w, const float* d_b, int32_t c_out,
                                        int32_t epilogue, void* d_aux, void* d_out, int64_t nx, int64_t ny, int64_t nz,
                                        void* hip_stream) {
@@ -754,6 +758,7 @@ extern "C" ig_status ig_conv3d_forward(const void* d_in, int32_t c_in, const flo
     if (epilogue == EPI_GELU && c_out != 32) return fail(IG_ERR_INVALID_ARG, "gelu epilogue needs 32 outputs");
     if (epilogue == EPI_RESID && (c_out != 1 || !d_aux || !d_b)) return fail(IG_ERR_INVALID_ARG, "residual epilogue");
     if (nx < 1 || ny < 1 || nz < 1) return fail(IG_ERR_INVALID_ARG, "bad shape");
+    if (nx * ny * nz >= kMaxConvVox) return fail(IG_ERR_INVALID_ARG, "cube too large: voxels x 32 must stay below 2^31");
     hipStream_t st = (hipStream_t)hip_stream;
     Dev pk, bias;
     HIP_TRY(pk.ensure(packed_count(c_in, c_out, 0) * 16));
@@ -773,6 +778,7 @@ extern "C" ig_status ig_conv3d_input_grad(const void* d_dz, int32_t c_out, const
         return fail(IG_ERR_INVALID_ARG, "bad conv arguments");
     if (d_aux && c_in != 32) return fail(IG_ERR_INVALID_ARG, "gelu' epilogue needs 32 inputs");
     if (nx < 1 || ny < 1 || nz < 1) return fail(IG_ERR_INVALID_ARG, "bad shape");
+    if (nx * ny * nz >= kMaxConvVox) return fail(IG_ERR_INVALID_ARG, "cube too large: voxels x 32 must stay below 2^31");
     hipStream_t st = (hipStream_t)hip_stream;
     Dev pk;
     HIP_TRY(pk.ensure(packed_count(c_in, c_out, 1) * 16));
@@ -788,6 +794,7 @@ extern "C" ig_status ig_conv3d_weight_grad(const void* d_a, int32_t c_in, const 
     if (!d_a || !d_dz || !d_dw || !d_db || !(c_in == 1 || c_in == 32) || !(c_out == 1 || c_out == 32))
         return fail(IG_ERR_INVALID_ARG, "bad conv arguments");
     if (nx < 1 || ny < 1 || nz < 1) return fail(IG_ERR_INVALID_ARG, "bad shape");
+    if (nx * ny * nz >= kMaxConvVox) return fail(IG_ERR_INVALID_ARG, "cube too large: voxels x 32 must stay below 2^31");
     hipStream_t st = (hipStream_t)hip_stream;
     Dev part, partb, pad;
     if (c_out == 32) {

@@ -244,3 +244,18 @@ def test_smooth_set_path_validation():
     assert ig.lib().ig_smooth_set_path(-1) == ig.IG_ERR_INVALID_ARG
     assert ig.lib().ig_smooth_set_path(1) == ig.IG_OK
     assert ig.lib().ig_smooth_set_path(0) == ig.IG_OK
+
+
+def test_single_layer_conv_rejects_cubes_past_32bit_offsets():
+    """The single-layer surrogate entry points run one kernel over the whole
+    cube; a cube of 2^31 / 32 voxels or more is refused on the host, before
+    any device work."""
+    from paper_1609_03782_amd import surrogate as sg
+    L = sg.slib()
+    fake = ctypes.c_void_p(0x1000)
+    n = (1 << 26)                         # 2^26 voxels x 32 channels = 2^31
+    assert L.ig_conv3d_forward(fake, 32, fake, fake, 32, 1, None, fake, 1 << 10, 1 << 8, n >> 18, None) \
+        == ig.IG_ERR_INVALID_ARG
+    assert b"too large" in ig.lib().ig_last_error()
+    assert L.ig_conv3d_input_grad(fake, 32, fake, 32, None, fake, 1 << 10, 1 << 8, n >> 18, None) == ig.IG_ERR_INVALID_ARG
+    assert L.ig_conv3d_weight_grad(fake, 32, fake, 32, fake, fake, 1 << 10, 1 << 8, n >> 18, None) == ig.IG_ERR_INVALID_ARG
