@@ -335,11 +335,15 @@ def bench_batch(steps):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     lat = np.array(ig.batch(items, want_latency=True)["latency_ms"])
+    launch = "one persistent launch" if ig.batch_get_launch() else "one launch per pass round"
+    ig.batch_set_launch(False)
     return {"cubes": len(items), "voxels": int(sum(x.numel() for x, _, _ in items)), "voxel_iters": int(work),
             "ms_per_batch": round(ms, 4), "Gvoxel_iter_s": round(work / ms / 1e6, 2),
             "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
             "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
-            "policy": "pass-major rounds, longest cubes first", "t_block": T, "waves": W, "zchunk": Z}
+            "policy": "pass-major items, longest cubes first",
+            "launch": launch,
+            "t_block": T, "waves": W, "zchunk": Z}
 
 
 def bench_batch_tiny(steps, count=512, side=32):

@@ -233,8 +233,13 @@ typedef struct {
 /* Filter `count` independent cubes of uneven sizes and parameters with one
  * graph launch (all items: FP32 storage, same device).  The graph holds the
  * per-cube noise-level scans, one launch for the LDS-resident cubes (below)
- * and one kernel launch per pass round (round r: pass r of every other cube
- * that has one).  It is built once per batch signature (item shapes and
+ * and either one kernel launch per pass round (round r: pass r of every other
+ * cube that has one) or, with ig_batch_set_launch(1), one persistent launch
+ * that runs every pass of every cube: its workgroups take (cube, pass, piece)
+ * items in pass-major order from a device counter and start a piece once the
+ * cube's previous pass is done.  A dependency wait that lasts more than 2 s
+ * marks every item failed, sets every output to NaN and makes a waiting call
+ * return IG_ERR_DEVICE.  The graph is built once per batch signature (item shapes and
  * parameters, whether each item runs in place, the buffers' alignment within
  * 16 bytes, and the batch settings) and replayed on later calls with the same
  * signature; a call with other buffers of the same signature rewrites the
@@ -270,6 +275,13 @@ int32_t ig_batch_cache_size(void);
  * share one conductance, and those not run LDS-resident need nx <= 256. */
 ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves, int32_t zchunk);
 
+/* Launch mode of later ig_filter_batch plans: 0 (default) one launch per
+ * pass round, 1 one persistent launch (see ig_filter_batch); results are
+ * bitwise the same.  Host only.  Errors: IG_ERR_INVALID_ARG for other
+ * values.  ig_batch_get_launch returns the current mode. */
+ig_status ig_batch_set_launch(int32_t persistent);
+int32_t ig_batch_get_launch(void);
+
 /* Resident limit of later ig_filter_batch plans: cubes of at most max_voxels
  * voxels (0..32768; 0 = none) run LDS-resident.  Host only.  Errors:
  * IG_ERR_INVALID_ARG outside that range. */
@@ -278,12 +290,13 @@ ig_status ig_batch_set_resident(int32_t max_voxels);
 /* The current resident limit (IG_ERR_INVALID_ARG for NULL). */
 ig_status ig_batch_get_resident(int32_t* max_voxels);
 
-/* Batch autotuner: runs the batch with t_block 1..4, waves 8, 12 and 16 and
- * z-chunks of 16, 32 and 64 planes, and, when some cube is small enough, with the
- * resident limit at 32768 and at 0; keeps the fastest (sets it as by
- * ig_batch_set_schedule and ig_batch_set_resident, and keeps only that plan
- * cached) and returns the schedule (the resident limit through
- * ig_batch_get_resident).  Every item must have d_in != d_out (outputs are
+/* Batch autotuner: runs the batch with t_block 1..4, waves 8, 12 and 16,
+ * z-chunks of 16, 32 and 64 planes, both launch modes, and, when some cube is
+ * small enough, with the resident limit at 32768 and at 0; keeps the fastest
+ * (sets it as by ig_batch_set_schedule, ig_batch_set_launch and
+ * ig_batch_set_resident, and keeps only that plan cached) and returns the
+ * schedule (the launch mode through ig_batch_get_launch, the resident limit
+ * through ig_batch_get_resident).  Every item must have d_in != d_out (outputs are
  * overwritten; inputs are read only).  Waits for the stream. */
 ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
                             int32_t* best_t_block, int32_t* best_waves, int32_t* best_zchunk, double* best_ms);

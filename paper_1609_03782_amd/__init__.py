@@ -111,6 +111,8 @@ SIGNATURES = {
     "ig_batch_cache_clear": (None, []),
     "ig_batch_cache_size": (ctypes.c_int32, []),
     "ig_batch_set_schedule": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "ig_batch_set_launch": (ctypes.c_int, [ctypes.c_int32]),
+    "ig_batch_get_launch": (ctypes.c_int32, []),
     "ig_batch_set_resident": (ctypes.c_int, [ctypes.c_int32]),
     "ig_batch_get_resident": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32)]),
     "ig_compare": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_int, _P,
@@ -457,6 +459,15 @@ def batch_cache_size():
 
 def batch_set_schedule(t_block=0, waves=16, zchunk=32):
     _check(lib().ig_batch_set_schedule(int(t_block), int(waves), int(zchunk)), "ig_batch_set_schedule")
+
+
+def batch_set_launch(persistent=False):
+    """Later batches: one persistent launch (True) or one launch per pass round (False)."""
+    _check(lib().ig_batch_set_launch(int(bool(persistent))), "ig_batch_set_launch")
+
+
+def batch_get_launch():
+    return bool(lib().ig_batch_get_launch())
 
 
 def batch_set_resident(max_voxels=32768):

@@ -49,7 +49,14 @@ struct BatchItem {
     int cube, pass, piece, depth;
 };
 
-constexpr int kCtrDone = 0;   // + cube: pieces of its last pass that are done
+constexpr int kCtrNext = 0;    // persistent launch: next item to take
+constexpr int kCtrAbort = 1;   // persistent launch: set when a dependency wait ran out of time
+constexpr int kCtrFin = 2;     // + cube: pieces done (rounds: of the last pass; persistent: of every pass)
+// A dependency wait of the persistent launch gives up after 2 s of the
+// 100 MHz constant clock (the whole 96-cube batch takes ~12 ms): every cube
+// is then marked failed and every workgroup leaves, so a mistake ends in an
+// error, never in a wait without end.
+constexpr unsigned long long kWaitTicks = 200000000ULL;
 
 // ------------------------------------------------------------ rms pre-pass
 struct SumChunk {
@@ -217,8 +224,104 @@ k_batch_round(const BatchCube* __restrict__ cubes, const BatchItem* __restrict__
     if (item.pass == cb.npass - 1) {   // completion stamp of the cube
         __syncthreads();
         if (tid == 0) {
-            const int prev = atomicAdd(&ctr[kCtrDone + item.cube], 1);
+            const int prev = atomicAdd(&ctr[kCtrFin + item.cube], 1);
             if (prev + 1 == cb.npieces) stamps[1 + item.cube] = wall_clock64();
+        }
+    }
+}
+
+// The whole item list in one launch: each workgroup takes the next item from
+// a counter, waits until every piece of the previous pass of its cube is
+// done, runs the piece and counts it done.  Items are listed pass-major (all
+// cubes' pass r before any cube's pass r + 1), so an item waits only on items
+// taken earlier by running workgroups, which wait only on still earlier ones:
+// every wait ends.  Cross-XCD visibility (each XCD has its own L2): the
+// waiting wavefront polls with relaxed device-scope loads (no cache
+// invalidation per poll), then takes one acquire fence (invalidate) before
+// the workgroup reads the previous pass; after a piece, every wavefront
+// drains its stores, the workgroup synchronises, and wavefront 0 takes one
+// release fence (L2 write-back) before counting the piece.  Pieces of a cube
+// whose input was non-finite run nothing but are still counted.
+//
+// All control flow around the barriers is wave-uniform: wavefront 0 as a
+// whole takes, waits for and publishes items, every value it branches on is
+// made uniform with readfirstlane, and each counter update is one atomic whose
+// other lanes add 0.  (With a single-lane `if` around the dequeue, the
+// compiler let the other lanes of the loop pass the start barrier without the
+// dequeue, so they kept rerunning the previous item.)
+template <int COND, int T>
+__global__ void __launch_bounds__(1024)
+k_batch_persist(const BatchCube* __restrict__ cubes, const BatchItem* __restrict__ items, int nitems,
+                const Piece* __restrict__ pieces, DevParams* __restrict__ prm, int ncubes, int* __restrict__ ctr,
+                unsigned long long* __restrict__ stamps) {
+    extern __shared__ float lds[];
+    __shared__ int s_item, s_go;
+    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const unsigned long long t_end = wall_clock64() + kWaitTicks;
+    const int one = lane == 0 ? 1 : 0;
+    for (;;) {
+        if (w == 0) {
+            const int it = __builtin_amdgcn_readfirstlane(atomicAdd(&ctr[kCtrNext], one));
+            int go = it < nitems ? 1 : 0;
+            if (go && __builtin_amdgcn_readfirstlane(
+                          __hip_atomic_load(&ctr[kCtrAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+                go = 0;
+            if (go) {
+                const int cube = __builtin_amdgcn_readfirstlane(items[it].cube);
+                const int need = __builtin_amdgcn_readfirstlane(items[it].pass * cubes[cube].npieces);
+                if (need > 0) {
+                    for (;;) {
+                        const int fin = __builtin_amdgcn_readfirstlane(
+                            __hip_atomic_load(&ctr[kCtrFin + cube], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        if (fin >= need) break;
+                        if (__builtin_amdgcn_readfirstlane(
+                                __hip_atomic_load(&ctr[kCtrAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                            go = 0;
+                            break;
+                        }
+                        if (wall_clock64() > t_end) {
+                            __hip_atomic_store(&ctr[kCtrAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            for (int c = lane; c < ncubes; c += 64)
+                                __hip_atomic_store(&prm[c].abort, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            go = 0;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    __builtin_amdgcn_s_waitcnt(0);
+                }
+            }
+            s_item = it;   // every lane writes the same values
+            s_go = go;
+        }
+        __syncthreads();
+        const int go = __builtin_amdgcn_readfirstlane(s_go);
+        if (!go) break;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        const BatchItem item = items[it];
+        const BatchCube& cb = cubes[item.cube];
+        const DevParams P = prm[item.cube];
+        if (!P.abort) {
+            const int k = item.pass + 1;
+            const float* src = item.pass == 0 ? (cb.stage ? cb.scratch : cb.in)
+                                              : (((cb.npass - (k - 1)) % 2 == 0) ? cb.out : cb.scratch);
+            float* dst = ((cb.npass - k) % 2 == 0) ? cb.out : cb.scratch;
+            const Piece pc = pieces[cb.piece_off + item.piece];
+            if constexpr (T >= 1) if (item.depth == 1) run_piece_v<COND, T, 1>(cb, src, dst, pc, P, lds);
+            if constexpr (T >= 2) if (item.depth == 2) run_piece_v<COND, T, 2>(cb, src, dst, pc, P, lds);
+            if constexpr (T >= 3) if (item.depth == 3) run_piece_v<COND, T, 3>(cb, src, dst, pc, P, lds);
+            if constexpr (T >= 4) if (item.depth == 4) run_piece_v<COND, T, 4>(cb, src, dst, pc, P, lds);
+        }
+        __builtin_amdgcn_s_waitcnt(0);   // this wavefront's stores have reached its L2
+        __syncthreads();
+        if (w == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
+            const int prev = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_fetch_add(&ctr[kCtrFin + item.cube], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (prev + 1 == cb.npass * cb.npieces) stamps[1 + item.cube] = wall_clock64();
         }
     }
 }
@@ -342,6 +445,25 @@ static BatchKernel batch_kernel(int cond, int T) {
     }
 }
 
+using PersistKernel = void (*)(const BatchCube*, const BatchItem*, int, const Piece*, DevParams*, int, int*,
+                               unsigned long long*);
+template <int COND>
+static PersistKernel persist_kernel_T(int T) {
+    switch (T) {
+        case 1: return k_batch_persist<COND, 1>;
+        case 2: return k_batch_persist<COND, 2>;
+        case 3: return k_batch_persist<COND, 3>;
+        default: return k_batch_persist<COND, 4>;
+    }
+}
+static PersistKernel persist_kernel(int cond, int T) {
+    switch (cond) {
+        case COND_INTENSITY: return persist_kernel_T<COND_INTENSITY>(T);
+        case COND_PM_EXP: return persist_kernel_T<COND_PM_EXP>(T);
+        default: return persist_kernel_T<COND_PM_RATIONAL>(T);
+    }
+}
+
 }  // namespace igk
 
 // ====================================================================== host
@@ -371,6 +493,8 @@ struct DevBuf {
 struct BatchPlan {
     int device = 0;
     int cond = 0, T = 1, W = 16, Z = 32;
+    int persist = 0;              // 1: one persistent launch instead of one launch per round
+    int grid = 0;                 // persistent launch: workgroups
     int count = 0;
     std::vector<int> passes;
     DevBuf<float> scratch;
@@ -428,13 +552,14 @@ uint64_t g_use = 0;
 // and the same settings reuses it without validating or hashing again.
 struct LastCall {
     std::vector<ig_batch_item> items;
-    int device = -1, T = 0, W = 0, Z = 0, res = 0;
+    int device = -1, T = 0, W = 0, Z = 0, res = 0, persist = 0;
     BatchPlan* plan = nullptr;
 };
 LastCall g_last;
 int g_batch_T = 0;    // 0: default choice
 int g_batch_W = 16;
 int g_batch_Z = 32;   // planes per z-chunk of a piece
+int g_batch_persist = 0;   // 1: one persistent launch runs every pass
 constexpr int kResidentMax = kResThreads * kResPerThread;   // 32768 voxels: 128 KiB of LDS
 int g_batch_res = kResidentMax;   // cubes of at most this many voxels run LDS-resident (0: none)
 
@@ -445,6 +570,7 @@ std::vector<uint64_t> signature(const ig_batch_item* items, int count, int devic
     key.push_back((uint64_t)g_batch_W);
     key.push_back((uint64_t)g_batch_Z);
     key.push_back((uint64_t)g_batch_res);
+    key.push_back((uint64_t)g_batch_persist);
     for (int i = 0; i < count; ++i) {
         uint64_t w[(sizeof(ig_params) + 7) / 8] = {};
         std::memcpy(w, &items[i].p, sizeof(ig_params));
@@ -496,6 +622,7 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     }
     bp->W = g_batch_W;
     bp->Z = g_batch_Z;
+    bp->persist = g_batch_persist;
     bp->T = g_batch_T > 0 ? g_batch_T : std::max(1, std::min(2, maxn));
     const int T = bp->T, W = bp->W;
     if (maxnx > 256) return fail(IG_ERR_UNSUPPORTED, "batch items need nx <= 256 (unless LDS-resident)");
@@ -622,7 +749,7 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     HIP_TRY(bp->d_nvox.alloc(count));
     HIP_TRY(bp->d_params.alloc(count));
     HIP_TRY(bp->d_outsum.alloc(count));
-    HIP_TRY(bp->d_ctr.alloc(kCtrDone + count));
+    HIP_TRY(bp->d_ctr.alloc(kCtrFin + count));
     HIP_TRY(bp->d_stamps.alloc(1 + count));
     HIP_TRY(bp->d_res.alloc(res_all.size()));
     if (!res_all.empty())
@@ -644,8 +771,15 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     HIP_TRY(hipMemcpy(bp->d_nvox.p, nvox.data(), count * sizeof(long), hipMemcpyHostToDevice));
 
     BatchKernel kern = batch_kernel(bp->cond, T);
-    if (lds > 65536)
+    PersistKernel pkern = persist_kernel(bp->cond, T);
+    if (lds > 65536) {
         HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        HIP_TRY(hipFuncSetAttribute((const void*)pkern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    // persistent launch: as many workgroups as the GPU holds at once (no more
+    // than there are items; the kernel's own 8 bytes of LDS counted), so
+    // every workgroup that takes an item is running
+    bp->grid = (int)std::min<long>(bp->nitems, (long)ncu * resident_per_cu(W, lds + 16));
     ResidentKernel rkern = resident_kernel(bp->cond);
     const size_t res_lds_max = *std::max_element(bp->res_lds.begin(), bp->res_lds.end());
     if (res_lds_max > 65536)
@@ -658,7 +792,7 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
     hipStream_t s = bp->cap;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, bp->d_ctr.p, kCtrDone + count, bp->d_stamps.p,
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, bp->d_ctr.p, kCtrFin + count, bp->d_stamps.p,
                        1 + count);
     chk(hipGetLastError());
     if (bp->nchunks > 0) {
@@ -681,12 +815,20 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
                            bp->d_res.p + bp->res_off[j], bp->d_params.p, bp->d_stamps.p);
         chk(hipGetLastError());
     }
-    for (size_t r = 0; r + 1 < bp->round_off.size(); ++r) {
-        const int n = bp->round_off[r + 1] - bp->round_off[r];
-        if (n <= 0) continue;
-        hipLaunchKernelGGL(kern, dim3(n), dim3(64, W), lds, s, bp->d_cubes.p, bp->d_items.p + bp->round_off[r],
-                           bp->d_pieces.p, bp->d_params.p, bp->d_ctr.p, bp->d_stamps.p);
-        chk(hipGetLastError());
+    if (bp->persist) {
+        if (bp->nitems > 0) {
+            hipLaunchKernelGGL(pkern, dim3(bp->grid), dim3(64, W), lds, s, bp->d_cubes.p, bp->d_items.p, bp->nitems,
+                               bp->d_pieces.p, bp->d_params.p, count, bp->d_ctr.p, bp->d_stamps.p);
+            chk(hipGetLastError());
+        }
+    } else {
+        for (size_t r = 0; r + 1 < bp->round_off.size(); ++r) {
+            const int n = bp->round_off[r + 1] - bp->round_off[r];
+            if (n <= 0) continue;
+            hipLaunchKernelGGL(kern, dim3(n), dim3(64, W), lds, s, bp->d_cubes.p, bp->d_items.p + bp->round_off[r],
+                               bp->d_pieces.p, bp->d_params.p, bp->d_ctr.p, bp->d_stamps.p);
+            chk(hipGetLastError());
+        }
     }
     if (bp->nchunks > 0) {
         hipLaunchKernelGGL(k_batch_nan, dim3(bp->nchunks), dim3(256), 0, s, bp->d_cubes.p, bp->d_chunks.p,
@@ -707,7 +849,7 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
 static bool same_as_last(const ig_batch_item* items, int count, int device) {
     return g_last.plan && g_last.device == device && (int)g_last.items.size() == count && g_last.T == g_batch_T &&
            g_last.W == g_batch_W && g_last.Z == g_batch_Z && g_last.res == g_batch_res &&
-           std::memcmp(g_last.items.data(), items, (size_t)count * sizeof(ig_batch_item)) == 0;
+           g_last.persist == g_batch_persist && std::memcmp(g_last.items.data(), items, (size_t)count * sizeof(ig_batch_item)) == 0;
 }
 
 extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, int device, void* hip_stream,
@@ -782,6 +924,7 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
         g_last.items.assign(items, items + count);
         g_last.device = device;
         g_last.T = g_batch_T; g_last.W = g_batch_W; g_last.Z = g_batch_Z; g_last.res = g_batch_res;
+        g_last.persist = g_batch_persist;
         g_last.plan = bp;
     }
     bp->last_use = ++g_use;
@@ -806,7 +949,7 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
     HIP_TRY(hipStreamSynchronize(s));
     int khz = 0;
     (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
-    bool bad = false;
+    bool bad = false, timed_out = false;
     for (int c = 0; c < count; ++c) {
         if (latency_ms)
             latency_ms[c] = (khz > 0 && stamps[1 + c] >= stamps[0]) ? (double)(stamps[1 + c] - stamps[0]) / khz : 0.0;
@@ -822,8 +965,11 @@ extern "C" ig_status ig_filter_batch(const ig_batch_item* items, int32_t count, 
             st.schedule = bp->resident[c] ? ig_schedule{IG_SCHED_BLOCKED, bp->niter[c], bp->resident[c], (int)p.nz, 1, 0, 0}
                                           : ig_schedule{IG_SCHED_BLOCKED, bp->T, bp->W, bp->Z, 4, 0, 0};
         }
-        if (prm[c].abort) bad = true;
+        if (prm[c].abort == 2) timed_out = true;
+        else if (prm[c].abort) bad = true;
     }
+    if (timed_out)
+        return fail(IG_ERR_DEVICE, "persistent batch: a dependency wait ran out of time (every output is set to NaN)");
     if (bad) return fail(IG_ERR_NONFINITE, "a batch item holds non-finite voxels (its output is set to NaN)");
     return IG_OK;
 }
@@ -859,47 +1005,51 @@ extern "C" ig_status ig_batch_autotune(const ig_batch_item* items, int32_t count
     for (int i = 0; i < count; ++i)
         any_small |= items[i].p.n_iter > 0 && items[i].p.nx * items[i].p.ny * items[i].p.nz <= kResidentMax;
     std::vector<int> res_modes = any_small ? std::vector<int>{kResidentMax, 0} : std::vector<int>{g_batch_res};
-    auto drop = [&](int T, int W, int Z, int R) {
+    auto drop = [&](int T, int W, int Z, int R, int P) {
         std::lock_guard<std::mutex> lk(g_mu);
-        const int t0 = g_batch_T, w0 = g_batch_W, z0 = g_batch_Z, r0 = g_batch_res;
-        g_batch_T = T; g_batch_W = W; g_batch_Z = Z; g_batch_res = R;
+        const int t0 = g_batch_T, w0 = g_batch_W, z0 = g_batch_Z, r0 = g_batch_res, p0 = g_batch_persist;
+        g_batch_T = T; g_batch_W = W; g_batch_Z = Z; g_batch_res = R; g_batch_persist = P;
         auto it = g_cache.find(signature(items, count, device));
         if (it != g_cache.end()) {
             if (g_last.plan == it->second.get()) g_last = LastCall{};
             g_cache.erase(it);
         }
-        g_batch_T = t0; g_batch_W = w0; g_batch_Z = z0; g_batch_res = r0;
+        g_batch_T = t0; g_batch_W = w0; g_batch_Z = z0; g_batch_res = r0; g_batch_persist = p0;
     };
     double best = 1e300;
-    int bT = 0, bW = 16, bZ = 32, bR = g_batch_res;
-    for (int R : res_modes)
-        for (int T = 1; T <= std::max(1, std::min(4, maxn)); ++T)
-            for (int W : {8, 12, 16})
-                for (int Z : {16, 32, 64}) {
-                    if (W <= 2 * T) continue;
-                    if (ig_batch_set_schedule(T, W, Z) != IG_OK || ig_batch_set_resident(R) != IG_OK) continue;
-                    if (ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) != IG_OK) {   // build + warm
-                        drop(T, W, Z, R);
-                        continue;
+    int bT = 0, bW = 16, bZ = 32, bR = g_batch_res, bP = 0;
+    for (int P : {0, 1})
+        for (int R : res_modes)
+            for (int T = 1; T <= std::max(1, std::min(4, maxn)); ++T)
+                for (int W : {8, 12, 16})
+                    for (int Z : {16, 32, 64}) {
+                        if (W <= 2 * T) continue;
+                        if (ig_batch_set_schedule(T, W, Z) != IG_OK || ig_batch_set_resident(R) != IG_OK ||
+                            ig_batch_set_launch(P) != IG_OK)
+                            continue;
+                        if (ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) != IG_OK) {   // build + warm
+                            drop(T, W, Z, R, P);
+                            continue;
+                        }
+                        float ms = 0.0f;
+                        bool ok = hipEventRecord(e0, s) == hipSuccess;
+                        for (int k = 0; k < 2 && ok; ++k)
+                            ok = ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) == IG_OK;
+                        ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                        if (ok && ms / 2 < best) {
+                            if (best < 1e300) drop(bT, bW, bZ, bR, bP);
+                            best = ms / 2; bT = T; bW = W; bZ = Z; bR = R; bP = P;
+                        } else {
+                            drop(T, W, Z, R, P);
+                        }
                     }
-                    float ms = 0.0f;
-                    bool ok = hipEventRecord(e0, s) == hipSuccess;
-                    for (int k = 0; k < 2 && ok; ++k)
-                        ok = ig_filter_batch(items, count, device, hip_stream, nullptr, nullptr) == IG_OK;
-                    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-                         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-                    if (ok && ms / 2 < best) {
-                        if (best < 1e300) drop(bT, bW, bZ, bR);
-                        best = ms / 2; bT = T; bW = W; bZ = Z; bR = R;
-                    } else {
-                        drop(T, W, Z, R);
-                    }
-                }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (best >= 1e300) return fail(IG_ERR_UNSUPPORTED, "no batch schedule ran");
     ig_status st = ig_batch_set_schedule(bT, bW, bZ);
     if (st == IG_OK) st = ig_batch_set_resident(bR);
+    if (st == IG_OK) st = ig_batch_set_launch(bP);
     if (st != IG_OK) return st;
     if (best_t_block) *best_t_block = bT;
     if (best_waves) *best_waves = bW;
@@ -916,6 +1066,18 @@ extern "C" ig_status ig_batch_set_schedule(int32_t t_block, int32_t waves, int32
     g_batch_W = waves;
     g_batch_Z = zchunk;
     return IG_OK;
+}
+
+extern "C" ig_status ig_batch_set_launch(int32_t persistent) {
+    if (persistent != 0 && persistent != 1) return fail(IG_ERR_INVALID_ARG, "launch mode must be 0 or 1");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_batch_persist = persistent;
+    return IG_OK;
+}
+
+extern "C" int32_t ig_batch_get_launch(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_batch_persist;
 }
 
 extern "C" ig_status ig_batch_set_resident(int32_t max_voxels) {

@@ -276,3 +276,73 @@ def test_batch_fresh_buffers_reuse_plan_and_cache_stays_bounded(dev):
         assert torch.equal(o, ig.Filter(tuple(x.shape), K=2.0, tau=1 / 16, n_iter=n).run(x)), n
     ig.batch_cache_clear()
     assert ig.batch_cache_size() == 0
+
+
+# --- persistent launch ----------------------------------------------------------
+@pytest.mark.parametrize("t_block,waves,zchunk", [(1, 8, 16), (2, 16, 7), (3, 12, 32)])
+def test_persistent_launch_bitwise_equal_to_rounds(dev, t_block, waves, zchunk):
+    """One persistent launch (workgroups take items from a device counter and
+    wait for the cube's previous pass) gives bitwise the output of one launch
+    per round, for in-place and out-of-place items, with latencies and
+    statistics filled and graph replays repeating the bytes."""
+    import torch
+    import paper_1609_03782_amd as ig
+    ig.batch_set_schedule(t_block, waves, zchunk)
+    ig.batch_set_resident(0)
+    try:
+        outs = {}
+        for persistent in (False, True):
+            ig.batch_set_launch(persistent)
+            assert ig.batch_get_launch() == persistent
+            cubes, items = _items(dev, seed=7)
+            res = ig.batch(items, want_stats=True, want_latency=True)
+            torch.cuda.synchronize()
+            outs[persistent] = [out.clone() for _, out, _ in items]
+            assert all(lat >= 0.0 for lat in res["latency_ms"])
+            for (c, n_iter, K, inplace), st in zip(cubes, res["stats"]):
+                assert st.nonfinite == 0
+            if persistent:   # graph replays on fresh buffers (in-place items: fresh inputs each time)
+                for _ in range(2):
+                    _, items2 = _items(dev, seed=7)
+                    for x, out, _ in items2:
+                        if out.data_ptr() != x.data_ptr():
+                            out.fill_(-1.0)
+                    ig.batch(items2)
+                    torch.cuda.synchronize()
+                    for a, (_, out, _) in zip(outs[True], items2):
+                        assert torch.equal(a, out)
+        for a, b in zip(outs[False], outs[True]):
+            assert torch.equal(a, b)
+    finally:
+        ig.batch_set_launch(False)
+        ig.batch_set_schedule(0, 16, 32)
+        ig.batch_set_resident(32768)
+        ig.batch_cache_clear()
+
+
+def test_persistent_launch_nonfinite_item(dev):
+    """A cube with a NaN voxel under the persistent launch: its pieces run
+    nothing but are counted, so the other cubes' passes still complete."""
+    import torch
+    import paper_1609_03782_amd as ig
+    ig.batch_set_launch(True)
+    ig.batch_set_resident(0)
+    try:
+        a = igsynth.random_cube((8, 30, 40), seed=1)
+        b = igsynth.random_cube((9, 20, 30), seed=2)
+        b[2, 3, 4] = np.nan
+        xa, xb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+        oa, ob = torch.empty_like(xa), torch.full_like(xb, 3.0)
+        kw = dict(K=2.0, tau=1 / 16, n_iter=9)
+        with pytest.raises(ig.IgError) as ei:
+            ig.batch([(xb, ob, kw), (xa, oa, kw)], want_stats=True)
+        assert ei.value.status == ig.IG_ERR_NONFINITE
+        torch.cuda.synchronize()
+        assert bool(torch.isnan(ob).all())
+        ref = ig.Filter(a.shape, **kw).run(xa)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, oa)
+    finally:
+        ig.batch_set_launch(False)
+        ig.batch_set_resident(32768)
+        ig.batch_cache_clear()

@@ -68,20 +68,25 @@ def test_batch_fullsize_sampled(dev, oracle_lib):
         x = torch.from_numpy(c).to(dev)
         cubes.append(c)
         items.append((x, torch.empty_like(x), dict(K=it.K, tau=1 / 16, n_iter=it.n_iter, cond="pm_exp")))
-    ig.batch_autotune(items)
-    res = ig.batch(items, want_stats=True)
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(3)
-    for k in range(0, 96, 12):
-        it, c = plan[k], cubes[k]
-        rho = res["stats"][k].rms_used
-        out = items[k][1].cpu().numpy()
-        pts = _points(c.shape, rng, k=3)
-        ref = oracle_lib.run_points(c, pts, "pm_exp", K=it.K, tau=1 / 16, n_iter=it.n_iter, rms=rho)
-        got = np.array([out[p] for p in pts], dtype=np.float64)
-        err = np.abs(got - ref).max()
-        assert err <= 1e-5 * rho, (k, c.shape, it.n_iter, err / rho)
-    ig.batch_cache_clear()
+    try:
+        ig.batch_autotune(items)
+        res = ig.batch(items, want_stats=True)
+        torch.cuda.synchronize()
+        print(f"batch autotuner: {'persistent launch' if ig.batch_get_launch() else 'launch per round'}")
+        rng = np.random.default_rng(3)
+        for k in range(0, 96, 12):
+            it, c = plan[k], cubes[k]
+            rho = res["stats"][k].rms_used
+            out = items[k][1].cpu().numpy()
+            pts = _points(c.shape, rng, k=3)
+            ref = oracle_lib.run_points(c, pts, "pm_exp", K=it.K, tau=1 / 16, n_iter=it.n_iter, rms=rho)
+            got = np.array([out[p] for p in pts], dtype=np.float64)
+            err = np.abs(got - ref).max()
+            assert err <= 1e-5 * rho, (k, c.shape, it.n_iter, err / rho)
+    finally:
+        ig.batch_set_launch(False)
+        ig.batch_set_schedule(0, 16, 32)
+        ig.batch_cache_clear()
 
 
 def test_surrogate_inference_fullsize_sampled(dev):
