@@ -311,8 +311,10 @@ def bench_paper_defaults(x, steps):
             "paper_gpu_s_for_1.4e8_voxels": 3.1}
 
 
-def bench_batch(steps):
-    """96 uneven cubes in one graph launch (one kernel per pass round)."""
+def bench_batch(steps, schedule=None):
+    """96 uneven cubes in one graph launch, under the batch autotuner's choice,
+    or under `schedule` = (t_block, waves, zchunk, persistent) when given (no
+    autotuning: for profiling one schedule)."""
     import numpy as np
     import torch
     import igsynth
@@ -323,7 +325,12 @@ def bench_batch(steps):
         x = torch.from_numpy(igsynth.batch_cube(it)).cuda()
         items.append((x, torch.empty_like(x), dict(K=it.K, tau=1 / 16, n_iter=it.n_iter, cond="pm_exp")))
         work += x.numel() * it.n_iter
-    T, W, Z, _ = ig.batch_autotune(items)
+    if schedule is None:
+        T, W, Z, _ = ig.batch_autotune(items)
+    else:
+        T, W, Z, P = schedule
+        ig.batch_set_schedule(T, W, Z)
+        ig.batch_set_launch(bool(P))
     prep = ig.batch_prepare(items)
     ig.batch(prep)
     torch.cuda.synchronize()
@@ -714,6 +721,8 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--clip", type=float, default=0.0, help="surrogate gradient-norm clip (0: off)")
     ap.add_argument("--threshold", type=float, default=0.05)
+    ap.add_argument("--batch-schedule", default="",
+                    help="with --workload batch: t_block,waves,zchunk,persistent (e.g. 2,16,64,1) instead of the autotuner")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of the cube size (counter calibration)")
     ap.add_argument("--smooth-only", action="store_true",
@@ -750,7 +759,8 @@ def main():
         bench_conv(args)
         return
     if args.workload == "batch":
-        print(json.dumps({"batch_96": bench_batch(max(3, args.steps // 4))}), flush=True)
+        sched = tuple(int(v) for v in args.batch_schedule.split(",")) if args.batch_schedule else None
+        print(json.dumps({"batch_96": bench_batch(max(3, args.steps // 4), sched)}), flush=True)
         return
 
     cube = igsynth.cube_field(SHAPE[2], seed=2, nz=SHAPE[0])
