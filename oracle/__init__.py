@@ -77,6 +77,8 @@ def _load():
         lib.oracle_round_bf16.restype = d
         lib.oracle_round_f16.argtypes = [d]
         lib.oracle_round_f16.restype = d
+        lib.oracle_round_n.argtypes = [p, p, p, p, i64, i32]
+        lib.oracle_round_n.restype = None
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = i32
         lib.oracle_set_threads.argtypes = [i32]
@@ -157,6 +159,42 @@ def round_bf16(x):
 def round_f16(x):
     lib = _load()
     return np.vectorize(lib.oracle_round_f16, otypes=[np.float64])(np.asarray(x, np.float64))
+
+
+def round_storage(x, name: str, d=None):
+    """Round values to the storage type `name` ("bf16", "f16", "f32"),
+    nearest with ties to even.  With d (same shape, >= 0) also return the
+    largest change of that rounding over [x - d, x + d]: zero wherever no
+    rounding boundary lies within d of x.  Returns y or (y, spread)."""
+    lib = _load()
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty_like(a)
+    if d is None:
+        lib.oracle_round_n(a.ctypes.data, None, y.ctypes.data, None, a.size, ROUND[name])
+        return y
+    dd = np.ascontiguousarray(np.broadcast_to(d, a.shape), dtype=np.float64)
+    sp = np.empty_like(a)
+    lib.oracle_round_n(a.ctypes.data, dd.ctypes.data, y.ctypes.data, sp.ctypes.data, a.size, ROUND[name])
+    return y, sp
+
+
+def step_points(cube, points, cond="pm_exp", K=2.0, tau=1.0 / 16, C=(1.0, 1.0, 1.0), rms: float = 1.0):
+    """One step at selected voxels of a large cube: (exact FP64 values,
+    first-order binary32 error bounds), each from the voxel's neighbourhood
+    (its sub-box of half-width 1, clipped to the cube, whose real faces keep
+    their boundary: after one step a voxel depends only on its six
+    neighbours).  `rms` must be the whole cube's value."""
+    a = np.asarray(cube)
+    nz, ny, nx = a.shape
+    vals, bnds = [], []
+    for (z, y, x) in points:
+        lo = [max(0, c - 1) for c in (z, y, x)]
+        hi = [min(e, c + 2) for c, e in zip((z, y, x), (nz, ny, nx))]
+        sub = a[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        ex, bd, _ = error_bound(sub, cond, K, tau, 1, C, rms=rms)
+        vals.append(ex[z - lo[0], y - lo[1], x - lo[2]])
+        bnds.append(bd[z - lo[0], y - lo[1], x - lo[2]])
+    return np.array(vals), np.array(bnds)
 
 
 def run_points(cube, points, cond="pm_exp", K=2.0, tau=1.0 / 16, n_iter=1, C=(1.0, 1.0, 1.0),

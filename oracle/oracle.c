@@ -118,6 +118,24 @@ static double round_store(double x, int mode)
     return x;
 }
 
+/* Storage rounding of n values, and the largest change of that rounding over
+ * an interval: y[i] = round(x[i]); if d != NULL, spread[i] = the largest
+ * |round(w) - round(x[i])| over |w - x[i]| <= d[i] (rounding is monotone, so
+ * it is reached at an end of the interval; zero when no rounding boundary
+ * lies within d[i] of x[i]). */
+void oracle_round_n(const double* x, const double* d, double* y, double* spread, int64_t n, int mode)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const double r = round_store(x[i], mode);
+        y[i] = r;
+        if (d && spread) {
+            const double hi = round_store(x[i] + d[i], mode) - r;
+            const double lo = r - round_store(x[i] - d[i], mode);
+            spread[i] = hi > lo ? hi : lo;
+        }
+    }
+}
+
 /* rms = sqrt(sum I^2 / N) over every voxel; also returns sum I and the number
  * of non-finite voxels (NaN / Inf are skipped in both sums). */
 double oracle_rms(const double* in, int64_t n, double* sum_out, int64_t* nonfinite_out)

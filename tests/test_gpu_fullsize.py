@@ -134,15 +134,14 @@ def test_fullsize_sampled_parity(dev, field, oracle_lib, cond, K, tau, n, C):
     assert r["ymax"] <= float(cube.max()) and r["ymin"] >= float(cube.min())
 
 
-def _ulp_at(mag, dtype):
-    """Spacing of the storage type at magnitude mag (normal range)."""
-    import torch
-    bits = 7 if dtype == torch.bfloat16 else 10
-    return 2.0 ** (np.floor(np.log2(mag)) - bits)
-
-
 @pytest.mark.parametrize("name", ["bf16", "f16"])
 def test_16bit_storage_vs_rounding_oracle(dev, oracle_lib, name):
+    """16-bit storage, 20 steps, checked step by step (reading R15): from the
+    GPU's own 16-bit state, the GPU's next state equals the storage rounding
+    of the exact FP64 step wherever no rounding boundary lies within the
+    oracle's binary32 error bound of that step, and lies inside the rounding
+    of that interval elsewhere.  The 20-step run equals the chain of single
+    steps bit for bit, and stays close to the exact unrounded filter."""
     import torch
     import paper_1609_03782_amd as ig
     dt = {"bf16": torch.bfloat16, "f16": torch.float16}[name]
@@ -150,24 +149,24 @@ def test_16bit_storage_vs_rounding_oracle(dev, oracle_lib, name):
     xq = torch.from_numpy(cube).to(dev).to(dt)
     q = xq.double().cpu().numpy()                     # the quantised input both sides start from
     n = 20
-    f = ig.Filter(cube.shape, K=2.0, tau=1 / 16, n_iter=n, dtype=name)
-    y = f.run(xq)
-    torch.cuda.synchronize()
-    g = y.double().cpu().numpy()
-    ref, rho = oracle_lib.run(q, "pm_exp", K=2.0, tau=1 / 16, n_iter=n, round_to=name)
-    frac_equal = float(np.mean(g == ref))
-    d = np.abs(g - ref)
-    unit = _ulp_at(np.abs(ref).max(), dt)
-    print(f"{name}: bitwise-equal fraction {frac_equal:.5f}, max-abs {d.max():.3e} "
-          f"(= {d.max() / unit:.2f} storage units at the cube's largest value)")
-    # FP32 (GPU) and FP64 (oracle) arithmetic take a different rounding only
-    # near ties; a flip moves a voxel by one storage unit of its magnitude and
-    # reaches its neighbours damped by tau*C*w < 1, so almost every voxel is
-    # bitwise equal and no difference exceeds two units at the largest value
-    assert frac_equal >= 0.99
-    assert d.max() <= 2.0 * unit
-    # and the whole run stays close to the exact (unrounded) filter
+    y, st = ig.Filter(cube.shape, K=2.0, tau=1 / 16, n_iter=n, dtype=name).run(xq, stats=True)
+    rho = st.rms_used
+    one = ig.Filter(cube.shape, K=2.0, tau=1 / 16, n_iter=1, rms=rho, dtype=name)
+    s, amb, diff = xq, 0, 0
+    for k in range(n):
+        s1 = one.run(s)
+        torch.cuda.synchronize()
+        ex, bd, _ = oracle_lib.error_bound(s.double().cpu().numpy(), "pm_exp", K=2.0, tau=1 / 16, n_iter=1, rms=rho)
+        ref, tol = oracle_lib.round_storage(ex, name, bd)
+        got = s1.double().cpu().numpy()
+        d = np.abs(got - ref)
+        assert (d <= tol).all(), (k, int((d > tol).sum()))
+        amb, diff = amb + int((tol > 0).sum()), diff + int((d > 0).sum())
+        s = s1
+    assert torch.equal(s, y)
+    print(f"{name}: {diff} voxel-steps differ from the rounded FP64 step, {amb} may (of {n * q.size})")
     exact, _ = oracle_lib.run(q, "pm_exp", K=2.0, tau=1 / 16, n_iter=n)
+    g = y.double().cpu().numpy()
     assert np.sqrt(np.mean((g - exact) ** 2)) <= (0.02 if name == "bf16" else 0.003) * rho
 
 

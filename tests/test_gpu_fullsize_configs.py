@@ -37,25 +37,40 @@ def _points(shape, rng, k=10):
 
 @pytest.mark.parametrize("name", ["bf16", "f16"])
 def test_16bit_storage_fullsize_sampled(dev, oracle_lib, name):
+    """The 512^3 cube, 50 steps, 16-bit storage (the bench's schedule).  The
+    50-step run equals the chain of single steps bit for bit; at each step,
+    sampled voxels (random, faces and corners, and the 200 brightest, where
+    backward diffusion amplifies differences) of the GPU's next state equal
+    the storage rounding of the exact FP64 step from the GPU's own state,
+    except where a rounding boundary lies within the oracle's binary32 error
+    bound of that step (reading R15)."""
     import torch
     import paper_1609_03782_amd as ig
     dt = {"bf16": torch.bfloat16, "f16": torch.float16}[name]
     cube = igsynth.cube_field(512, seed=2)
     xq = torch.from_numpy(cube).to(dev).to(dt)
-    q = xq.double().cpu().numpy()
-    f = ig.Filter(q.shape, K=2.0, tau=1 / 16, n_iter=50, dtype=name)
-    y, st = f.run(xq, stats=True)
-    g = y.double().cpu().numpy()
-    pts = _points(q.shape, np.random.default_rng(7))
-    ref = oracle_lib.run_points(q, pts, "pm_exp", K=2.0, tau=1 / 16, n_iter=50, rms=st.rms_used, round_to=name)
-    got = np.array([g[p] for p in pts])
-    bits = 7 if name == "bf16" else 10
-    unit = 2.0 ** (np.floor(np.log2(np.abs(g).max())) - bits)
-    d = np.abs(got - ref)
-    print(f"{name} 512^3 n=50: {np.mean(d == 0):.2f} of samples bitwise equal, max diff {d.max():.3e} "
-          f"(= {d.max() / unit:.2f} storage units at the cube's largest value)")
-    assert d.max() <= 2.0 * unit
-    assert np.mean(d == 0) >= 0.75
+    n = 50
+    y, st = ig.Filter(cube.shape, K=2.0, tau=1 / 16, n_iter=n, dtype=name).run(xq, stats=True)
+    rho = st.rms_used
+    one = ig.Filter(cube.shape, K=2.0, tau=1 / 16, n_iter=1, rms=rho, dtype=name)
+    bright = np.argsort(cube.ravel())[-200:]
+    pts = _points(cube.shape, np.random.default_rng(7), k=300) + [tuple(int(c) for c in np.unravel_index(b, cube.shape))
+                                                                   for b in bright]
+    s, amb, diff = xq, 0, 0
+    for k in range(n):
+        s1 = one.run(s)
+        prev = s.float().cpu().numpy()
+        got = s1.float().cpu().numpy()
+        ex, bd = oracle_lib.step_points(prev, pts, "pm_exp", K=2.0, tau=1 / 16, rms=rho)
+        ref, tol = oracle_lib.round_storage(ex, name, bd)
+        g = np.array([got[p] for p in pts], dtype=np.float64)
+        d = np.abs(g - ref)
+        assert (d <= tol).all(), (k, int((d > tol).sum()))
+        amb, diff = amb + int((tol > 0).sum()), diff + int((d > 0).sum())
+        s = s1
+    assert torch.equal(s, y)
+    print(f"{name} 512^3 n=50: {len(pts)} samples per step; {diff} sample-steps differ from the rounded FP64 "
+          f"step, {amb} may")
 
 
 def test_batch_fullsize_sampled(dev, oracle_lib):

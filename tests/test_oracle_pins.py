@@ -409,3 +409,37 @@ def test_error_bound_covers_independent_binary32_computation(oracle_lib):
     ratio = np.abs(got - ref) / B
     assert ratio.max() <= 1.0, ratio.max()
     assert np.abs(got - ref).max() > 0            # it is a different computation
+
+
+def test_round_storage_and_spread(oracle_lib):
+    """round_storage equals the scalar rounding functions; its spread is the
+    largest rounding change over the interval, found here by brute force on a
+    dense grid inside it (zero exactly when no rounding boundary lies within
+    d, a whole number of storage steps otherwise)."""
+    rng = np.random.default_rng(31)
+    x = np.concatenate([rng.standard_normal(300) * 3, rng.standard_normal(100) * 1e-6,
+                        (np.arange(1024, 1040) + 0.5) * 2.0 ** -10])
+    d = np.abs(rng.standard_normal(x.size)) * np.abs(x) * 10.0 ** rng.uniform(-6, -1, x.size)
+    for name, fn in (("bf16", oracle_lib.round_bf16), ("f16", oracle_lib.round_f16), ("f32", None)):
+        y, sp = oracle_lib.round_storage(x, name, d)
+        ref = fn(x) if fn else x.astype(np.float32).astype(np.float64)
+        np.testing.assert_array_equal(y, ref)
+        np.testing.assert_array_equal(oracle_lib.round_storage(x, name), ref)
+        for i in range(x.size):
+            w = np.linspace(x[i] - d[i], x[i] + d[i], 401)
+            rw = fn(w) if fn else w.astype(np.float32).astype(np.float64)
+            assert sp[i] == np.abs(rw - y[i]).max(), (name, i)
+        assert (sp >= 0).all()
+        if name == "bf16":     # most intervals here are far narrower than a bf16 step
+            assert (sp == 0).mean() > 0.2
+
+
+def test_step_points_match_the_whole_cube(oracle_lib):
+    """One step at sampled voxels (each from its clipped 3x3x3 neighbourhood)
+    equals the whole-cube step and its bound, at faces, edges and corners too."""
+    c = igsynth.random_cube((9, 10, 11), seed=32, scale=2.0).astype(np.float64)
+    ex, bd, rho = oracle_lib.error_bound(c, "pm_exp", K=2.0, tau=1 / 16, n_iter=1)
+    pts = [(0, 0, 0), (8, 9, 10), (4, 0, 5), (0, 5, 10), (4, 5, 6), (8, 3, 0)]
+    v, b = oracle_lib.step_points(c, pts, "pm_exp", K=2.0, tau=1 / 16, rms=rho)
+    np.testing.assert_array_equal(v, np.array([ex[p] for p in pts]))
+    np.testing.assert_array_equal(b, np.array([bd[p] for p in pts]))
