@@ -774,7 +774,8 @@ def main():
     N = cube.size
     value = N * N_ITER / (ms_step * 1e-3) / 1e9
     eff_gbs = 8.0 * N * N_ITER / (ms_step * 1e-3) / 1e9
-    # dominant kernel: k_stream, T iterations per launch over N voxels.
+    # dominant kernel: k_stream (or k_stream_grouped, whose workgroups take
+    # equal shares of the pieces), T iterations per launch over N voxels.
     # Algorithmic bytes per launch: 8 B per voxel (the cube read once and
     # written once; the T - 1 levels in between stay on chip); algorithmic
     # ALU work: 24 issue slots per voxel-iteration, N * T per launch.
@@ -801,7 +802,9 @@ def main():
     eff_launch = 8.0 * N * T / (avg_ms * 1e-3) / 1e9
     roof["effective_hbm"] = {"achieved": round(eff_launch, 1), "unit": "GB/s",
                              "frac": round(eff_launch / HBM_PEAK_GBS, 4)}
-    roof.update({"kernel": "k_stream", "avg_launch_ms": round(avg_ms, 5), "launches": k_launches,
+    grouped = sched["kind"] == "blocked" and ig.schedule_plan_groups(tuple(x.shape), sched, T) is not None
+    roof.update({"kernel": "k_stream_grouped" if grouped else "k_stream", "avg_launch_ms": round(avg_ms, 5),
+                 "launches": k_launches,
                  "iterations_per_launch": T})
     # the same rates against what a plain device copy of the cube reaches here
     cp = copy_gbps(x)

@@ -211,6 +211,19 @@ ig_status ig_filter_get_timing(ig_filter* f, double* total_ms, int64_t* launches
 ig_status ig_schedule_plan(const ig_params* p, const ig_schedule* s, int32_t t_block, int32_t ncu,
                            int32_t* geom, int32_t* pieces, int64_t cap, int64_t* count);
 
+/* Host-only: the schedule a filter created with p and no schedule runs
+ * (kind BLOCKED or NAIVE, all fields resolved). */
+ig_status ig_schedule_auto(const ig_params* p, ig_schedule* out);
+
+/* Host-only: the workgroups of the same pass.  When the balanced split would
+ * leave workgroups unequal (the tile count does not divide the workgroups),
+ * each workgroup instead runs a contiguous share of the pieces in turn:
+ * *nwg receives the number of workgroups and, if first != NULL, up to cap
+ * entries of first[0..nwg] (workgroup b runs pieces [first[b], first[b+1])
+ * of ig_schedule_plan's list).  *nwg = 0: one piece per workgroup. */
+ig_status ig_schedule_plan_groups(const ig_params* p, const ig_schedule* s, int32_t t_block, int32_t ncu,
+                                  int32_t* first, int64_t cap, int64_t* nwg);
+
 /* Replace the filter parameters of f (conductance, K, tau, n_iter, C, rms) in
  * place.  The shape and storage type must stay those f was created with
  * (else IG_ERR_INVALID_ARG); the scratch cube, the schedule and its piece

@@ -106,6 +106,10 @@ SIGNATURES = {
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "ig_schedule_check": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSchedule)]),
+    "ig_schedule_auto": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSchedule)]),
+    "ig_schedule_plan_groups": (ctypes.c_int, [ctypes.POINTER(IgParams), ctypes.POINTER(IgSchedule), ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
+                                               ctypes.POINTER(ctypes.c_int64)]),
     "ig_filter_batch": (ctypes.c_int, [ctypes.POINTER(IgBatchItem), ctypes.c_int32, ctypes.c_int, _P,
                                        ctypes.POINTER(IgStats), ctypes.POINTER(ctypes.c_double)]),
     "ig_batch_cache_clear": (None, []),
@@ -219,6 +223,33 @@ def schedule_plan(shape, sched: dict, t_block: int, ncu: int = 256, **params):
                                   ctypes.byref(cnt)), "ig_schedule_plan")
     keys = ["ntx", "nty", "ox", "oy", "waves", "vec_io", "V", "pieces", "rows"]
     return dict(zip(keys, list(geom))), arr
+
+
+def schedule_auto(shape, **params) -> dict:
+    """Host-only: the schedule a Filter of this shape and parameters runs by default."""
+    p = make_params(shape, **params)
+    s = IgSchedule()
+    _check(lib().ig_schedule_auto(ctypes.byref(p), ctypes.byref(s)), "ig_schedule_auto")
+    return _sched_dict(s)
+
+
+def schedule_plan_groups(shape, sched: dict, t_block: int, ncu: int = 256, **params):
+    """Host-only: each workgroup's first piece (array of nwg + 1 entries) when
+    the pass runs several pieces per workgroup, else None."""
+    import numpy as np
+    p = make_params(shape, **params)
+    s = IgSchedule(SCHED[sched.get("kind", "blocked")], sched.get("t_block", 2), sched.get("waves", 16),
+                   sched.get("zchunk", 0), sched.get("vec", 0), sched.get("rounds", 0), sched.get("rows", 0))
+    n = ctypes.c_int64()
+    _check(lib().ig_schedule_plan_groups(ctypes.byref(p), ctypes.byref(s), t_block, ncu, None, 0, ctypes.byref(n)),
+           "ig_schedule_plan_groups")
+    if n.value == 0:
+        return None
+    first = np.zeros(n.value + 1, np.int32)
+    _check(lib().ig_schedule_plan_groups(ctypes.byref(p), ctypes.byref(s), t_block, ncu,
+                                         first.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n.value + 1,
+                                         ctypes.byref(n)), "ig_schedule_plan_groups")
+    return first
 
 
 def _torch_dtype_name(t):

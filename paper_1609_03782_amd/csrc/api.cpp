@@ -291,6 +291,29 @@ extern "C" ig_status ig_schedule_plan(const ig_params* p, const ig_schedule* s, 
     return IG_OK;
 }
 
+extern "C" ig_status ig_schedule_auto(const ig_params* p, ig_schedule* out) {
+    ig_status st = igk_validate_params(p);
+    if (st != IG_OK) return st;
+    if (!out) return fail(IG_ERR_INVALID_ARG, "out is NULL");
+    *out = igk_auto_schedule(p);
+    return IG_OK;
+}
+
+extern "C" ig_status ig_schedule_plan_groups(const ig_params* p, const ig_schedule* s, int32_t t_block, int32_t ncu,
+                                             int32_t* first, int64_t cap, int64_t* nwg) {
+    ig_status st = igk_validate_params(p);
+    if (st != IG_OK) return st;
+    if (!s || !nwg || ncu < 1) return fail(IG_ERR_INVALID_ARG, "bad argument");
+    if (s->kind != IG_SCHED_BLOCKED) return fail(IG_ERR_INVALID_ARG, "only BLOCKED schedules have a work split");
+    PassPlan pp;
+    const char* why = plan_pass(*p, *s, t_block, ncu, &pp);
+    if (why) return fail(IG_ERR_INVALID_ARG, "%s", why);
+    *nwg = pp.first.empty() ? 0 : (int64_t)pp.first.size() - 1;
+    if (first)
+        for (int64_t k = 0; k < std::min<int64_t>(cap, (int64_t)pp.first.size()); ++k) first[k] = pp.first[k];
+    return IG_OK;
+}
+
 static void drop_plans(ig_filter* f) {
     for (int T = 0; T < 5; ++T) {
         igk_free(f->dpieces[T]);
@@ -325,11 +348,16 @@ static ig_status get_plan(ig_filter* f, const ig_schedule& sched, int T, const P
     if (!f->planned[T]) {
         const char* why = plan_pass(f->p, sched, T, f->ncu, &f->plans[T]);
         if (why) return fail(IG_ERR_INVALID_ARG, "schedule cannot serve this shape: %s", why);
-        const size_t bytes = f->plans[T].pieces.size() * sizeof(Piece);
+        // the piece table, then (grouped plans) each workgroup's first piece
+        const PassPlan& pl = f->plans[T];
+        const size_t bytes = pl.pieces.size() * sizeof(Piece), extra = pl.first.size() * sizeof(int);
         igk_free(f->dpieces[T]);
         f->dpieces[T] = nullptr;
-        HIP_TRY(igk_malloc((void**)&f->dpieces[T], bytes));
-        HIP_TRY(hipMemcpy(f->dpieces[T], f->plans[T].pieces.data(), bytes, hipMemcpyHostToDevice));
+        HIP_TRY(igk_malloc((void**)&f->dpieces[T], bytes + extra));
+        HIP_TRY(hipMemcpy(f->dpieces[T], pl.pieces.data(), bytes, hipMemcpyHostToDevice));
+        if (extra)
+            HIP_TRY(hipMemcpy(reinterpret_cast<char*>(f->dpieces[T]) + bytes, pl.first.data(), extra,
+                              hipMemcpyHostToDevice));
         f->planned[T] = true;
     }
     *out = &f->plans[T];
@@ -413,7 +441,7 @@ ig_status igk_enqueue_run(const RunCtx& c, const ig_schedule& sched, const void*
                 const size_t al = (size_t)pp->V * dtype_size(p.dtype);
                 if (((uintptr_t)src % al) || ((uintptr_t)dst % al)) g.vec = 0;
                 HIP_TRY(record());
-                e = L->blocked(src, dst, g, pp->V, D, dev, (int)pp->pieces.size(), c.dparams, stream);
+                e = L->blocked(src, dst, g, pp->V, D, dev, pp->workgroups(), c.dparams, stream);
             }
             if (e != hipSuccess) return fail(IG_ERR_DEVICE, "stencil launch: %s", hipGetErrorString(e));
             HIP_TRY(record());

@@ -687,6 +687,7 @@ ig_status build_plan(const ig_batch_item* items, int count, int device, BatchPla
         PassPlan pp;
         const char* why = plan_pass(p, s, T, ncu, &pp);
         if (why) return fail(IG_ERR_INVALID_ARG, "batch item %d: %s", c, why);
+        if (pp.g.grouped) return fail(IG_ERR_DEVICE, "batch item %d: unexpected grouped plan", c);
         if (pp.V != 4 && pp.V != 2 && pp.V != 1)
             return fail(IG_ERR_UNSUPPORTED, "batch item %d: layout with %d voxels per lane", c, pp.V);
         lds = std::max(lds, stream_lds_bytes(pp.V, T, W));

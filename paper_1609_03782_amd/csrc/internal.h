@@ -39,8 +39,10 @@ hipError_t launch_nan_if_abort(int dtype, void* x, long n, const DevParams* dp, 
 // V in {1,2,4,8}, T in {1..4}.
 struct StencilLaunch {
     hipError_t (*naive)(const void* src, void* dst, int nx, int ny, int nz, const DevParams* dp, hipStream_t s);
+    // one workgroup per piece, or (g.grouped) nwg workgroups each running its
+    // range of the table
     hipError_t (*blocked)(const void* src, void* dst, const BlockGeom& g, int V, int T, const Piece* pieces,
-                          int npieces, const DevParams* dp, hipStream_t s);
+                          int nwg, const DevParams* dp, hipStream_t s);
 };
 const StencilLaunch* stencil_table(int cond, int dtype);
 

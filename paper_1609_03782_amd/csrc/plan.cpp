@@ -84,6 +84,43 @@ int resident_per_cu(int W, size_t lds) {
     return std::max(1, std::min(by_waves, by_lds));
 }
 
+// Equal shares of work per workgroup: the sequence tile 0 planes 0..nz-1,
+// tile 1 planes 0..nz-1, ... (tiles in y-then-x order, every tile-plane one
+// unit of work) is cut into G contiguous ranges of equal cost, and range b
+// becomes the pieces of workgroup b (one, or two where it crosses a tile
+// boundary).  Every piece refills the pipeline (its 2T halo planes and T
+// extra steps), so each tile boundary inside the sequence counts 3T units:
+// a range that takes a second piece takes fewer planes.  (Cutting each XCD's
+// z-band separately, to keep neighbouring tiles on one L2, gave every
+// workgroup two or three short pieces and measured slower.)
+static void group_split(const BlockGeom& g, long ntiles, long G, int T, PassPlan* pp) {
+    const int64_t nz = g.nz, F = 3 * T;
+    const int64_t unit = nz + F;                 // a tile's cost with the refill that starts it
+    const int64_t tot = ntiles * unit - F;       // the first tile's fill is paid by every range alike
+    // position of cost x: (tile, plane); inside a refill it is plane 0 of that tile
+    auto pos = [&](int64_t x, long* ti, int64_t* pl) {
+        if (x >= tot) { *ti = ntiles; *pl = 0; return; }
+        const int64_t y = x + F;                 // tile t spans [t unit, (t + 1) unit), its planes after F
+        *ti = (long)(y / unit);
+        *pl = std::max<int64_t>(0, y % unit - F);
+    };
+    pp->pieces.clear();
+    pp->first.assign(1, 0);
+    for (long b = 0; b < G; ++b) {
+        long ta, tb;
+        int64_t pa, pb;
+        pos(tot * b / G, &ta, &pa);
+        pos(b + 1 == G ? tot : tot * (b + 1) / G, &tb, &pb);
+        for (long t = ta; t <= tb && t < ntiles; ++t) {
+            const int64_t p0 = t == ta ? pa : 0, p1 = t == tb ? pb : nz;
+            if (p1 > p0) pp->pieces.push_back(Piece{(int)(t % g.ntx), (int)(t / g.ntx), (int)p0, (int)p1});
+        }
+        pp->first.push_back((int)pp->pieces.size());
+    }
+    pp->g.npieces = (int)pp->pieces.size();
+    pp->g.grouped = 1;
+}
+
 // Plan the pass of depth T for schedule s; returns nullptr or the reason it
 // cannot serve the shape.
 const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, PassPlan* pp) {
@@ -144,6 +181,8 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
     pp->T = T;
     auto& pcs = pp->pieces;
     pcs.clear();
+    pp->first.clear();
+    g.grouped = 0;
     const long ntiles = (long)g.ntx * g.nty;
     if (s.zchunk > 0) {
         const int nzc = (nz + s.zchunk - 1) / s.zchunk;
@@ -152,30 +191,22 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
             for (int ty = 0; ty < g.nty; ++ty)
                 for (int tx = 0; tx < g.ntx; ++tx)
                     pcs.push_back(Piece{tx, ty, tz * s.zchunk, std::min(nz, (tz + 1) * s.zchunk)});
+        g.npieces = (int)pcs.size();
         return nullptr;
     }
     // balanced split: G pieces of (nearly) equal work, G a whole number of
-    // rounds of the resident workgroups.  A tile's work per plane is set by
-    // the rows and columns it computes (its outputs and halo inside the
-    // cube), not by its outputs alone: a plane step costs the same whether
-    // a tile outputs 11 rows or 12.
+    // rounds of the resident workgroups.  Every tile costs the same per plane
+    // step: its wavefronts step through the planes together, a step takes as
+    // long as its busiest SIMD, and tiles differ only by the few halo rows or
+    // columns that fall outside the cube at its faces (a tile there computes
+    // no fewer levels per step on its other rows).  So a piece's work is its
+    // plane count, whatever its tile's outputs.
     const long slots = (long)ncu * resident_per_cu(W, lds);
     long rounds = s.rounds > 0 ? s.rounds : std::max<long>(1, (ntiles + slots - 1) / slots);
     long G = std::min<long>(slots * rounds, ntiles * (long)nz);
     if (G > (1L << 24)) return "too many pieces";
-    std::vector<double> area(ntiles);
-    double total = 0.0;
-    for (int ty = 0; ty < g.nty; ++ty)
-        for (int tx = 0; tx < g.ntx; ++tx) {
-            int x0, x1, y0, y1;
-            tile_cols(g, V, tx, &x0, &x1);
-            tile_rows(g, ty, &y0, &y1);
-            const int rx0 = g.ntx > 1 ? x0 - g.hx : 0, ry0 = g.nty > 1 ? y0 - T : 0;
-            const int ex = std::min(rx0 + RX, nx) - std::max(rx0, 0);
-            const int ey = std::min(ry0 + W * R, ny) - std::max(ry0, 0);
-            area[(long)ty * g.ntx + tx] = (double)ex * ey;
-            total += (double)ex * ey;
-        }
+    std::vector<double> area(ntiles, 1.0);
+    const double total = (double)ntiles;
     std::vector<int> cnt(ntiles);
     long used = 0;
     for (long i = 0; i < ntiles; ++i) {
@@ -190,6 +221,27 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
         if (best < 0) break;
         ++cnt[best];
         ++used;
+    }
+    // When the tile count does not divide the workgroups (512 rows in 43
+    // tiles of 16-row workgroups over 256 compute units: some tiles get 5
+    // pieces of 102 planes, the others 6 of 85), the longest piece sets the
+    // pass time.  Then each workgroup takes an equal share of the (tile,
+    // plane) sequence instead, one or two pieces in turn, if that is cheaper
+    // counting the halo planes every piece reloads.
+    {
+        double old_cost = 0.0, amax = 0.0;
+        for (long i = 0; i < ntiles; ++i) {
+            old_cost = std::max(old_cost, area[i] * ((nz + cnt[i] - 1) / cnt[i] + 3 * T));
+            amax = std::max(amax, area[i]);
+        }
+        const double new_cost = (total * (nz + 3.0 * T) - 3.0 * T) / (double)G + 3.0 * T * amax;
+        // grouped kernels exist for depths 1 and 2; cubes wider than one
+        // tile keep the one-piece split, whose order keeps x neighbours'
+        // halos on one L2 (grouping them measured slower)
+        if (T <= 2 && g.ntx == 1 && used == G && new_cost < 0.97 * old_cost) {
+            group_split(g, ntiles, G, T, pp);
+            return nullptr;
+        }
     }
     struct Item { Piece pc; double key; };
     std::vector<Item> items;
@@ -219,6 +271,7 @@ const char* plan_pass(const ig_params& p, const ig_schedule& s, int T, int ncu, 
     } else {
         for (long k = 0; k < n; ++k) pcs[k] = items[k].pc;
     }
+    g.npieces = (int)pcs.size();
     return nullptr;
 }
 
@@ -235,6 +288,32 @@ ig_schedule igk_auto_schedule(const ig_params* p) {
     if (stream_lds_bytes(s.vec, s.t_block, s.waves) > kMaxLds) s.waves = 8;
     s.zchunk = 0;
     s.rounds = 1;
+    // 16 wavefronts (four per SIMD, 12 output rows per tile) when their
+    // workgroups take equal shares of the planes (grouped plan) and the
+    // longest share, in plane steps times the measured cost of a 16-wave step
+    // (2.96 us against 2.13 us for a 12-wave step on the 512^3 cube, T = 2,
+    // 8 voxels per lane), is shorter: 512^3 runs 93 such steps against 134.
+    if (s.t_block == 2 && s.vec == 8 && s.rows == 1 && p->nx % 8 == 0 && p->nx <= 512 &&
+        (long)16 * p->nx * (long)dtype_size(p->dtype) < (1L << 30)) {
+        auto longest = [&](int W, bool* grouped) -> double {
+            ig_schedule t = s;
+            t.waves = W;
+            PassPlan pp;
+            if (plan_pass(*p, t, 2, 256, &pp)) return 1e300;
+            *grouped = !pp.first.empty();
+            double m = 0.0;
+            for (int b = 0; b < pp.workgroups(); ++b) {
+                const int k0 = pp.first.empty() ? b : pp.first[b], k1 = pp.first.empty() ? b + 1 : pp.first[b + 1];
+                double steps = 0.0;
+                for (int k = k0; k < k1; ++k) steps += pp.pieces[k].z1 - pp.pieces[k].z0 + 6;
+                m = std::max(m, steps);
+            }
+            return m;
+        };
+        bool g12 = false, g16 = false;
+        const double t12 = longest(12, &g12), t16 = longest(16, &g16);
+        if (g16 && 2.96 * t16 < 2.13 * t12) s.waves = 16;
+    }
     if ((long)s.waves * s.rows * p->nx * (long)dtype_size(p->dtype) >= (1L << 30)) {   // absurdly long rows
         ig_schedule n{};
         n.kind = IG_SCHED_NAIVE;

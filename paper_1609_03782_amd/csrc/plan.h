@@ -21,6 +21,8 @@ struct BlockGeom {
     int vec;              // 1: lane chunks are whole and aligned (vector I/O)
     int R;                // rows per wavefront (1, 2 or 4); a tile has W * R rows
     int hx;               // x halo of a tile when ntx > 1 (t_block rounded up to whole lane chunks)
+    int npieces;          // pieces in the table
+    int grouped;          // 1: workgroup b runs pieces [first[b], first[b+1]) (the ints after the table); 0: piece b
 };
 
 struct Piece {
@@ -47,11 +49,15 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 }  // namespace igk
 
-// One pass of the streaming kernel, fully planned: geometry and piece table.
+// One pass of the streaming kernel, fully planned: geometry and piece table;
+// with `first` non-empty, workgroup b runs pieces [first[b], first[b+1]) in
+// turn (the device table holds the pieces, then `first` as ints).
 struct PassPlan {
     igk::BlockGeom g{};
     std::vector<igk::Piece> pieces;
+    std::vector<int> first;
     int V = 0, T = 0;
+    int workgroups() const { return first.empty() ? (int)pieces.size() : (int)first.size() - 1; }
 };
 void auto_vec_rows(int64_t nx, int* V, int* R);
 int resident_per_cu(int W, size_t lds);

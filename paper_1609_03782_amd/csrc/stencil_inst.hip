@@ -38,6 +38,10 @@ template <int V, int T, bool VEC, int R>
 static hipError_t stream_one(const void* src, void* dst, const BlockGeom& g, const Piece* pieces, int npieces,
                              const DevParams* dp, hipStream_t s) {
     auto kern = k_stream<IG_COND, ST, V, T, VEC, R>;
+    if (g.grouped) {   // grouped plans exist for passes of depth 1 and 2 only
+        if constexpr (T <= 2) kern = k_stream_grouped<IG_COND, ST, V, T, VEC, R>;
+        else return hipErrorInvalidValue;
+    }
     const size_t lds = stream_lds_bytes(V, T, g.W);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

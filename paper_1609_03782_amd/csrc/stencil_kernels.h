@@ -721,4 +721,24 @@ k_stream(const ST* __restrict__ src, ST* __restrict__ dst, BlockGeom g, const Pi
     stream_piece<COND, ST, V, T, VEC, R>(src, dst, g, pieces[blockIdx.x], P, lds);
 }
 
+// Grouped plans: workgroup b runs pieces [first[b], first[b + 1]) in turn
+// (first: the ints after the piece table; the bounds come from
+// workgroup-uniform addresses, so the loop is uniform).  A kernel of its own:
+// the loop around the streaming body raises register pressure (the per-lane
+// geometry stays live across pieces), which the one-piece kernel should not pay.
+template <int COND, typename ST, int V, int T, bool VEC, int R>
+__global__ void __launch_bounds__(1024)
+k_stream_grouped(const ST* __restrict__ src, ST* __restrict__ dst, BlockGeom g, const Piece* __restrict__ pieces,
+                 const DevParams* __restrict__ dp) {
+    extern __shared__ float lds[];
+    const DevParams P = *dp;
+    if (P.abort) return;
+    const int* first = reinterpret_cast<const int*>(pieces + g.npieces);
+    const int k0 = first[blockIdx.x], k1 = first[blockIdx.x + 1];
+    for (int k = k0; k < k1; ++k) {
+        if (k > k0) __syncthreads();   // the previous piece is done with the LDS
+        stream_piece<COND, ST, V, T, VEC, R>(src, dst, g, pieces[k], P, lds);
+    }
+}
+
 }  // namespace igk

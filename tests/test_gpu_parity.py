@@ -277,3 +277,33 @@ def test_wide_cubes_bitwise(dev, oracle_lib, cond, shape):
             assert np.array_equal(y, outs[0]), (dtype, k)
         if dtype == "f32":
             assert _err(outs[0], ref) <= TOL * rho
+
+
+GROUPED_CASES = [((64, 512, 512), dict(kind="blocked", t_block=2, waves=16, vec=8)),
+                 ((20, 130, 520), dict(kind="blocked", t_block=1, waves=16)),
+                 ((24, 100, 300), dict(kind="blocked", t_block=2, waves=16, rounds=2))]
+
+
+@pytest.mark.parametrize("cond", CONDS)
+@pytest.mark.parametrize("shape,sched", GROUPED_CASES)
+def test_grouped_workgroups_bitwise(dev, oracle_lib, cond, shape, sched):
+    """Plans in which a workgroup runs a share of the pieces in turn (one or
+    two pieces; the tile count does not divide the workgroups) give bitwise
+    the naive schedule's result, and the oracle's within the parity bar."""
+    import torch
+    import paper_1609_03782_amd as ig
+    grouped = ig.schedule_plan_groups(shape, sched, sched["t_block"])
+    cube = igsynth.random_cube(shape, seed=sum(shape) + 11, scale=2.0)
+    cube[shape[0] // 2, shape[1] // 2, shape[2] // 3] = 11.0
+    x = torch.from_numpy(cube).to(dev)
+    n = 5
+    f0 = ig.Filter(shape, K=2.0, tau=1 / 16, n_iter=n, cond=cond)
+    f0.set_schedule("naive")
+    y0 = f0.run(x)
+    f = ig.Filter(shape, K=2.0, tau=1 / 16, n_iter=n, cond=cond)
+    f.set_schedule(**sched)
+    y = f.run(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y0), (shape, sched, grouped is not None)
+    ref, rho = oracle_lib.run(cube, cond, K=2.0, tau=1 / 16, n_iter=n)
+    assert _err(y.cpu().numpy(), ref) <= TOL * rho

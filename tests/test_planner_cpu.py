@@ -138,18 +138,64 @@ def test_even_tile_split():
             assert max(rows) <= g["oy"] and max(rows) - min(rows) <= 1, (ny, waves, T, g)
 
 
+def _wg_costs(shape, sched):
+    """Steps each workgroup of the pass runs: per piece its planes plus the
+    3 t_block of the pipeline refill."""
+    T = sched["t_block"]
+    sd = dict(kind="blocked", **sched)
+    g, pcs = ig.schedule_plan(shape, sd, T, ncu=256)
+    first = ig.schedule_plan_groups(shape, sd, T, ncu=256)
+    if first is None:
+        first = np.arange(len(pcs) + 1)
+    cost = np.array([sum(int(z1 - z0) + 3 * T for _, _, z0, z1 in pcs[first[b]:first[b + 1]])
+                     for b in range(len(first) - 1)])
+    return g, pcs, first, cost
+
+
 def test_ragged_shapes_balance_in_one_round():
-    """A cube whose rows do not divide into whole tiles still gets one round
-    of pieces, and no piece is longer in z than the tile count forces: with
-    k = floor(256 / tiles) pieces per tile at least, the longest piece has at
-    most ceil(nz / k) planes (a thin last tile used to get a single piece of
-    all nz planes that outlasted every other piece)."""
+    """Whole rounds of workgroups, and no workgroup much longer than the average:
+    a thin last tile used to get a single piece of all nz planes that
+    outlasted every other piece, and tile counts that do not divide the
+    workgroups (43 tiles of 16-wave workgroups over 256) left some tiles with
+    fewer, longer pieces; workgroups now take equal shares of the
+    (tile, plane) sequence in that case."""
     for shape, sched in [((512, 512, 512), dict(t_block=2, waves=14)), ((500, 500, 500), dict(t_block=2, waves=12)),
                          ((512, 512, 512), dict(t_block=1, waves=12)), ((512, 512, 512), dict(t_block=2, waves=10)),
-                         ((512, 500, 512), dict(t_block=2, waves=16))]:
-        g, pcs = ig.schedule_plan(shape, dict(kind="blocked", **sched), sched["t_block"], ncu=256)
+                         ((512, 500, 512), dict(t_block=2, waves=16)), ((512, 512, 512), dict(t_block=2, waves=16))]:
+        g, pcs, first, cost = _wg_costs(shape, sched)
         tiles = g["ntx"] * g["nty"]
-        assert len(pcs) <= 256 and tiles <= 256
-        k = 256 // tiles
-        planes = np.array([z1 - z0 for tx, ty, z0, z1 in pcs])
-        assert planes.max() <= -(-shape[0] // k), (shape, sched, planes.max(), k)
+        assert len(first) - 1 <= 256 * max(1, -(-tiles // 256)), (shape, sched)   # whole rounds
+        T = sched["t_block"]
+        assert cost.max() <= 1.08 * cost.mean() + 3 * T, (shape, sched, cost.max(), cost.mean())
+
+
+def test_grouped_plan_partitions_the_sequence():
+    """A grouped plan: the workgroups' ranges partition the piece list, each
+    workgroup's pieces are consecutive in (tile, plane) order (at most one
+    tile boundary inside a share at these sizes), and the shares cost the
+    same to within one refill."""
+    for shape, sched in [((512, 512, 512), dict(t_block=2, waves=16)), ((512, 512, 512), dict(t_block=1, waves=16)),
+                         ((64, 512, 512), dict(t_block=2, waves=16))]:
+        g, pcs, first, cost = _wg_costs(shape, sched)
+        assert ig.schedule_plan_groups(shape, dict(kind="blocked", **sched), sched["t_block"]) is not None
+        assert first[0] == 0 and first[-1] == len(pcs) and (np.diff(first) >= 1).all()
+        nz = shape[0]
+        spans = [((ty * g["ntx"] + tx) * nz + z0, (ty * g["ntx"] + tx) * nz + z1) for tx, ty, z0, z1 in pcs]
+        assert all(a < b for a, b in spans)
+        assert all(p[1] <= q[0] for p, q in zip(spans, spans[1:]))    # sequence order, no overlap
+        assert (np.diff(first) <= 2).all()
+        T = sched["t_block"]
+        assert cost.max() - cost.min() <= 3 * T + 1, (shape, sched, cost.min(), cost.max())
+
+
+
+
+def test_grouping_only_where_it_pays():
+    """Grouped plans only for passes of depth 1 and 2 on cubes one tile wide,
+    and only when the one-piece split is unbalanced: the 512^3 cube keeps one
+    piece per workgroup with 12 wavefronts (64 tiles x 4) and wide cubes keep
+    their one-piece split."""
+    assert ig.schedule_plan_groups((512, 512, 512), dict(kind="blocked", t_block=2, waves=12), 2) is None
+    assert ig.schedule_plan_groups((128, 1024, 1024), dict(kind="blocked", t_block=2, waves=12), 2) is None
+    assert ig.schedule_plan_groups((512, 512, 512), dict(kind="blocked", t_block=3, waves=10), 3) is None
+    assert ig.schedule_plan_groups((512, 512, 512), dict(kind="blocked", t_block=2, waves=16), 2) is not None
