@@ -142,11 +142,12 @@ def code_only(src):
 
 def counter_traffic():
     """HBM bytes per k_stream launch from the committed FETCH_SIZE/WRITE_SIZE
-    summary, if it was taken from the kernel sources as they are now."""
+    summary, if it was taken from the kernel and planner sources as they are
+    now (the planner's tiles and piece order decide the halo re-reads)."""
     import hashlib
     import re
     prof = os.path.join(ROOT, "profiles", "k_stream_pm_exp_512cube.md")
-    srcs = ["stencil_kernels.h", "stencil_common.h", "stencil_inst.hip"]
+    srcs = ["stencil_kernels.h", "stencil_common.h", "stencil_inst.hip", "plan.h", "plan.cpp"]
     try:
         m = re.search(r"traffic_bytes_per_launch=(\d+) code_sha256=([0-9a-f]+)", open(prof).read())
         h = hashlib.sha256()
