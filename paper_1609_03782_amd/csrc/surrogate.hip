@@ -48,18 +48,22 @@ struct Dev {
     template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-dim3 conv_grid(long nx, long ny, long nz) { return dim3((nx + TX - 1) / TX, (ny + TY - 1) / TY, nz); }
 long wgrad_units(long nx, long ny, long nz) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * nz; }
 long wgrad_groups(long nx, long ny, long nz) { return std::min(kWgradGroups, wgrad_units(nx, ny, nz)); }
 
-// z-streaming launch for a 32-channel input: the z chunk that minimises the slowest compute unit's share (in planes, counting the
-// two margin planes and the B copy as about two more) with one workgroup per CU.
-template <int NB, int EPI, int MT>
-hipError_t zs_launch(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
-                     long nz, hipStream_t s) {
-    constexpr int XW = 16 * MT;
-    const int ntx = (int)((nx + XW - 1) / XW), nty = (int)((ny + kZsRows - 1) / kZsRows);
-    const long tiles = (long)ntx * nty;
+// Grid of the z-streaming kernels (tiles of xw voxels by kZsRows rows, one
+// workgroup per (tile, z chunk)): the z chunk that minimises the slowest
+// compute unit's share (in planes, counting the two margin planes and the
+// set-up as about two more) with one workgroup per CU.
+struct ZsGrid {
+    int ntx, nty, zch;
+    long groups;
+};
+ZsGrid zs_grid(long nx, long ny, long nz, int xw) {
+    ZsGrid g;
+    g.ntx = (int)((nx + xw - 1) / xw);
+    g.nty = (int)((ny + kZsRows - 1) / kZsRows);
+    const long tiles = (long)g.ntx * g.nty;
     int ncu = 256;
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -71,56 +75,76 @@ hipError_t zs_launch(const u16* x, const bf16x8* wp, const float* b, void* out, 
         if (best_cost < 0 || cost < best_cost) { best_cost = cost; zch = zc; }
         if (zc == 1) break;
     }
-    const long groups = tiles * ((nz + zch - 1) / zch);
+    g.zch = (int)zch;
+    g.groups = tiles * ((nz + zch - 1) / zch);
+    return g;
+}
+
+// 32-channel input: 8 rows of 32 voxels (2 M-tiles) per workgroup, the largest
+// tile whose three padded planes and the weights fit the 160 KB of LDS
+template <int NB, int EPI>
+hipError_t zs_launch(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
+                     long nz, hipStream_t s) {
+    constexpr int MT = 2;
+    static_assert(zs_lds_bytes<MT, 2>() <= 160 * 1024, "z-stream tile exceeds LDS");
+    const ZsGrid g = zs_grid(nx, ny, nz, 16 * MT);
     const size_t lds = zs_lds_bytes<MT, NB>();
     auto kern = k_conv_zs<NB, EPI, MT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64 * kZsRows), lds, s, x, wp, b, out, aux, (int)nx, (int)ny,
-                       (int)nz, ntx, nty, (int)zch);
+    hipLaunchKernelGGL(kern, dim3((unsigned)g.groups), dim3(64 * kZsRows), lds, s, x, wp, b, out, aux, (int)nx,
+                       (int)ny, (int)nz, g.ntx, g.nty, g.zch);
     return hipGetLastError();
 }
 
+// 1-channel input (first layer; input gradient of a 1-channel output)
 template <int NB, int EPI>
-hipError_t zs_launch_mt(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
-                        long nz, hipStream_t s) {
-    // 8 rows of 32 voxels (2 M-tiles) per workgroup: the largest tile whose
-    // three padded planes and the weights fit the 160 KB of LDS
-    static_assert(zs_lds_bytes<2, 2>() <= 160 * 1024, "z-stream tile exceeds LDS");
-    return zs_launch<NB, EPI, 2>(x, wp, b, out, aux, nx, ny, nz, s);
+hipError_t zs1_launch(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
+                      long nz, hipStream_t s) {
+    constexpr int MT = 2;
+    const ZsGrid g = zs_grid(nx, ny, nz, 16 * MT);
+    hipLaunchKernelGGL((k_conv1_zs<NB, EPI, MT>), dim3((unsigned)g.groups), dim3(64 * kZsRows), 0, s, x, wp, b, out,
+                       aux, (int)nx, (int)ny, (int)nz, g.ntx, g.nty, g.zch);
+    return hipGetLastError();
 }
 
-// forward conv launch (packed weights)
+// 32-channel input, one output channel (last layer): per-tap partial sums
+template <int EPI>
+hipError_t out1_launch(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
+                       long nz, hipStream_t s) {
+    static_assert(kO1Lds <= 160 * 1024, "tap partials exceed LDS");
+    const ZsGrid g = zs_grid(nx, ny, nz, kO1X);
+    auto kern = k_conv_out1<EPI>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kO1Lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)g.groups), dim3(64 * kZsRows), kO1Lds, s, x, wp, b,
+                       static_cast<float*>(out), static_cast<const float*>(aux), (int)nx, (int)ny, (int)nz, g.ntx,
+                       g.nty, g.zch);
+    return hipGetLastError();
+}
+
+// forward conv launch (packed weights); cin is 1 or 32
 hipError_t launch_conv(int cin, int cout, int epi, const void* in, const bf16x8* wp, const float* b, void* out,
                        const void* aux, long nx, long ny, long nz, hipStream_t s) {
-    const dim3 g = conv_grid(nx, ny, nz), blk(256);
     const int NB = cout > 16 ? 2 : 1;
     const u16* x = static_cast<const u16*>(in);
-    if (cin == 32) {
-#define Z(NBV, EPIV) return zs_launch_mt<NBV, EPIV>(x, wp, b, out, aux, nx, ny, nz, s)
-        if (NB == 2) {
-            if (epi == EPI_RAW) Z(2, EPI_RAW); else if (epi == EPI_GELU) Z(2, EPI_GELU); else if (epi == EPI_BACK_GELU) Z(2, EPI_BACK_GELU); else Z(2, EPI_RESID);
-        } else {
-            if (epi == EPI_RAW) Z(1, EPI_RAW); else if (epi == EPI_GELU) Z(1, EPI_GELU); else if (epi == EPI_BACK_GELU) Z(1, EPI_BACK_GELU); else Z(1, EPI_RESID);
-        }
+    if (cin == 32 && cout == 1 && (epi == EPI_RAW || epi == EPI_RESID)) {
+        if (epi == EPI_RAW) return out1_launch<EPI_RAW>(x, wp, b, out, aux, nx, ny, nz, s);
+        return out1_launch<EPI_RESID>(x, wp, b, out, aux, nx, ny, nz, s);
+    }
+#define Z(F, NBV, EPIV) return F<NBV, EPIV>(x, wp, b, out, aux, nx, ny, nz, s)
+#define PICK(F)                                                                                             \
+    if (NB == 2) {                                                                                          \
+        if (epi == EPI_RAW) Z(F, 2, EPI_RAW); else if (epi == EPI_GELU) Z(F, 2, EPI_GELU);                  \
+        else if (epi == EPI_BACK_GELU) Z(F, 2, EPI_BACK_GELU); else Z(F, 2, EPI_RESID);                     \
+    } else {                                                                                                \
+        if (epi == EPI_RAW) Z(F, 1, EPI_RAW); else if (epi == EPI_GELU) Z(F, 1, EPI_GELU);                  \
+        else if (epi == EPI_BACK_GELU) Z(F, 1, EPI_BACK_GELU); else Z(F, 1, EPI_RESID);                     \
+    }
+    if (cin == 32) { PICK(zs_launch) }
+    PICK(zs1_launch)
+#undef PICK
 #undef Z
-    }
-#define L(CIN, NBV, EPIV) hipLaunchKernelGGL((k_conv<CIN, NBV, EPIV>), g, blk, 0, s, x, wp, b, out, aux, (int)nx, (int)ny, (int)nz)
-    if (cin == 1) {
-        if (NB == 2) {
-            if (epi == EPI_RAW) L(1, 2, EPI_RAW); else if (epi == EPI_GELU) L(1, 2, EPI_GELU); else if (epi == EPI_BACK_GELU) L(1, 2, EPI_BACK_GELU); else L(1, 2, EPI_RESID);
-        } else {
-            if (epi == EPI_RAW) L(1, 1, EPI_RAW); else if (epi == EPI_GELU) L(1, 1, EPI_GELU); else if (epi == EPI_BACK_GELU) L(1, 1, EPI_BACK_GELU); else L(1, 1, EPI_RESID);
-        }
-    } else {
-        if (NB == 2) {
-            if (epi == EPI_RAW) L(32, 2, EPI_RAW); else if (epi == EPI_GELU) L(32, 2, EPI_GELU); else if (epi == EPI_BACK_GELU) L(32, 2, EPI_BACK_GELU); else L(32, 2, EPI_RESID);
-        } else {
-            if (epi == EPI_RAW) L(32, 1, EPI_RAW); else if (epi == EPI_GELU) L(32, 1, EPI_GELU); else if (epi == EPI_BACK_GELU) L(32, 1, EPI_BACK_GELU); else L(32, 1, EPI_RESID);
-        }
-    }
-#undef L
-    return hipGetLastError();
 }
 
 hipError_t launch_pack(const float* W, int cin, int cout, int mode, bf16x8* out, hipStream_t s) {

@@ -48,123 +48,6 @@ __device__ __forceinline__ u16 f2bf(float f) {   // round to nearest, ties to ev
     u += 0x7fffu + ((u >> 16) & 1u);
     return (u16)(u >> 16);
 }
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * (0.39894228040143268f * __expf(-0.5f * z * z));
-}
-
-// ---------------------------------------------------------------- conv
-// Output channels padded to 16*NB.  aux: pre-activation (EPI_GELU, optional,
-// bf16 [v][16*NB]), pre-activation of the layer below (EPI_BACK_GELU), or the
-// FP32 input cube for the residual (EPI_RESID, output channel 0 only).
-template <int CIN, int NB, int EPI>
-__global__ void __launch_bounds__(256)
-k_conv(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* __restrict__ bias,
-       void* __restrict__ out, const void* __restrict__ aux, int nx, int ny, int nz) {
-    constexpr int COUTP = 16 * NB;
-    constexpr int LX = TX + 2, LY = TY + 2;
-    constexpr int CS = lds_stride<CIN>();
-    __shared__ __attribute__((aligned(16))) u16 tile[3 * LY * LX * CS];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z;
-
-    // stage the input region (with a one-voxel margin; zero outside the cube)
-    if constexpr (CIN % 8 == 0) {
-        constexpr int CH = CIN / 8;   // 16-byte chunks per voxel
-        for (int q = threadIdx.x; q < 3 * LY * LX * CH; q += 256) {
-            const int c = q % CH, vox = q / CH;
-            const int xx = vox % LX, yy = (vox / LX) % LY, zz = vox / (LX * LY);
-            const int x = x0 + xx - 1, y = y0 + yy - 1, z = z0 + zz - 1;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz)
-                v = *reinterpret_cast<const uint4*>(in + ((long)(z * ny + y) * nx + x) * CIN + 8 * c);
-            *reinterpret_cast<uint4*>(tile + vox * CS + 8 * c) = v;
-        }
-    } else {
-        for (int vox = threadIdx.x; vox < 3 * LY * LX; vox += 256) {
-            const int xx = vox % LX, yy = (vox / LX) % LY, zz = vox / (LX * LY);
-            const int x = x0 + xx - 1, y = y0 + yy - 1, z = z0 + zz - 1;
-            tile[vox] = (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz)
-                            ? in[(long)(z * ny + y) * nx + x] : (u16)0;
-        }
-    }
-    __syncthreads();
-
-    f32x4 acc[2][NB];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const int i = lane & 15, kg = lane >> 4;
-    if constexpr (CIN == 1) {
-        // K = taps: lane holds taps 8*kg .. 8*kg+7 of voxel row i
-        bf16x8 b[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) b[nb] = wp[nb * 64 + lane];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            bf16x8 a;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int t = 8 * kg + e;
-                u16 h = 0;
-                if (t < 27) {
-                    const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // 0..2 = offset + 1
-                    h = tile[(dz * LY + (w + dy)) * LX + (16 * s + i + dx)];
-                }
-                a[e] = __builtin_bit_cast(__bf16, h);
-            }
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[s][nb], 0, 0, 0);
-        }
-    } else {
-        static_assert(CIN == 32, "CIN must be 1 or 32");
-        for (int t = 0; t < 27; ++t) {
-            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            bf16x8 b[NB];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) b[nb] = wp[(t * NB + nb) * 64 + lane];
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int vox = (dz * LY + (w + dy)) * LX + (16 * s + i + dx);
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(tile + vox * CS + 8 * kg);
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[s][nb], 0, 0, 0);
-            }
-        }
-    }
-
-    // epilogue: lane holds D[m = 4*kg + e][n = 16*nb + i] of subtile s
-    const int y = y0 + w;
-    if (y >= ny) return;
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int x = x0 + 16 * s + 4 * kg + e;
-            if (x >= nx) continue;
-            const long v = (long)(z0 * ny + y) * nx + x;
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int n = 16 * nb + i;
-                const float d = acc[s][nb][e];
-                if constexpr (EPI == EPI_RAW) {
-                    static_cast<float*>(out)[v * COUTP + n] = d + (bias ? bias[n] : 0.0f);
-                } else if constexpr (EPI == EPI_GELU) {
-                    const float zpre = d + bias[n];
-                    if (aux) const_cast<u16*>(static_cast<const u16*>(aux))[v * COUTP + n] = f2bf(zpre);
-                    static_cast<u16*>(out)[v * COUTP + n] = f2bf(gelu(zpre));
-                } else if constexpr (EPI == EPI_BACK_GELU) {
-                    const float zb = bf2f(static_cast<const u16*>(aux)[v * COUTP + n]);
-                    static_cast<u16*>(out)[v * COUTP + n] = f2bf(d * gelu_grad(zb));
-                } else {   // EPI_RESID: output channel 0 only
-                    if (n == 0) static_cast<float*>(out)[v] = static_cast<const float*>(aux)[v] + (d + bias[0]);
-                }
-            }
-        }
-}
 
 // ------------------------------------------------ conv, z-streaming, 32 in
 // Error function by Abramowitz & Stegun, Handbook of Mathematical Functions,
@@ -213,11 +96,65 @@ __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
 // channels of one voxel and stores them with one 8-byte write.  Per output the
 // taps are accumulated in the order 0..26, then the bias is added.
 constexpr int kZsRows = 8;
+constexpr int kZsAhead = 2;   // taps whose LDS fragments are in flight ahead of the MFMAs
 
 template <int MT>
 constexpr int zs_plane_u16() { return (16 * MT + 2) * (kZsRows + 2) * lds_stride<32>(); }
 template <int MT, int NB>
 constexpr size_t zs_lds_bytes() { return (size_t)27 * NB * 64 * 16 + (size_t)3 * zs_plane_u16<MT>() * 2; }
+
+// Epilogue of the z-stream kernels: lane (i + 16 kg) holds D[m = 4 kg + e][n = i]
+// of each (s, nb), output channels 16 nb + 4 kg + e of voxel 16 s + i of row y,
+// plane z; four consecutive channels go out in one 8- or 16-byte store.
+// Output channels are padded to 16 NB.  aux: the bf16 pre-activation
+// [v][16 NB] (EPI_GELU, optional), the pre-activation of the layer below
+// (EPI_BACK_GELU), or the FP32 input cube for the residual (EPI_RESID, output
+// channel 0 only).
+template <int NB, int EPI, int MT>
+__device__ __forceinline__ void zs_store(const f32x4 (&acc)[MT][NB], const float* __restrict__ bias,
+                                         void* __restrict__ out, const void* __restrict__ aux, int x0, int y, int z,
+                                         int nx, int ny, int i, int kg) {
+    constexpr int COUTP = 16 * NB;
+    if (y < ny) {
+#pragma unroll
+        for (int s = 0; s < MT; ++s) {
+            const int x = x0 + 16 * s + i;
+            if (x >= nx) continue;
+            const long v = (long)(z * ny + y) * nx + x;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int n0 = 16 * nb + 4 * kg;
+                const f32x4 d = acc[s][nb];
+                if constexpr (EPI == EPI_RAW) {
+                    float4 r;
+                    r.x = d[0] + (bias ? bias[n0] : 0.0f);
+                    r.y = d[1] + (bias ? bias[n0 + 1] : 0.0f);
+                    r.z = d[2] + (bias ? bias[n0 + 2] : 0.0f);
+                    r.w = d[3] + (bias ? bias[n0 + 3] : 0.0f);
+                    *reinterpret_cast<float4*>(static_cast<float*>(out) + v * COUTP + n0) = r;
+                } else if constexpr (EPI == EPI_GELU) {
+                    const float z0p = d[0] + bias[n0], z1p = d[1] + bias[n0 + 1];
+                    const float z2p = d[2] + bias[n0 + 2], z3p = d[3] + bias[n0 + 3];
+                    if (aux)
+                        *reinterpret_cast<uint2*>(const_cast<u16*>(static_cast<const u16*>(aux)) + v * COUTP + n0) =
+                            pack_bf16x4(z0p, z1p, z2p, z3p);
+                    *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
+                        pack_bf16x4(gelu_fast(z0p), gelu_fast(z1p), gelu_fast(z2p), gelu_fast(z3p));
+                } else if constexpr (EPI == EPI_BACK_GELU) {
+                    const uint2 pb = *reinterpret_cast<const uint2*>(static_cast<const u16*>(aux) + v * COUTP + n0);
+                    const float g0 = gelu_grad_fast(__uint_as_float(pb.x << 16));
+                    const float g1 = gelu_grad_fast(__uint_as_float(pb.x & 0xffff0000u));
+                    const float g2 = gelu_grad_fast(__uint_as_float(pb.y << 16));
+                    const float g3 = gelu_grad_fast(__uint_as_float(pb.y & 0xffff0000u));
+                    *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
+                        pack_bf16x4(d[0] * g0, d[1] * g1, d[2] * g2, d[3] * g3);
+                } else {   // EPI_RESID: output channel 0 only
+                    if (n0 == 0) static_cast<float*>(out)[v] = static_cast<const float*>(aux)[v] + (d[0] + bias[0]);
+                }
+            }
+        }
+    }
+}
 
 template <int NB, int EPI, int MT>
 __global__ void __launch_bounds__(512)
@@ -280,68 +217,225 @@ k_conv_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float
         for (int s = 0; s < MT; ++s)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // taps in order 0..26, the LDS fragments of tap t + kZsAhead read while
+        // tap t's MFMAs run (the scheduling barriers keep the compiler from
+        // sinking each read down to its use, which left every pair of MFMAs
+        // waiting for the LDS)
+        bf16x8 wr[kZsAhead + 1][NB], ar[kZsAhead + 1][MT];
+        auto load = [&](int t, bf16x8 (&wf)[NB], bf16x8 (&av)[MT]) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const u16* slot = ring + ((z + 2 + dz) % 3) * PLU;
 #pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-            const u16* slot = ring + ((z - 1 + dz + 3) % 3) * PLU;
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const int t = dz * 9 + dy * 3 + dx;
-                    bf16x8 wf[NB];
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) wf[nb] = Bs[(t * NB + nb) * 64 + lane];
-#pragma unroll
-                    for (int s = 0; s < MT; ++s) {
-                        const int vox = (w + dy) * LX + (16 * s + i + dx);
-                        const bf16x8 a = *reinterpret_cast<const bf16x8*>(slot + vox * CS + 8 * kg);
-#pragma unroll
-                        for (int nb = 0; nb < NB; ++nb)
-                            acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], a, acc[s][nb], 0, 0, 0);
-                    }
-                }
-        }
-        // epilogue: lane holds D[m = 4*kg + e][n = i], output channel 16*nb + 4*kg + e of voxel 16*s + i
-        if (y < ny) {
+            for (int nb = 0; nb < NB; ++nb) wf[nb] = Bs[(t * NB + nb) * 64 + lane];
 #pragma unroll
             for (int s = 0; s < MT; ++s) {
-                const int x = x0 + 16 * s + i;
-                if (x >= nx) continue;
-                const long v = (long)(z * ny + y) * nx + x;
+                const int vox = (w + dy) * LX + (16 * s + i + dx);
+                av[s] = *reinterpret_cast<const bf16x8*>(slot + vox * CS + 8 * kg);
+            }
+        };
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    const int n0 = 16 * nb + 4 * kg;
-                    const f32x4 d = acc[s][nb];
-                    if constexpr (EPI == EPI_RAW) {
-                        float4 r;
-                        r.x = d[0] + (bias ? bias[n0] : 0.0f);
-                        r.y = d[1] + (bias ? bias[n0 + 1] : 0.0f);
-                        r.z = d[2] + (bias ? bias[n0 + 2] : 0.0f);
-                        r.w = d[3] + (bias ? bias[n0 + 3] : 0.0f);
-                        *reinterpret_cast<float4*>(static_cast<float*>(out) + v * COUTP + n0) = r;
-                    } else if constexpr (EPI == EPI_GELU) {
-                        const float z0p = d[0] + bias[n0], z1p = d[1] + bias[n0 + 1];
-                        const float z2p = d[2] + bias[n0 + 2], z3p = d[3] + bias[n0 + 3];
-                        if (aux)
-                            *reinterpret_cast<uint2*>(const_cast<u16*>(static_cast<const u16*>(aux)) + v * COUTP + n0) =
-                                pack_bf16x4(z0p, z1p, z2p, z3p);
-                        *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
-                            pack_bf16x4(gelu_fast(z0p), gelu_fast(z1p), gelu_fast(z2p), gelu_fast(z3p));
-                    } else if constexpr (EPI == EPI_BACK_GELU) {
-                        const uint2 pb = *reinterpret_cast<const uint2*>(static_cast<const u16*>(aux) + v * COUTP + n0);
-                        const float g0 = gelu_grad_fast(__uint_as_float(pb.x << 16));
-                        const float g1 = gelu_grad_fast(__uint_as_float(pb.x & 0xffff0000u));
-                        const float g2 = gelu_grad_fast(__uint_as_float(pb.y << 16));
-                        const float g3 = gelu_grad_fast(__uint_as_float(pb.y & 0xffff0000u));
-                        *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
-                            pack_bf16x4(d[0] * g0, d[1] * g1, d[2] * g2, d[3] * g3);
-                    } else {   // EPI_RESID: output channel 0 only
-                        if (n0 == 0) static_cast<float*>(out)[v] = static_cast<const float*>(aux)[v] + (d[0] + bias[0]);
+        for (int t = 0; t < kZsAhead; ++t) load(t, wr[t], ar[t]);
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            if (t + kZsAhead < 27) load(t + kZsAhead, wr[(t + kZsAhead) % (kZsAhead + 1)], ar[(t + kZsAhead) % (kZsAhead + 1)]);
+            __builtin_amdgcn_sched_barrier(0);
+            const int r = t % (kZsAhead + 1);
+#pragma unroll
+            for (int s = 0; s < MT; ++s)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[r][nb], ar[r][s], acc[s][nb], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        zs_store<NB, EPI, MT>(acc, bias, out, aux, x0, y, z, nx, ny, i, kg);
+        __syncthreads();   // every wavefront is done with slot (z - 1) before it takes plane z + 2
+    }
+}
+
+// The convolution of a 1-channel input as a z-stream (the network's first
+// layer, and the input gradient of its 1-channel last layer): the tiles and z
+// chunks of k_conv_zs, with K = the 27 taps of one voxel (padded to 32).  The
+// three input planes z-1 .. z+1 of the tile and its margin (one bf16 value per
+// voxel) sit in a small LDS ring, each lane gathers its 8 taps from it, and the
+// weights, the MFMA's A operand, stay in registers, so each lane ends with
+// four consecutive output channels of one voxel like k_conv_zs.  Per output
+// the taps are summed inside the MFMA, then the bias is added.
+template <int NB, int EPI, int MT>
+__global__ void __launch_bounds__(512)
+k_conv1_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* __restrict__ bias,
+           void* __restrict__ out, const void* __restrict__ aux, int nx, int ny, int nz, int ntx, int nty, int zch) {
+    constexpr int XW = 16 * MT, LX = XW + 2, LY = kZsRows + 2, NPL = LX * LY;
+    static_assert(NPL <= 64 * kZsRows, "one staged voxel per thread");
+    __shared__ u16 ring[3 * NPL];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kg = lane >> 4;
+    const int bt = blockIdx.x;
+    const int tx = bt % ntx, ty = (bt / ntx) % nty, tz = bt / (ntx * nty);
+    const int x0 = tx * XW, y0 = ty * kZsRows;
+    const int z0 = tz * zch, z1 = min(nz, z0 + zch);
+
+    bf16x8 wf[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) wf[nb] = wp[nb * 64 + lane];
+
+    // thread q stages voxel q of every plane (zero outside the cube)
+    const int q = threadIdx.x;
+    const int qx = x0 + q % LX - 1, qy = y0 + q / LX - 1;
+    const bool qin = q < NPL && qx >= 0 && qx < nx && qy >= 0 && qy < ny;
+    const long qoff = qin ? (long)qy * nx + qx : 0;
+    const long plane = (long)nx * ny;
+    auto fetch = [&](int z) -> u16 { return (qin && z >= 0 && z < nz) ? in[z * plane + qoff] : (u16)0; };
+    auto put = [&](int z, u16 v) {
+        if (q < NPL) ring[((z + 3) % 3) * NPL + q] = v;
+    };
+    put(z0 - 1, fetch(z0 - 1));
+    put(z0, fetch(z0));
+    u16 nxt = fetch(z0 + 1);
+
+    const int y = y0 + w;
+    for (int z = z0; z < z1; ++z) {
+        put(z + 1, nxt);
+        __syncthreads();
+        if (z + 1 < z1) nxt = fetch(z + 2);
+
+        f32x4 acc[MT][NB];
+#pragma unroll
+        for (int s = 0; s < MT; ++s) {
+            bf16x8 a;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int t = 8 * kg + e;
+                u16 h = 0;
+                if (t < 27) {
+                    const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                    h = ring[((z + 2 + dz) % 3) * NPL + (w + dy) * LX + 16 * s + i + dx];
+                }
+                a[e] = __builtin_bit_cast(__bf16, h);
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nb], a, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        }
+        zs_store<NB, EPI, MT>(acc, bias, out, aux, x0, y, z, nx, ny, i, kg);
+        __syncthreads();   // every wavefront is done with slot (z - 1) before it takes plane z + 2
+    }
+}
+
+// A 32-channel input to one output channel (the network's last layer) as a
+// z-stream.  For each plane u of the tile and its one-voxel margin the MFMA
+// computes the 27 per-tap sums P_t(v) = sum_c X(v, c) W[t][c] of every voxel
+// (weights as the A operand, M = taps, K = channels; activations as B, 16
+// voxels per MFMA), into LDS.  Output (x, y, z) then adds P_t at its 27
+// neighbours: the dz = 0 taps from plane z-1, the dz = 1 taps from plane z, the
+// dz = 2 taps from plane z+1, so it sums its taps in the order 0..26 and then
+// adds the bias (and, for the residual, adds that to the input).  Each
+// activation is read from memory and multiplied once, instead of once per tap
+// with 15 of 16 MFMA columns idle.  P is double-buffered, one barrier per plane.
+constexpr int kO1X = 32;                                    // output tile: 32 x kZsRows
+constexpr int kO1Vox = (kO1X + 2) * (kZsRows + 2);          // voxels of the tile and margin
+constexpr int kO1Groups = (kO1Vox + 15) / 16;               // MFMA column groups of 16 voxels
+constexpr int kO1Stride = kO1Groups * 16 + 4;               // floats per tap (4 taps apart: 16 banks apart)
+constexpr size_t kO1Lds = (size_t)2 * 27 * kO1Stride * 4;
+
+template <int EPI>
+__global__ void __launch_bounds__(512)
+k_conv_out1(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* __restrict__ bias,
+            float* __restrict__ out, const float* __restrict__ aux, int nx, int ny, int nz, int ntx, int nty,
+            int zch) {
+    static_assert(EPI == EPI_RAW || EPI == EPI_RESID, "raw or residual output");
+    constexpr int LX = kO1X + 2;
+    constexpr int GPW = (kO1Groups + kZsRows - 1) / kZsRows;   // column groups per wavefront
+    extern __shared__ float o1_smem[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kg = lane >> 4;
+    const int bt = blockIdx.x;
+    const int tx = bt % ntx, ty = (bt / ntx) % nty, tz = bt / (ntx * nty);
+    const int x0 = tx * kO1X, y0 = ty * kZsRows;
+    const int z0 = tz * zch, z1 = min(nz, z0 + zch);
+    const long plane = (long)nx * ny;
+
+    // A fragments: lane (i + 16 kg) holds W[tap 16 mb + i][channels 8 kg .. 8 kg + 7];
+    // the packed B layout of tap t keeps exactly that in its lane 16 kg
+    bf16x8 wa[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        const int t = 16 * mb + i;
+        wa[mb] = t < 27 ? wp[t * 64 + 16 * kg] : bf16x8{};
+    }
+    // this lane's B column: voxel 16 g + i of the tile and margin, channels 8 kg ..
+    long voff[GPW];
+    bool vin[GPW];
+#pragma unroll
+    for (int k = 0; k < GPW; ++k) {
+        const int g = w + kZsRows * k, q = 16 * g + i;
+        const int qx = x0 + q % LX - 1, qy = y0 + q / LX - 1;
+        vin[k] = g < kO1Groups && q < kO1Vox && qx >= 0 && qx < nx && qy >= 0 && qy < ny;
+        voff[k] = vin[k] ? ((long)qy * nx + qx) * 32 + 8 * kg : 0;
+    }
+    uint4 b[GPW];
+    auto fetch = [&](int u) {
+#pragma unroll
+        for (int k = 0; k < GPW; ++k)
+            b[k] = (vin[k] && u >= 0 && u < nz) ? *reinterpret_cast<const uint4*>(in + u * plane * 32 + voff[k])
+                                                : make_uint4(0, 0, 0, 0);
+    };
+
+    // output voxel of this thread (threads 256 .. 511 only compute P)
+    const int ox = threadIdx.x % kO1X, oy = threadIdx.x / kO1X;
+    const bool owner = threadIdx.x < kO1X * kZsRows;
+    const int x = x0 + ox, y = y0 + oy;
+    const bool store = owner && x < nx && y < ny;
+    float a_prev = 0.f, a_cur = 0.f;   // sums of outputs z = u - 1 and z = u
+
+    fetch(z0 - 1);
+    for (int u = z0 - 1; u <= z1; ++u) {
+        float* P = o1_smem + (u & 1) * 27 * kO1Stride;
+#pragma unroll
+        for (int k = 0; k < GPW; ++k) {
+            const int g = w + kZsRows * k;
+            if (g < kO1Groups) {
+                const bf16x8 bv = __builtin_bit_cast(bf16x8, b[k]);
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) {
+                    const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb], bv, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int t = 16 * mb + 4 * kg + e;
+                        if (t < 27) P[t * kO1Stride + 16 * g + i] = d[e];
                     }
                 }
             }
         }
-        __syncthreads();   // every wavefront is done with slot (z - 1) before it takes plane z + 2
+        if (u < z1) fetch(u + 1);
+        __syncthreads();
+        if (owner) {
+            const float* c = P + oy * LX + ox;
+            float a_next = c[0];
+#pragma unroll
+            for (int t = 1; t < 9; ++t) a_next += c[t * kO1Stride + (t / 3) * LX + t % 3];
+#pragma unroll
+            for (int t = 9; t < 18; ++t) a_cur += c[t * kO1Stride + ((t / 3) % 3) * LX + t % 3];
+#pragma unroll
+            for (int t = 18; t < 27; ++t) a_prev += c[t * kO1Stride + ((t / 3) % 3) * LX + t % 3];
+            const int zo = u - 1;   // a_prev is complete
+            if (store && zo >= z0) {
+                const long v = (long)zo * plane + (long)y * nx + x;
+                if constexpr (EPI == EPI_RESID) {
+                    out[v] = aux[v] + (a_prev + bias[0]);
+                } else {
+                    float4 r0, r1, r2, r3;
+                    r0.x = a_prev + (bias ? bias[0] : 0.0f);
+                    r0.y = bias ? bias[1] : 0.0f; r0.z = bias ? bias[2] : 0.0f; r0.w = bias ? bias[3] : 0.0f;
+                    r1 = bias ? make_float4(bias[4], bias[5], bias[6], bias[7]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    r2 = bias ? make_float4(bias[8], bias[9], bias[10], bias[11]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    r3 = bias ? make_float4(bias[12], bias[13], bias[14], bias[15]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    float4* o = reinterpret_cast<float4*>(out + v * 16);
+                    o[0] = r0; o[1] = r1; o[2] = r2; o[3] = r3;
+                }
+            }
+            a_prev = a_cur;
+            a_cur = a_next;
+        }
     }
 }
 
