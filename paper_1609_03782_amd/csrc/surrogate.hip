@@ -54,12 +54,13 @@ long wgrad_groups(long nx, long ny, long nz) { return std::min(kWgradGroups, wgr
 // Grid of the z-streaming kernels (tiles of xw voxels by kZsRows rows, one
 // workgroup per (tile, z chunk)): the z chunk that minimises the slowest
 // compute unit's share (in planes, counting the two margin planes and the
-// set-up as about two more) with one workgroup per CU.
+// set-up as about two more, and for a kernel that computes planes in pairs an
+// odd chunk's last plane as a whole pair) with one workgroup per CU.
 struct ZsGrid {
     int ntx, nty, zch;
     long groups;
 };
-ZsGrid zs_grid(long nx, long ny, long nz, int xw) {
+ZsGrid zs_grid(long nx, long ny, long nz, int xw, bool pairs) {
     ZsGrid g;
     g.ntx = (int)((nx + xw - 1) / xw);
     g.nty = (int)((ny + kZsRows - 1) / kZsRows);
@@ -71,7 +72,7 @@ ZsGrid zs_grid(long nx, long ny, long nz, int xw) {
     for (long nzc = 1; nzc <= nz; ++nzc) {
         const long zc = (nz + nzc - 1) / nzc;
         const long groups = tiles * ((nz + zc - 1) / zc);
-        const long cost = ((groups + ncu - 1) / ncu) * (zc + 4);
+        const long cost = ((groups + ncu - 1) / ncu) * (zc + (pairs ? (zc & 1) : 0) + 4);
         if (best_cost < 0 || cost < best_cost) { best_cost = cost; zch = zc; }
         if (zc == 1) break;
     }
@@ -81,13 +82,13 @@ ZsGrid zs_grid(long nx, long ny, long nz, int xw) {
 }
 
 // 32-channel input: 8 rows of 32 voxels (2 M-tiles) per workgroup, the largest
-// tile whose three padded planes and the weights fit the 160 KB of LDS
+// tile whose four staged planes and the weights fit the 160 KB of LDS
 template <int NB, int EPI>
 hipError_t zs_launch(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
                      long nz, hipStream_t s) {
     constexpr int MT = 2;
     static_assert(zs_lds_bytes<MT, 2>() <= 160 * 1024, "z-stream tile exceeds LDS");
-    const ZsGrid g = zs_grid(nx, ny, nz, 16 * MT);
+    const ZsGrid g = zs_grid(nx, ny, nz, 16 * MT, true);
     const size_t lds = zs_lds_bytes<MT, NB>();
     auto kern = k_conv_zs<NB, EPI, MT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -102,7 +103,7 @@ template <int NB, int EPI>
 hipError_t zs1_launch(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
                       long nz, hipStream_t s) {
     constexpr int MT = 2;
-    const ZsGrid g = zs_grid(nx, ny, nz, 16 * MT);
+    const ZsGrid g = zs_grid(nx, ny, nz, 16 * MT, false);
     hipLaunchKernelGGL((k_conv1_zs<NB, EPI, MT>), dim3((unsigned)g.groups), dim3(64 * kZsRows), 0, s, x, wp, b, out,
                        aux, (int)nx, (int)ny, (int)nz, g.ntx, g.nty, g.zch);
     return hipGetLastError();
@@ -113,7 +114,7 @@ template <int EPI>
 hipError_t out1_launch(const u16* x, const bf16x8* wp, const float* b, void* out, const void* aux, long nx, long ny,
                        long nz, hipStream_t s) {
     static_assert(kO1Lds <= 160 * 1024, "tap partials exceed LDS");
-    const ZsGrid g = zs_grid(nx, ny, nz, kO1X);
+    const ZsGrid g = zs_grid(nx, ny, nz, kO1X, false);
     auto kern = k_conv_out1<EPI>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kO1Lds);
     if (e != hipSuccess) return e;

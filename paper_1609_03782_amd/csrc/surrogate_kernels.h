@@ -86,22 +86,27 @@ __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
 
 // The convolution of a 32-channel input as a z-stream: a workgroup of 8
 // wavefronts owns an output tile of 16*MT voxels in x by 8 rows in y (one
-// row per wavefront, MT 16-voxel tiles each) and a chunk of planes [z0, z1).
-// The packed weight fragments of all 27 taps are copied to LDS once; input
-// planes z-1, z, z+1 (tile plus a one-voxel margin, zeros outside the cube)
-// sit in a ring of three LDS slots, and while plane z is computed the global
-// loads of plane z+2 are in flight in registers.  The weights are the MFMA's
-// A operand and the activations its B operand (the same register fragments
-// as the other way round), so each lane ends with four consecutive output
-// channels of one voxel and stores them with one 8-byte write.  Per output the
-// taps are accumulated in the order 0..26, then the bias is added.
+// row per wavefront, MT 16-voxel tiles each) and a chunk of planes [z0, z1),
+// computed two planes at a time.  The packed weight fragments of all 27 taps
+// are copied to LDS once; input planes z-1 .. z+2 (tile plus a one-voxel
+// margin, zeros outside the cube) sit in a ring of four LDS slots, and while
+// planes z and z+1 are computed the global loads of planes z+3 and z+4 are in
+// flight in registers.  The LDS bandwidth (128 bytes per clock per CU for
+// 16-byte reads, whatever the address pattern: measured) bounds this kernel,
+// so each weight fragment read from LDS serves both planes: 6 fragment reads
+// per tap feed 8 MFMAs instead of 4 reads feeding 4.  The weights are the
+// MFMA's A operand and the activations its B operand (the same register
+// fragments as the other way round), so each lane ends with four consecutive
+// output channels of one voxel and stores them with one 8-byte write.  Per
+// output the taps are accumulated in the order 0..26, then the bias is added.
 constexpr int kZsRows = 8;
 constexpr int kZsAhead = 2;   // taps whose LDS fragments are in flight ahead of the MFMAs
+constexpr int kZsCS = 32;     // u16 per staged voxel (32 channels, unpadded)
 
 template <int MT>
-constexpr int zs_plane_u16() { return (16 * MT + 2) * (kZsRows + 2) * lds_stride<32>(); }
+constexpr int zs_plane_u16() { return (16 * MT + 2) * (kZsRows + 2) * kZsCS; }
 template <int MT, int NB>
-constexpr size_t zs_lds_bytes() { return (size_t)27 * NB * 64 * 16 + (size_t)3 * zs_plane_u16<MT>() * 2; }
+constexpr size_t zs_lds_bytes() { return (size_t)27 * NB * 64 * 16 + (size_t)4 * zs_plane_u16<MT>() * 2; }
 
 // Epilogue of the z-stream kernels: lane (i + 16 kg) holds D[m = 4 kg + e][n = i]
 // of each (s, nb), output channels 16 nb + 4 kg + e of voxel 16 s + i of row y,
@@ -110,59 +115,71 @@ constexpr size_t zs_lds_bytes() { return (size_t)27 * NB * 64 * 16 + (size_t)3 *
 // [v][16 NB] (EPI_GELU, optional), the pre-activation of the layer below
 // (EPI_BACK_GELU), or the FP32 input cube for the residual (EPI_RESID, output
 // channel 0 only).
+// The four bf16 pre-activations EPI_BACK_GELU multiplies by (0 outside the cube).
+template <int NB>
+__device__ __forceinline__ uint2 zs_pre(const void* __restrict__ aux, int s, int nb, int x0, int y, int z, int nx,
+                                        int ny, int i, int kg) {
+    const int x = x0 + 16 * s + i;
+    if (y >= ny || x >= nx) return make_uint2(0, 0);
+    const long v = (long)(z * ny + y) * nx + x;
+    return *reinterpret_cast<const uint2*>(static_cast<const u16*>(aux) + v * 16 * NB + 16 * nb + 4 * kg);
+}
+
+// pb: the pre-activations of this fragment (EPI_BACK_GELU only, from zs_pre)
+template <int NB, int EPI>
+__device__ __forceinline__ void zs_store_one(const f32x4& d, uint2 pb, int s, int nb, const float* __restrict__ bias,
+                                             void* __restrict__ out, const void* __restrict__ aux, int x0, int y, int z,
+                                             int nx, int ny, int i, int kg) {
+    constexpr int COUTP = 16 * NB;
+    const int x = x0 + 16 * s + i;
+    if (y >= ny || x >= nx) return;
+    const long v = (long)(z * ny + y) * nx + x;
+    const int n0 = 16 * nb + 4 * kg;
+    if constexpr (EPI == EPI_RAW) {
+        float4 r;
+        r.x = d[0] + (bias ? bias[n0] : 0.0f);
+        r.y = d[1] + (bias ? bias[n0 + 1] : 0.0f);
+        r.z = d[2] + (bias ? bias[n0 + 2] : 0.0f);
+        r.w = d[3] + (bias ? bias[n0 + 3] : 0.0f);
+        *reinterpret_cast<float4*>(static_cast<float*>(out) + v * COUTP + n0) = r;
+    } else if constexpr (EPI == EPI_GELU) {
+        const float z0p = d[0] + bias[n0], z1p = d[1] + bias[n0 + 1];
+        const float z2p = d[2] + bias[n0 + 2], z3p = d[3] + bias[n0 + 3];
+        if (aux)
+            *reinterpret_cast<uint2*>(const_cast<u16*>(static_cast<const u16*>(aux)) + v * COUTP + n0) =
+                pack_bf16x4(z0p, z1p, z2p, z3p);
+        *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
+            pack_bf16x4(gelu_fast(z0p), gelu_fast(z1p), gelu_fast(z2p), gelu_fast(z3p));
+    } else if constexpr (EPI == EPI_BACK_GELU) {
+        const float g0 = gelu_grad_fast(__uint_as_float(pb.x << 16));
+        const float g1 = gelu_grad_fast(__uint_as_float(pb.x & 0xffff0000u));
+        const float g2 = gelu_grad_fast(__uint_as_float(pb.y << 16));
+        const float g3 = gelu_grad_fast(__uint_as_float(pb.y & 0xffff0000u));
+        *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
+            pack_bf16x4(d[0] * g0, d[1] * g1, d[2] * g2, d[3] * g3);
+    } else {   // EPI_RESID: output channel 0 only
+        if (n0 == 0) static_cast<float*>(out)[v] = static_cast<const float*>(aux)[v] + (d[0] + bias[0]);
+    }
+}
+
 template <int NB, int EPI, int MT>
 __device__ __forceinline__ void zs_store(const f32x4 (&acc)[MT][NB], const float* __restrict__ bias,
                                          void* __restrict__ out, const void* __restrict__ aux, int x0, int y, int z,
                                          int nx, int ny, int i, int kg) {
-    constexpr int COUTP = 16 * NB;
-    if (y < ny) {
 #pragma unroll
-        for (int s = 0; s < MT; ++s) {
-            const int x = x0 + 16 * s + i;
-            if (x >= nx) continue;
-            const long v = (long)(z * ny + y) * nx + x;
+    for (int s = 0; s < MT; ++s)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int n0 = 16 * nb + 4 * kg;
-                const f32x4 d = acc[s][nb];
-                if constexpr (EPI == EPI_RAW) {
-                    float4 r;
-                    r.x = d[0] + (bias ? bias[n0] : 0.0f);
-                    r.y = d[1] + (bias ? bias[n0 + 1] : 0.0f);
-                    r.z = d[2] + (bias ? bias[n0 + 2] : 0.0f);
-                    r.w = d[3] + (bias ? bias[n0 + 3] : 0.0f);
-                    *reinterpret_cast<float4*>(static_cast<float*>(out) + v * COUTP + n0) = r;
-                } else if constexpr (EPI == EPI_GELU) {
-                    const float z0p = d[0] + bias[n0], z1p = d[1] + bias[n0 + 1];
-                    const float z2p = d[2] + bias[n0 + 2], z3p = d[3] + bias[n0 + 3];
-                    if (aux)
-                        *reinterpret_cast<uint2*>(const_cast<u16*>(static_cast<const u16*>(aux)) + v * COUTP + n0) =
-                            pack_bf16x4(z0p, z1p, z2p, z3p);
-                    *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
-                        pack_bf16x4(gelu_fast(z0p), gelu_fast(z1p), gelu_fast(z2p), gelu_fast(z3p));
-                } else if constexpr (EPI == EPI_BACK_GELU) {
-                    const uint2 pb = *reinterpret_cast<const uint2*>(static_cast<const u16*>(aux) + v * COUTP + n0);
-                    const float g0 = gelu_grad_fast(__uint_as_float(pb.x << 16));
-                    const float g1 = gelu_grad_fast(__uint_as_float(pb.x & 0xffff0000u));
-                    const float g2 = gelu_grad_fast(__uint_as_float(pb.y << 16));
-                    const float g3 = gelu_grad_fast(__uint_as_float(pb.y & 0xffff0000u));
-                    *reinterpret_cast<uint2*>(static_cast<u16*>(out) + v * COUTP + n0) =
-                        pack_bf16x4(d[0] * g0, d[1] * g1, d[2] * g2, d[3] * g3);
-                } else {   // EPI_RESID: output channel 0 only
-                    if (n0 == 0) static_cast<float*>(out)[v] = static_cast<const float*>(aux)[v] + (d[0] + bias[0]);
-                }
-            }
+        for (int nb = 0; nb < NB; ++nb) {
+            const uint2 pb = EPI == EPI_BACK_GELU ? zs_pre<NB>(aux, s, nb, x0, y, z, nx, ny, i, kg) : make_uint2(0, 0);
+            zs_store_one<NB, EPI>(acc[s][nb], pb, s, nb, bias, out, aux, x0, y, z, nx, ny, i, kg);
         }
-    }
 }
 
 template <int NB, int EPI, int MT>
 __global__ void __launch_bounds__(512)
 k_conv_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float* __restrict__ bias,
           void* __restrict__ out, const void* __restrict__ aux, int nx, int ny, int nz, int ntx, int nty, int zch) {
-    constexpr int COUTP = 16 * NB;
     constexpr int XW = 16 * MT, LX = XW + 2, LY = kZsRows + 2;
-    constexpr int CS = lds_stride<32>();
     constexpr int PLU = zs_plane_u16<MT>();
     constexpr int NT = 64 * kZsRows;                // threads
     constexpr int NCH = LX * LY * 4;               // 16-byte chunks of one staged plane
@@ -179,8 +196,8 @@ k_conv_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float
 
     for (int q = threadIdx.x; q < 27 * NB * 64; q += NT) Bs[q] = wp[q];
 
-    uint4 st[PER];
-    auto fetch = [&](int z) {
+    uint4 st[2][PER];
+    auto fetch = [&](int z, uint4 (&dst)[PER]) {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int q = threadIdx.x + NT * k;
@@ -189,48 +206,75 @@ k_conv_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float
             const int x = x0 + vox % LX - 1, y = y0 + vox / LX - 1;
             if (q < NCH && z >= 0 && z < nz && x >= 0 && x < nx && y >= 0 && y < ny)
                 v = *reinterpret_cast<const uint4*>(in + ((long)(z * ny + y) * nx + x) * 32 + 8 * c);
-            st[k] = v;
+            dst[k] = v;
         }
     };
-    auto put = [&](int z) {
-        u16* slot = ring + ((z + 3) % 3) * PLU;
+    auto put = [&](int z, const uint4 (&src)[PER]) {   // plane z goes to slot z mod 4
+        u16* slot = ring + ((z + 4) & 3) * PLU;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int q = threadIdx.x + NT * k;
-            if (q < NCH) *reinterpret_cast<uint4*>(slot + (q >> 2) * CS + 8 * (q & 3)) = st[k];
+            if (q < NCH) *reinterpret_cast<uint4*>(slot + (q >> 2) * kZsCS + 8 * (q & 3)) = src[k];
         }
     };
-    fetch(z0 - 1);
-    put(z0 - 1);
-    fetch(z0);
-    put(z0);
-    fetch(z0 + 1);
+    fetch(z0 - 1, st[0]);
+    put(z0 - 1, st[0]);
+    fetch(z0, st[0]);
+    put(z0, st[0]);
+    fetch(z0 + 1, st[0]);
+    fetch(z0 + 2, st[1]);
 
     const int y = y0 + w;
-    for (int z = z0; z < z1; ++z) {
-        put(z + 1);
+    // results of the previous pair of planes (zp, zp + 1), stored piecewise
+    // during the next pair's tap loop so the epilogue's VALU work (GELU) runs
+    // beside the MFMAs and LDS reads instead of between two barriers
+    // (EPI_BACK_GELU: the pre-activations they need are loaded before the next
+    // planes' staging loads, so their wait does not include those)
+    constexpr int NPART = 2 * MT * NB;
+    f32x4 prev[2][MT][NB];
+    uint2 pre[2][MT][NB];
+    int zp = -1;
+    bool zp2 = false;   // the previous pair's second plane is an output
+    auto store_part = [&](int j) {
+        const int pp = j / (MT * NB), s = (j / NB) % MT, nb = j % NB;
+        if (zp >= 0 && (pp == 0 || zp2))
+            zs_store_one<NB, EPI>(prev[pp][s][nb], pre[pp][s][nb], s, nb, bias, out, aux, x0, y, zp + pp, nx, ny, i, kg);
+    };
+    for (int z = z0; z < z1; z += 2) {
+        put(z + 1, st[0]);
+        put(z + 2, st[1]);
         __syncthreads();
-        if (z + 1 < z1) fetch(z + 2);
+        if (z + 2 < z1) {
+            fetch(z + 3, st[0]);
+            fetch(z + 4, st[1]);
+        }
 
-        f32x4 acc[MT][NB];
+        // planes z and z + 1 (the second is computed but not stored when the
+        // chunk ends at z + 1; its inputs are the ring's planes z .. z + 2)
+        f32x4 acc[2][MT][NB];
 #pragma unroll
-        for (int s = 0; s < MT; ++s)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < MT; ++s)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[p][s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
         // taps in order 0..26, the LDS fragments of tap t + kZsAhead read while
         // tap t's MFMAs run (the scheduling barriers keep the compiler from
         // sinking each read down to its use, which left every pair of MFMAs
         // waiting for the LDS)
-        bf16x8 wr[kZsAhead + 1][NB], ar[kZsAhead + 1][MT];
-        auto load = [&](int t, bf16x8 (&wf)[NB], bf16x8 (&av)[MT]) {
+        bf16x8 wr[kZsAhead + 1][NB], ar[kZsAhead + 1][2][MT];
+        auto load = [&](int t, bf16x8 (&wf)[NB], bf16x8 (&av)[2][MT]) {
             const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const u16* slot = ring + ((z + 2 + dz) % 3) * PLU;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) wf[nb] = Bs[(t * NB + nb) * 64 + lane];
 #pragma unroll
-            for (int s = 0; s < MT; ++s) {
-                const int vox = (w + dy) * LX + (16 * s + i + dx);
-                av[s] = *reinterpret_cast<const bf16x8*>(slot + vox * CS + 8 * kg);
+            for (int p = 0; p < 2; ++p) {
+                const u16* slot = ring + ((z + 3 + p + dz) & 3) * PLU;   // plane z + p - 1 + dz
+#pragma unroll
+                for (int s = 0; s < MT; ++s) {
+                    const int vox = (w + dy) * LX + (16 * s + i + dx);
+                    av[p][s] = *reinterpret_cast<const bf16x8*>(slot + vox * kZsCS + 8 * kg);
+                }
             }
         };
 #pragma unroll
@@ -241,15 +285,34 @@ k_conv_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const float
             __builtin_amdgcn_sched_barrier(0);
             const int r = t % (kZsAhead + 1);
 #pragma unroll
-            for (int s = 0; s < MT; ++s)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[r][nb], ar[r][s], acc[s][nb], 0, 0, 0);
+                for (int s = 0; s < MT; ++s)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[p][s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[r][nb], ar[r][p][s], acc[p][s][nb], 0, 0, 0);
+            // one part of the previous pair's epilogue after every third tap
+            if (t % 3 == 1 && t / 3 < NPART) store_part(t / 3);
             __builtin_amdgcn_sched_barrier(0);
         }
-        zs_store<NB, EPI, MT>(acc, bias, out, aux, x0, y, z, nx, ny, i, kg);
-        __syncthreads();   // every wavefront is done with slot (z - 1) before it takes plane z + 2
+#pragma unroll
+        for (int j = 9; j < NPART; ++j) store_part(j);
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int s = 0; s < MT; ++s)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    prev[p][s][nb] = acc[p][s][nb];
+                    pre[p][s][nb] = EPI == EPI_BACK_GELU && (p == 0 || z + 1 < z1)
+                                        ? zs_pre<NB>(aux, s, nb, x0, y, z + p, nx, ny, i, kg) : make_uint2(0, 0);
+                }
+        zp = z;
+        zp2 = z + 1 < z1;
+        __syncthreads();   // every wavefront is done with slots z - 1 and z before they take planes z + 3, z + 4
     }
+#pragma unroll
+    for (int j = 0; j < NPART; ++j) store_part(j);
 }
 
 // The convolution of a 1-channel input as a z-stream (the network's first
