@@ -31,6 +31,13 @@ int64_t ig_debug_live_allocations(void);
  * finished; later calls allocate them again. */
 void ig_debug_release_caches(void);
 
+/* Largest piece ig_surrogate_infer runs in one pass, in voxels (larger cubes
+ * are cut into slabs or tiles with a halo of the network's depth, which gives
+ * the same result bit for bit); voxels <= 0 restores the default, 2^28.
+ * Returns the previous limit.  Host only; process-wide: lets tests exercise
+ * the tiled path on small cubes. */
+int64_t ig_debug_set_infer_piece_limit(int64_t voxels);
+
 #ifdef __cplusplus
 }
 #endif

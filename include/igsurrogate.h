@@ -95,11 +95,13 @@ ig_status ig_surrogate_train_step(ig_surrogate* s, const float* const* d_x, cons
 
 /* Predict y from x.  tile > 0: cubes of tile^3 outputs, each computed with a
  * halo of `depth` voxels (the network's receptive radius), which gives the
- * same result as one piece; (tile + 2 depth)^3 x 32 must stay below 2^31
- * (32-bit activation offsets).  tile == 0: the whole cube in one piece when
- * voxels x 32 < 2^31, otherwise slabs of the whole x-y extent: the fewest
- * equal runs of planes whose slab with its halo planes satisfies that bound
- * (three slabs of 171 planes, 187 with halo, for a 512^3 cube). */
+ * same result as one piece; a piece with its halo must stay below the piece
+ * limit, 2^28 voxels (its two 32-channel bf16 activation buffers take 128
+ * bytes per voxel: 32 GiB at the limit).  tile == 0: the whole cube in one
+ * piece below that limit (a 512^3 cube: 17 GiB of buffers), otherwise slabs
+ * of the whole x-y extent: the fewest equal runs of planes whose slab with
+ * its halo planes stays below it.  The buffers are kept by the handle for the
+ * next call. */
 ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float* d_y, int64_t nx, int64_t ny, int64_t nz,
                              int32_t tile, void* hip_stream);
 
@@ -132,9 +134,9 @@ ig_status ig_surrogate_infer_checked(ig_surrogate* s, const ig_params* p, const 
  *   conv with input d_a bf16 [v][c_in] (1 or 32) and output gradient d_dz
  *   bf16 [v][c_out] (1 or 32); partial sums in a fixed order (deterministic).
  * All three allocate temporaries and wait for the stream, and return
- * IG_ERR_INVALID_ARG for cubes of 2^31 / 32 voxels or more (one kernel runs
- * over the whole cube with 32-bit element offsets; the network's own entry
- * points tile such cubes). */
+ * IG_ERR_INVALID_ARG for cubes of 2^31 / 32 voxels or more (these entry points
+ * are for checking the kernels on small cubes; each allocates a whole-cube
+ * 32-channel temporary per call). */
 ig_status ig_conv3d_forward(const void* d_in, int32_t c_in, const float* d_w, const float* d_b, int32_t c_out,
                             int32_t epilogue, void* d_aux, void* d_out, int64_t nx, int64_t ny, int64_t nz,
                             void* hip_stream);

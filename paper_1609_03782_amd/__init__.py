@@ -144,6 +144,7 @@ SIGNATURES = {
     "ig_debug_fail_alloc": (None, [ctypes.c_int64]),
     "ig_debug_live_allocations": (ctypes.c_int64, []),
     "ig_debug_release_caches": (None, []),
+    "ig_debug_set_infer_piece_limit": (ctypes.c_int64, [ctypes.c_int64]),
     "ig_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ig_last_error": (ctypes.c_char_p, []),
     "ig_version": (ctypes.c_char_p, []),

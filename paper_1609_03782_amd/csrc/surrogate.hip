@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "igdebug.h"
 #include "igsurrogate.h"
 #include "internal.h"
 #include "surrogate_kernels.h"
@@ -24,6 +25,17 @@ using namespace igs;
             return fail(e_ == hipErrorOutOfMemory ? IG_ERR_OUT_OF_MEMORY : IG_ERR_DEVICE, "%s: %s", \
                         #expr, hipGetErrorString(e_));                                             \
     } while (0)
+
+// Largest inference piece in voxels (2^28: 32 GiB of activation buffers);
+// larger cubes are cut into slabs or tiles.  Changed by a test hook.
+constexpr long kInferPieceVox = 1L << 28;
+long g_infer_piece_vox = kInferPieceVox;
+
+extern "C" int64_t ig_debug_set_infer_piece_limit(int64_t voxels) {
+    const long prev = g_infer_piece_vox;
+    g_infer_piece_vox = voxels > 0 ? voxels : kInferPieceVox;
+    return prev;
+}
 
 namespace {
 
@@ -253,6 +265,9 @@ struct ig_surrogate {
     long cap = 0;
     std::vector<Dev> act, pre;          // act[0] 1 channel, act[1..L-1] 32; pre[1..L-1]
     Dev y, dy, dzA, dzB, part, partb, parts, sub_x, sub_y, tmp;
+    // inference: the bf16 input and two 32-channel buffers used in turn
+    long icap = 0;
+    Dev iact0, iact[2];
 };
 
 namespace {
@@ -280,6 +295,41 @@ ig_status ensure_acts(ig_surrogate* s, long n) {
     HIP_TRY(s->dzA.ensure(n * 32 * 2));
     HIP_TRY(s->dzB.ensure(n * 32 * 2));
     s->cap = n;
+    return IG_OK;
+}
+
+ig_status to_bf16(const float* x, void* a, long n, hipStream_t st);
+
+ig_status ensure_infer(ig_surrogate* s, long n) {
+    if (n <= s->icap) return IG_OK;
+    HIP_TRY(s->iact0.ensure(n * 2));
+    HIP_TRY(s->iact[0].ensure(n * 32 * 2));
+    HIP_TRY(s->iact[1].ensure(n * 32 * 2));
+    s->icap = n;
+    return IG_OK;
+}
+
+// inference on one cube: x converted to bf16, then the layers through two
+// activation buffers in turn (no pre-activations kept); writes y (FP32)
+ig_status forward_infer(ig_surrogate* s, const float* x, float* y, long nx, long ny, long nz, hipStream_t st) {
+    const long n = nx * ny * nz;
+    ig_status rc = ensure_infer(s, n);
+    if (rc != IG_OK) return rc;
+    rc = to_bf16(x, s->iact0.p, n, st);
+    if (rc != IG_OK) return rc;
+    const float* P = s->params.as<float>();
+    const void* in = s->iact0.p;
+    for (int l = 0; l < s->L; ++l) {
+        const float* b = P + s->b_off[l];
+        if (l < s->L - 1) {
+            void* o = s->iact[l & 1].p;
+            HIP_TRY(launch_conv(s->cin[l], s->cout[l], EPI_GELU, in, s->pk_f[l].as<bf16x8>(), b, o, nullptr, nx, ny, nz,
+                                st));
+            in = o;
+        } else {
+            HIP_TRY(launch_conv(s->cin[l], s->cout[l], EPI_RESID, in, s->pk_f[l].as<bf16x8>(), b, y, x, nx, ny, nz, st));
+        }
+    }
     return IG_OK;
 }
 
@@ -494,14 +544,16 @@ extern "C" ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float
         if (cb != IG_OK) return cb;
     }
     const int H = s->L;   // receptive radius
-    // activations are addressed with 32-bit offsets: voxels x 32 channels < 2^31
-    constexpr long kMaxVox = (1LL << 31) / 32;
+    // one piece holds at most g_infer_piece_vox voxels (its two 32-channel
+    // bf16 activation buffers take 128 bytes per voxel)
+    const long kMaxVox = g_infer_piece_vox;
     auto fits = [&](long t) {
         const long d = t + 2 * H;
         return std::min(nx, d) * std::min(ny, d) * std::min(nz, d) < kMaxVox;
     };
     if (tile > 0 && !(tile >= nx && tile >= ny && tile >= nz) && !fits(tile))
-        return fail(IG_ERR_INVALID_ARG, "tile %d too large (tile + 2 depth)^3 x 32 must stay below 2^31", tile);
+        return fail(IG_ERR_INVALID_ARG, "tile %d too large: (tile + 2 depth)^3 must stay below %lld voxels", tile,
+                    (long long)kMaxVox);
     // piece extents per axis: the whole cube; cubes of `tile`; or (tile == 0
     // and a cube too large for one piece) slabs of the whole x-y extent and
     // the fewest equal runs of planes whose piece with its halo fits
@@ -517,15 +569,9 @@ extern "C" ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float
         if (tz == 0) return fail(IG_ERR_UNSUPPORTED, "one plane of %lld x %lld voxels is too large for a piece",
                                  (long long)nx, (long long)ny);
     }
-    if (tx >= nx && ty >= ny && tz >= nz) {
-        ig_status rc = ensure_acts(s, n);
-        if (rc != IG_OK) return rc;
-        rc = to_bf16(d_x, s->act[0].p, n, st);
-        if (rc != IG_OK) return rc;
-        return forward(s, d_x, d_y, nx, ny, nz, false, st);
-    }
+    if (tx >= nx && ty >= ny && tz >= nz) return forward_infer(s, d_x, d_y, nx, ny, nz, st);
     const long pmax = std::min(nx, tx + 2 * H) * std::min(ny, ty + 2 * H) * std::min(nz, tz + 2 * H);
-    ig_status rc = ensure_acts(s, pmax);
+    ig_status rc = ensure_infer(s, pmax);
     if (rc != IG_OK) return rc;
     HIP_TRY(s->sub_x.ensure(pmax * 4));
     HIP_TRY(s->sub_y.ensure(pmax * 4));
@@ -540,9 +586,7 @@ extern "C" ig_status ig_surrogate_infer(ig_surrogate* s, const float* d_x, float
                 hipLaunchKernelGGL(k_gather, dim3((m + 255) / 256), dim3(256), 0, st, d_x, nx, ny, (int)bx, (int)by,
                                    (int)bz, (int)dx, (int)dy, (int)dz, s->sub_x.as<float>());
                 HIP_TRY(hipGetLastError());
-                rc = to_bf16(s->sub_x.as<float>(), s->act[0].p, m, st);
-                if (rc != IG_OK) return rc;
-                rc = forward(s, s->sub_x.as<float>(), s->sub_y.as<float>(), dx, dy, dz, false, st);
+                rc = forward_infer(s, s->sub_x.as<float>(), s->sub_y.as<float>(), dx, dy, dz, st);
                 if (rc != IG_OK) return rc;
                 const long e = ex * ey * ez;
                 hipLaunchKernelGGL(k_scatter, dim3((e + 255) / 256), dim3(256), 0, st, s->sub_y.as<float>(), (int)dx,

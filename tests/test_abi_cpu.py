@@ -259,3 +259,14 @@ def test_single_layer_conv_rejects_cubes_past_32bit_offsets():
     assert b"too large" in ig.lib().ig_last_error()
     assert L.ig_conv3d_input_grad(fake, 32, fake, 32, None, fake, 1 << 10, 1 << 8, n >> 18, None) == ig.IG_ERR_INVALID_ARG
     assert L.ig_conv3d_weight_grad(fake, 32, fake, 32, fake, fake, 1 << 10, 1 << 8, n >> 18, None) == ig.IG_ERR_INVALID_ARG
+
+
+def test_infer_piece_limit_hook():
+    """The test hook that lowers the surrogate's inference piece limit returns
+    the previous limit; 0 restores the default of 2^28 voxels."""
+    L = ig.lib()
+    default = 1 << 28
+    assert L.ig_debug_set_infer_piece_limit(12345) == default
+    assert L.ig_debug_set_infer_piece_limit(0) == 12345
+    assert L.ig_debug_set_infer_piece_limit(-5) == default
+    assert L.ig_debug_set_infer_piece_limit(0) == default

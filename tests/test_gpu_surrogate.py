@@ -202,10 +202,12 @@ def test_network_forward_and_tiling(dev):
 
 
 def test_large_cube_auto_tiles(dev):
-    """A cube whose activations exceed 32-bit offsets (voxels x 32 >= 2^31)
-    is tiled by the library when tile == 0; tiling is exact, so the result
-    equals an explicit tiling bit for bit."""
+    """A cube above the library's piece limit is cut into slabs when tile == 0;
+    tiling is exact, so the result equals an explicit tiling and the whole-cube
+    pass bit for bit.  The limit (2^28 voxels by default) is lowered through
+    the test hook so that a small cube takes the tiled path."""
     import torch
+    import paper_1609_03782_amd as ig
     from paper_1609_03782_amd import surrogate as sg
     net = sg.Surrogate(depth=8, seed=5)
     # random weights in every layer (the initial last layer is zero, which
@@ -215,20 +217,27 @@ def test_large_cube_auto_tiles(dev):
     Ws = [(rng.standard_normal(W.shape) * np.sqrt(1.0 / (27 * W.shape[1]))).astype(np.float32) for W in Ws]
     bs = [(0.1 * rng.standard_normal(b.shape)).astype(np.float32) for b in bs]
     net.set_weights(sg.join_params(Ws, bs))
-    x = torch.randn(257, 512, 512, device=dev)       # 6.74e7 voxels: 32 x voxels > 2^31
-    y0 = net.infer(x)                                # library-picked slabs (2 x 129 planes)
-    y1 = net.infer(x, tile=200)                      # cubes of 200^3
-    torch.cuda.synchronize()
-    assert torch.equal(y0, y1)
-    assert bool(torch.isfinite(y0).all())
-    assert float((y0 - x).abs().max()) > 1e-2       # the network changes its input
+    x = torch.randn(40, 256, 512, device=dev)        # 5.2e6 voxels
+    yw = net.infer(x)                                # one piece under the default limit
+    L = ig.lib()
+    L.ig_debug_set_infer_piece_limit(1 << 22)        # 4.2e6 voxels: slabs of 14 planes + halo
+    try:
+        y0 = net.infer(x)                            # library-picked slabs
+        y1 = net.infer(x, tile=200)                  # cubes of 200^3
+        torch.cuda.synchronize()
+        with pytest.raises(Exception):
+            net.infer(x, tile=500)                   # 512 x 256 x 40 voxels with the halo >= the limit
+    finally:
+        L.ig_debug_set_infer_piece_limit(0)
+    assert torch.equal(y0, yw)
+    assert torch.equal(y1, yw)
+    assert bool(torch.isfinite(yw).all())
+    assert float((yw - x).abs().max()) > 1e-2       # the network changes its input
     # a piece of the interior equals the network on that piece with its halo
-    sub = x[100:140, 200:260, 300:380].contiguous()
+    sub = x[10:34, 100:160, 300:380].contiguous()
     ys = net.infer(sub)
     torch.cuda.synchronize()
-    assert torch.equal(ys[8:-8, 8:-8, 8:-8], y0[108:132, 208:252, 308:372])
-    with pytest.raises(Exception):
-        net.infer(x, tile=500)                       # (500 + 16)^2 x 257 x 32 >= 2^31
+    assert torch.equal(ys[8:-8, 8:-8, 8:-8], yw[18:26, 108:152, 308:372])
 
 
 def test_training_gradient_matches_oracle(dev):
