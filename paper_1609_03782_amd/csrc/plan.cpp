@@ -293,7 +293,10 @@ ig_schedule igk_auto_schedule(const ig_params* p) {
     // longest share, in plane steps times the measured cost of a 16-wave step
     // (2.96 us against 2.13 us for a 12-wave step on the 512^3 cube, T = 2,
     // 8 voxels per lane), is shorter: 512^3 runs 93 such steps against 134.
-    if (s.t_block == 2 && s.vec == 8 && s.rows == 1 && p->nx % 8 == 0 && p->nx <= 512 &&
+    // FP32 storage only: with 16-bit storage the 16-wave grouped pass measured
+    // slower than 12 waves (bf16 840 against 871, fp16 851 against 873
+    // Gvoxel-iter/s on the 512^3 cube).
+    if (p->dtype == IG_F32 && s.t_block == 2 && s.vec == 8 && s.rows == 1 && p->nx % 8 == 0 && p->nx <= 512 &&
         (long)16 * p->nx * (long)dtype_size(p->dtype) < (1L << 30)) {
         auto longest = [&](int W, bool* grouped) -> double {
             ig_schedule t = s;
