@@ -67,9 +67,20 @@ __device__ __forceinline__ float erf_as(float x, float* e2) {
     return x < 0.0f ? -y : y;
 }
 // gelu(z) = z/2 (1 + erf(z/sqrt2)); gelu'(z) = (1 + erf(z/sqrt2))/2 + z e^{-z^2/2}/sqrt(2 pi)
+// GELU through the complementary function the same formula gives directly,
+// erfc(x) = (a1 t + ... + a5 t^5) e^{-x^2} for x >= 0: with c = erfc(|z|/sqrt2),
+// gelu(z) = max(z, 0) - |z|/2 c on both sides of 0 (12 VALU operations, a
+// reciprocal and an exp2).
 __device__ __forceinline__ float gelu_fast(float z) {
-    float e;
-    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f, &e));
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
+    const float ex = __builtin_amdgcn_exp2f((z * -0.72134752044448170f) * z);   // e^{-z^2/2}
+    float pl = __builtin_fmaf(1.061405429f, t, -1.453152027f);
+    pl = __builtin_fmaf(pl, t, 1.421413741f);
+    pl = __builtin_fmaf(pl, t, -0.284496736f);
+    pl = __builtin_fmaf(pl, t, 0.254829592f);
+    const float c = (pl * t) * ex;
+    return __builtin_fmaf(-0.5f * az, c, fmaxf(z, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad_fast(float z) {
     float e;
