@@ -24,6 +24,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace igs {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -340,7 +342,7 @@ k_conv1_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const floa
            void* __restrict__ out, const void* __restrict__ aux, int nx, int ny, int nz, int ntx, int nty, int zch) {
     constexpr int XW = 16 * MT, LX = XW + 2, LY = kZsRows + 2, NPL = LX * LY;
     static_assert(NPL <= 64 * kZsRows, "one staged voxel per thread");
-    __shared__ u16 ring[3 * NPL];
+    __shared__ u16 ring[3 * NPL + 16 * MT];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, kg = lane >> 4;
     const int bt = blockIdx.x;
@@ -352,7 +354,9 @@ k_conv1_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const floa
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) wf[nb] = wp[nb * 64 + lane];
 
-    // thread q stages voxel q of every plane (zero outside the cube)
+    // thread q stages voxel q of every plane (zero outside the cube); plane p
+    // sits in slot (p - z0 + 1) mod 3, and zeros after the three slots stand
+    // for the padding taps 27..31
     const int q = threadIdx.x;
     const int qx = x0 + q % LX - 1, qy = y0 + q / LX - 1;
     const bool qin = q < NPL && qx >= 0 && qx < nx && qy >= 0 && qy < ny;
@@ -360,14 +364,27 @@ k_conv1_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const floa
     const long plane = (long)nx * ny;
     auto fetch = [&](int z) -> u16 { return (qin && z >= 0 && z < nz) ? in[z * plane + qoff] : (u16)0; };
     auto put = [&](int z, u16 v) {
-        if (q < NPL) ring[((z + 3) % 3) * NPL + q] = v;
+        if (q < NPL) ring[((z - z0 + 1) % 3) * NPL + q] = v;
     };
+    if (threadIdx.x < 16 * MT) ring[3 * NPL + threadIdx.x] = 0;
+    // this lane's 8 taps t = 8 kg + e of voxel i, for each of the three ring
+    // rotations r = (z - z0) mod 3: the LDS index of the tap's input voxel
+    int gidx[3][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int t = 8 * kg + e;
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        const int off = (w + dy) * LX + i + dx;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) gidx[r][e] = t < 27 ? ((r + dz) % 3) * NPL + off : 3 * NPL;
+    }
     put(z0 - 1, fetch(z0 - 1));
     put(z0, fetch(z0));
     u16 nxt = fetch(z0 + 1);
 
     const int y = y0 + w;
-    for (int z = z0; z < z1; ++z) {
+    // one plane; R = (z - z0) mod 3 known at compile time
+    auto plane_step = [&](int z, auto R) {
         put(z + 1, nxt);
         __syncthreads();
         if (z + 1 < z1) nxt = fetch(z + 2);
@@ -378,13 +395,7 @@ k_conv1_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const floa
             bf16x8 a;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int t = 8 * kg + e;
-                u16 h = 0;
-                if (t < 27) {
-                    const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-                    h = ring[((z + 2 + dz) % 3) * NPL + (w + dy) * LX + 16 * s + i + dx];
-                }
-                a[e] = __builtin_bit_cast(__bf16, h);
+                a[e] = __builtin_bit_cast(__bf16, ring[gidx[decltype(R)::value][e] + 16 * s]);
             }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
@@ -392,6 +403,11 @@ k_conv1_zs(const u16* __restrict__ in, const bf16x8* __restrict__ wp, const floa
         }
         zs_store<NB, EPI, MT>(acc, bias, out, aux, x0, y, z, nx, ny, i, kg);
         __syncthreads();   // every wavefront is done with slot (z - 1) before it takes plane z + 2
+    };
+    for (int z = z0; z < z1; z += 3) {
+        plane_step(z, std::integral_constant<int, 0>{});
+        if (z + 1 < z1) plane_step(z + 1, std::integral_constant<int, 1>{});
+        if (z + 2 < z1) plane_step(z + 2, std::integral_constant<int, 2>{});
     }
 }
 
