@@ -9,7 +9,7 @@
  *     y = x + z_depth  (one output channel, residual to the input),
  * with zero padding outside the cube and gelu(z) = z/2 (1 + erf(z/sqrt 2)).
  * Weights and activations are bf16, accumulation FP32 on the matrix cores,
- * master weights FP32 with Adam.  The filter remains the judge: a residual
+ * master weights FP32 with Adam.  The filter keeps the last word: a residual
  * check runs two plain filter steps on the prediction and falls back to the
  * full filter when the predicted error is too large.
  *
