@@ -307,3 +307,25 @@ def test_grouped_workgroups_bitwise(dev, oracle_lib, cond, shape, sched):
     assert torch.equal(y, y0), (shape, sched, grouped is not None)
     ref, rho = oracle_lib.run(cube, cond, K=2.0, tau=1 / 16, n_iter=n)
     assert _err(y.cpu().numpy(), ref) <= TOL * rho
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_grouped_workgroups_16bit_bitwise(dev, dtype):
+    """The grouped 16-wave plan with 16-bit storage (not the default there,
+    but reachable through an explicit schedule) gives bitwise the naive
+    schedule's result in the same storage type."""
+    import torch
+    import paper_1609_03782_amd as ig
+    shape, sched = (64, 512, 512), dict(kind="blocked", t_block=2, waves=16, vec=8)
+    assert ig.schedule_plan_groups(shape, sched, 2) is not None
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+    cube = igsynth.random_cube(shape, seed=77, scale=2.0)
+    x = torch.from_numpy(cube).to(dev).to(tdt)
+    f0 = ig.Filter(shape, K=2.0, tau=1 / 16, n_iter=6, dtype=dtype)
+    f0.set_schedule("naive")
+    y0 = f0.run(x)
+    f = ig.Filter(shape, K=2.0, tau=1 / 16, n_iter=6, dtype=dtype)
+    f.set_schedule(**sched)
+    y = f.run(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y0)
