@@ -37,14 +37,29 @@ def test_pieces_cover_every_output_once(shape, sched):
             continue
         g, pcs = ig.schedule_plan(shape, dict(kind="blocked", **sched), T)
         assert g["pieces"] == len(pcs) > 0
-        cover = np.zeros(shape, np.int32)
+        # the x and y tiles partition the columns and rows ...
+        for part, n in (([tile_cols(g, nx, k) for k in range(g["ntx"])], nx),
+                        ([tile_rows(g, ny, k) for k in range(g["nty"])], ny)):
+            assert part[0][0] == 0 and part[-1][1] == n and all(a[1] == b[0] for a, b in zip(part, part[1:]))
+        # ... and each tile's pieces partition its planes
+        zs = {}
         for tx, ty, z0, z1 in pcs:
             assert 0 <= tx < g["ntx"] and 0 <= ty < g["nty"] and 0 <= z0 < z1 <= nz
             (x0, x1), (y0, y1) = tile_cols(g, nx, tx), tile_rows(g, ny, ty)
             assert 0 <= x0 < x1 <= nx and x1 - x0 <= g["ox"] and x0 % g["V"] == 0
             assert 0 <= y0 < y1 <= ny and y1 - y0 <= g["oy"]
-            cover[z0:z1, y0:y1, x0:x1] += 1
-        assert cover.min() == 1 and cover.max() == 1, (shape, sched, T)
+            zs.setdefault((int(tx), int(ty)), []).append((int(z0), int(z1)))
+        assert len(zs) == g["ntx"] * g["nty"], (shape, sched, T)
+        for iv in zs.values():
+            iv.sort()
+            assert iv[0][0] == 0 and iv[-1][1] == nz and all(a[1] == b[0] for a, b in zip(iv, iv[1:])), \
+                (shape, sched, T)
+        if nz * ny * nx <= 1 << 22:   # the same by counting every voxel
+            cover = np.zeros(shape, np.int32)
+            for tx, ty, z0, z1 in pcs:
+                (x0, x1), (y0, y1) = tile_cols(g, nx, tx), tile_rows(g, ny, ty)
+                cover[z0:z1, y0:y1, x0:x1] += 1
+            assert cover.min() == 1 and cover.max() == 1, (shape, sched, T)
         if g["ntx"] == 1:
             assert 64 // g["rows"] * g["V"] >= nx
         if g["nty"] == 1:
