@@ -110,6 +110,9 @@ ig_status static_plan(void* self, const ig_schedule& sched, int T, const PassPla
 ig_schedule static_schedule(const ig_params& p, int ncu) {
     ig_schedule s = igk_auto_schedule(&p);
     if (s.kind != IG_SCHED_BLOCKED) return s;
+    // the 16-wave layout pays only through a grouped plan (equal shares of
+    // the tiles' planes), which the regular grid of the static tables is not
+    if (s.waves == 16 && s.t_block == 2 && s.vec == 8 && s.rows == 1) s.waves = 12;
     s.rounds = 0;
     s.zchunk = (int)p.nz;
     PassPlan pp;
